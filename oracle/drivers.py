@@ -1,0 +1,228 @@
+"""The paper's parallel algorithms over oracle chains (plain Python control flow).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Positions are 1-based: position l of a chain is its l-th recorded state.  Each
+property (state set) runs its own state machine on chains that depend only on
+(network, seed, chain id), so a property's result does not depend on which other
+properties share the chains; the oracle therefore solves each property alone.
+
+Readings of the paper (where it is silent or garbled) that this file follows:
+  * Alg. 2: the scalar monitored is the property's 0-1 indicator; s_i uses the
+    denominator psi-1; the chains first reach 2*psi0 positions, and each check
+    uses positions psi+1..2psi; "close to 1" means R < psrf_max; a check with
+    W == 0 counts as not converged; the returned psi is the last one checked.
+  * Alg. 3: the first pass estimates alpha, beta from the existing second halves
+    (positions psi+1..2psi) without extending; the extension is
+    ceil((N - omega*n)/omega) and the inner loop ends when it is <= 0; the
+    estimate of alpha, beta uses all pairs of consecutive positions inside each
+    chain's window (summed over chains); a re-run happens when M > psi and
+    discards M - psi more positions from each chain's front (psi := M); if the
+    window becomes empty it is refilled to the Gelman-Rubin psi; the estimate is
+    the fraction of ones in the final window.  If alpha or beta is undefined the
+    window is doubled.
+  * Alg. 5 (Skart-P): eta0 = ceil(1280/omega)*omega initial observations from
+    position psi+1; batch size 16 if the sample skewness exceeds 4 in absolute
+    value, else 1; p batches of kappa positions, p/omega consecutive batches per
+    chain (chain-major order); randomness test = von Neumann ratio over
+    within-chain adjacent batch means at level 0.20, on failure kappa :=
+    ceil(sqrt(2) kappa), p := ceil(0.9 p) rounded up to a multiple of omega (at
+    most 10 times); CI = skewness- (Willink) and lag-1 autoregression-adjusted
+    t interval on the batch means; if its half-width H exceeds H* the batch size
+    grows to ceil(kappa (H/H*)^2).
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List
+
+import numpy as np
+
+from . import Chains, Net
+from . import stats
+
+OK = 0
+NOT_CONVERGED = 5
+
+
+def _cdiv(a: int, b: int) -> int:
+    return -((-a) // b)
+
+
+class NotConverged(Exception):
+    pass
+
+
+def generate_converged_chains(ch: Chains, q: int, psi0: int, psrf_max: float, cap: int):
+    """Alg. 2 for property q; returns (psi, R)."""
+    psi = psi0
+    while True:
+        if 2 * psi > cap:
+            raise NotConverged("psrf")
+        ch.extend_to(2 * psi)
+        R = stats.psrf(ch.bits[q][:, psi: 2 * psi])
+        if R < psrf_max:
+            return psi, R
+        psi = 2 * psi
+
+
+def estimate_probability_in_parallel(ch: Chains, q: int, psi0: int, psrf_max: float, eps: float,
+                                     r: float, s: float, cap: int) -> Dict:
+    """Alg. 3 for property q on chains ch."""
+    omega = ch.omega
+    z = stats.z_of_confidence(s)
+    res = dict(status=OK, psi_gr=0, rhat=math.nan, psi=0, n=0, N=0, M=0, prob=math.nan,
+               ci_lo=math.nan, ci_hi=math.nan, kappa=0, batches=0, chain_len=0)
+    try:
+        psi, R = generate_converged_chains(ch, q, psi0, psrf_max, cap)
+    except NotConverged:
+        res["status"] = NOT_CONVERGED
+        res["chain_len"] = ch.length
+        return res
+    res["psi_gr"], res["rhat"] = psi, R
+    psi_gr = psi
+    n = psi
+    N = 0
+    while True:
+        while True:
+            if psi + n > cap:
+                res.update(status=NOT_CONVERGED, psi=psi, n=n, chain_len=ch.length)
+                return res
+            ch.extend_to(psi + n)
+            win = ch.bits[q][:, psi: psi + n]
+            ab = stats.alpha_beta(stats.transition_counts(win))
+            if ab is None:
+                extend_by = n
+            else:
+                a, b = ab
+                N = int(math.ceil(stats.sample_size_N(a, b, z, r)))
+                extend_by = _cdiv(N - omega * n, omega)
+                if extend_by <= 0:
+                    break
+            n += extend_by
+        M = stats.burn_in_M(a, b, eps)
+        if M > psi:
+            n -= M - psi
+            psi = M
+            if n <= 0:
+                n = psi_gr
+            continue
+        break
+    win = ch.bits[q][:, psi: psi + n]
+    res.update(psi=psi, n=n, N=N, M=M, prob=float(np.sum(win)) / (omega * n),
+               chain_len=psi + n)
+    return res
+
+
+def _batch_means(ch: Chains, q: int, base: int, kappa: int, p: int) -> np.ndarray:
+    m = p // ch.omega
+    ch.extend_to(base + kappa * m)
+    x = ch.bits[q][:, base: base + kappa * m].astype(np.float64)
+    return x.reshape(ch.omega, m, kappa).sum(axis=2) / kappa       # [omega][m]
+
+
+def von_neumann_passes(Y: np.ndarray, level: float = 0.20) -> bool:
+    """Randomness test over within-chain adjacent batch means (reading of Alg. 5)."""
+    omega, m = Y.shape
+    if m < 2:
+        return True
+    ybar = float(np.sum(Y)) / Y.size
+    den = float(np.sum((Y - ybar) ** 2))
+    if den == 0.0:
+        return True
+    num = float(np.sum((Y[:, 1:] - Y[:, :-1]) ** 2))
+    npairs = omega * (m - 1)
+    C = 1.0 - (num / npairs) / (2.0 * den / (Y.size - 1))
+    return C <= stats.normal_quantile(1.0 - level) * math.sqrt(1.0 / npairs)
+
+
+def adjusted_ci(Y: np.ndarray, alpha: float):
+    """Skewness- and autoregression-adjusted CI on batch means (reading of Alg. 5)."""
+    omega, m = Y.shape
+    pp = Y.size
+    mu = float(np.sum(Y)) / pp
+    dev = Y - mu
+    ss = float(np.sum(dev ** 2))
+    if ss == 0.0:
+        return mu, mu, mu
+    S2 = ss / (pp - 1)
+    phi = 0.0
+    if m >= 2:
+        phi = (float(np.sum(dev[:, 1:] * dev[:, :-1])) / (omega * (m - 1))) / (ss / pp)
+    A = (1.0 + phi) / (1.0 - phi) if phi > 0.0 else 1.0
+    skew = (float(np.sum(dev ** 3)) / pp) / (ss / pp) ** 1.5
+    beta = skew / (6.0 * math.sqrt(pp))
+    t_hi = stats.t_quantile(1.0 - alpha / 2.0, pp - 1)
+    se = math.sqrt(A * S2 / pp)
+    lo = mu - stats.willink_G(t_hi, beta) * se
+    hi = mu - stats.willink_G(-t_hi, beta) * se
+    return mu, lo, hi
+
+
+def estimate_ci_in_parallel(ch: Chains, q: int, psi0: int, psrf_max: float, H_star: float,
+                            s: float, cap: int) -> Dict:
+    """Alg. 5 (Skart-P) for property q on chains ch."""
+    omega = ch.omega
+    alpha = 1.0 - s
+    res = dict(status=OK, psi_gr=0, rhat=math.nan, psi=0, n=0, N=0, M=0, prob=math.nan,
+               ci_lo=math.nan, ci_hi=math.nan, kappa=0, batches=0, chain_len=0)
+    try:
+        psi, R = generate_converged_chains(ch, q, psi0, psrf_max, cap)
+    except NotConverged:
+        res["status"] = NOT_CONVERGED
+        res["chain_len"] = ch.length
+        return res
+    res.update(psi_gr=psi, rhat=R, psi=psi)
+    base = psi
+    eta0 = _cdiv(1280, omega) * omega
+    m0 = eta0 // omega
+    ch.extend_to(base + m0)
+    B = stats.skewness(ch.bits[q][:, base: base + m0].reshape(-1))
+    kappa = 16 if abs(B) > 4.0 else 1
+    p = eta0
+    Y = _batch_means(ch, q, base, kappa, p)
+    tries = 0
+    while not von_neumann_passes(Y) and tries < 10:
+        kappa = int(math.ceil(math.sqrt(2.0) * kappa))
+        p = max(omega, _cdiv(int(math.ceil(0.9 * p)), omega) * omega)
+        tries += 1
+        if base + kappa * (p // omega) > cap:
+            res.update(status=NOT_CONVERGED, chain_len=ch.length)
+            return res
+        Y = _batch_means(ch, q, base, kappa, p)
+    while True:
+        if base + kappa * (p // omega) > cap:
+            res.update(status=NOT_CONVERGED, chain_len=ch.length, kappa=kappa, batches=p)
+            return res
+        Y = _batch_means(ch, q, base, kappa, p)
+        mu, lo, hi = adjusted_ci(Y, alpha)
+        H = max(mu - lo, hi - mu)
+        if H > H_star:
+            ratio = H / H_star
+            kappa = int(math.ceil(kappa * (ratio * ratio)))
+            continue
+        break
+    n = kappa * (p // omega)
+    res.update(prob=mu, ci_lo=lo, ci_hi=hi, kappa=kappa, batches=p, n=n, chain_len=base + n)
+    return res
+
+
+DEFAULTS = dict(psi0=256, eps=1e-10, cap=1 << 26)
+
+
+def solve(text: str, omega: int, seed: int, patterns, r: float, s: float, psrf_max: float,
+          method: str = "two_state", psi0: int = 256, eps: float = 1e-10, cap: int = 1 << 26,
+          threads: int | None = None) -> List[Dict]:
+    """Solve every property alone (fresh chains, same seed); the per-property
+    results equal those of a shared-chain run."""
+    net = Net(text)
+    out = []
+    for q in range(len(patterns)):
+        ch = Chains(net, omega, seed, [patterns[q]], threads=threads)
+        if method == "two_state":
+            out.append(estimate_probability_in_parallel(ch, 0, psi0, psrf_max, eps, r, s, cap))
+        elif method == "skart":
+            out.append(estimate_ci_in_parallel(ch, 0, psi0, psrf_max, r, s, cap))
+        else:
+            raise ValueError(method)
+    return out

@@ -1,0 +1,160 @@
+"""Pins for the oracle's statistics (Alg. 1 line-8 formulas, Alg. 2, Skart-P pieces).
+
+* Gelman-Rubin: a worked-by-hand example (golden file) and the identical-chains
+  case R = sqrt(1 - 1/psi) (B = 0).
+* N: the binomial special case alpha + beta = 1 (N = q(1-q) z^2 / r^2, 9604 at
+  q = 1/2, r = 0.01, s = 0.95) and the asymptotic variance of the sample mean of
+  a simulated two-state chain.
+* M: the 2x2 transition matrix raised to the M-th power is within eps of its
+  limit, and not yet at M-1.
+* Quantiles against scipy; the skewness adjustment inverts Willink's cubic.
+* Alg. 3 control flow on a scripted 0-1 process worked by hand (golden file).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import stats as sst
+
+from oracle import drivers, stats
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    out = {}
+    for line in open(os.path.join(GOLD, name)):
+        if line.strip() and not line.startswith("#"):
+            k, *v = line.split()
+            out[k] = v
+    return out
+
+
+def test_gr_hand_example():
+    g = _golden("gr_hand_example.txt")
+    x = np.array([[int(ch) for ch in c] for c in g["chains"]])
+    assert abs(stats.psrf(x) ** 2 - float(g["rhat2"][0])) < 1e-12
+
+
+@pytest.mark.parametrize("psi", [4, 16, 100])
+def test_gr_identical_chains(psi):
+    rng = np.random.default_rng(psi)
+    row = rng.integers(0, 2, psi)
+    row[0], row[1] = 0, 1
+    x = np.tile(row, (5, 1))
+    assert abs(stats.psrf(x) - math.sqrt(1 - 1 / psi)) < 1e-12
+
+
+def test_gr_constant_window_not_converged():
+    assert stats.psrf(np.ones((3, 8))) == math.inf
+
+
+def test_N_binomial_case():
+    z = stats.z_of_confidence(0.95)
+    assert math.ceil(stats.sample_size_N(0.5, 0.5, z, 0.01)) == 9604
+    for a in (0.1, 0.3, 0.77):
+        b = 1 - a
+        q = a / (a + b)
+        assert abs(stats.sample_size_N(a, b, z, 0.02) - q * (1 - q) * z * z / 0.02 ** 2) < 1e-6
+    # worked sequence 0 0 1 1 0: every pair type once -> alpha = beta = 1/2
+    cnt = stats.transition_counts(np.array([[0, 0, 1, 1, 0]]))
+    assert cnt == (1, 1, 1, 1)
+    assert stats.alpha_beta(cnt) == (0.5, 0.5)
+    assert stats.burn_in_M(0.5, 0.5, 1e-10) == 0
+
+
+def test_N_matches_two_state_variance():
+    # N z^-2 r^2 is the asymptotic variance of the sample mean times the length.
+    rng = np.random.default_rng(5)
+    a, b, L, reps = 0.05, 0.15, 4000, 1500
+    x = np.zeros((reps, L), np.int8)
+    x[:, 0] = rng.random(reps) < a / (a + b)
+    u = rng.random((reps, L))
+    for t in range(1, L):
+        prev = x[:, t - 1]
+        x[:, t] = np.where(prev == 1, u[:, t] >= b, u[:, t] < a)
+    var_emp = x.mean(axis=1).var(ddof=1) * L
+    var_formula = stats.sample_size_N(a, b, 1.0, 1.0)
+    assert abs(var_emp / var_formula - 1) < 0.12
+
+
+@pytest.mark.parametrize("a,b", [(0.05, 0.15), (0.3, 0.01), (0.9, 0.8), (0.002, 0.004)])
+def test_M_reaches_eps(a, b):
+    eps = 1e-10
+    M = stats.burn_in_M(a, b, eps)
+    P = np.array([[1 - a, a], [b, 1 - b]])
+    pi = np.array([b, a]) / (a + b)
+
+    def dev(m):
+        Pm = np.linalg.matrix_power(P, m)
+        return np.abs(Pm - pi[None, :]).max()
+    assert dev(M) <= eps * (1 + 1e-6)
+    assert dev(M - 1) > eps * (1 - 1e-6)
+
+
+def test_quantiles_vs_scipy():
+    for s in (0.5, 0.9, 0.95, 0.99, 0.999999):
+        z = stats.z_of_confidence(s)
+        assert abs(z - sst.norm.ppf(0.5 * (1 + s))) <= 1e-15 * max(1, abs(z)) * 4
+    for p in (1e-300, 1e-20, 1e-5, 0.02, 0.3, 0.7, 0.98):
+        assert abs(stats.normal_quantile(p) - sst.norm.ppf(p)) <= 1e-14 * abs(sst.norm.ppf(p))
+    assert stats.z_of_confidence(0.95) == pytest.approx(1.959963984540054, rel=1e-15)
+    for nu in (100, 500, 1279, 10000):
+        for p in (0.975, 0.995, 0.025, 0.9):
+            err = 1e-9 if nu < 1000 else 1e-12
+            assert abs(stats.t_quantile(p, nu) - sst.t.ppf(p, nu)) < err
+
+
+def test_willink_inverts_cubic():
+    for beta in (1e-4, 0.01, 0.05, -0.03):
+        for zeta in (-2.5, -1.96, 0.3, 1.96, 2.8):
+            g = stats.willink_G(zeta, beta)
+            b2 = 2 * beta
+            h = g + b2 * g * g + b2 * b2 * g ** 3 / 3          # Willink's transform with skew 2 beta
+            assert abs(h - (zeta - beta)) < 1e-12
+    assert stats.willink_G(1.7, 0.0) == 1.7
+
+
+def test_ci_reduces_to_t_interval():
+    # one batch per chain and no skewness adjustment: the textbook t interval
+    rng = np.random.default_rng(2)
+    Y = rng.normal(0.3, 0.05, size=(2000, 1))
+    mu, lo, hi = drivers.adjusted_ci(Y, 0.05)
+    se = Y.std(ddof=1) / math.sqrt(Y.size)
+    tlo, thi = sst.t.interval(0.95, Y.size - 1, loc=Y.mean(), scale=se)
+    skew = sst.skew(Y.ravel())
+    # the skewness shift is about beta (1 + 2 t^2) se with beta = skew/(6 sqrt(p)); bound it
+    slack = abs(skew) / (6 * math.sqrt(Y.size)) * 12.0 * se + 1e-12
+    assert abs(lo - tlo) < slack and abs(hi - thi) < slack
+    # symmetric data: exact match
+    Ys = np.concatenate([Y, 2 * Y.mean() - Y])
+    mu, lo, hi = drivers.adjusted_ci(Ys, 0.05)
+    se = Ys.std(ddof=1) / math.sqrt(Ys.size)
+    tlo, thi = sst.t.interval(0.95, Ys.size - 1, loc=Ys.mean(), scale=se)
+    assert abs(lo - tlo) < 1e-11 and abs(hi - thi) < 1e-11
+
+
+class ScriptedChains:
+    """Stand-in for oracle chains: position l holds ((l-1) div 2) mod 2."""
+
+    def __init__(self, omega):
+        self.omega = omega
+        self.length = 0
+
+    def extend_to(self, L):
+        self.length = max(self.length, L)
+
+    @property
+    def bits(self):
+        l = np.arange(1, self.length + 1)
+        row = (((l - 1) // 2) % 2).astype(np.uint8)
+        return np.tile(row, (1, self.omega, 1))
+
+
+def test_alg3_hand_trace():
+    g = _golden("alg3_hand_trace.txt")
+    res = drivers.estimate_probability_in_parallel(ScriptedChains(2), 0, 4, 1.1, 1e-10, 0.01, 0.95, 1 << 20)
+    for key in ("psi_gr", "psi", "n", "N", "M", "chain_len"):
+        assert res[key] == int(g[key][0]), key
+    assert res["prob"] == float(g["prob"][0])
