@@ -1,0 +1,232 @@
+/*
+ * pbnssa — steady-state analysis of probabilistic Boolean networks on MI355X.
+ *
+ * C ABI of the GPU library (libpbnssa.so).  Plain C types only: host pointers,
+ * device pointers passed as void*, sizes.  No exceptions cross this boundary.
+ *
+ * Model (Mizera, Pang, Yuan, "Parallel approximate steady-state analysis of
+ * large probabilistic Boolean networks", Sec. 2.2): n binary nodes; node i has
+ * l(i) predictor functions, one chosen per step with probabilities c_j^(i)
+ * (instantaneously random PBN); a perturbation vector gamma(t) with
+ * gamma_i ~ Bernoulli(p); if gamma(t) = 0 the state is updated synchronously by
+ * the selected functions, otherwise s(t+1) = s(t) XOR gamma(t).
+ *
+ * Method (Sec. 3-4): omega chains run in parallel; Gelman & Rubin's potential
+ * scale reduction factor (Alg. 2) certifies convergence; then either the
+ * two-state Markov chain approach (Alg. 3, sample size N and burn-in M of
+ * Alg. 1) or a parallel Skart batch-means procedure (Alg. 5) decides how long
+ * the chains must run to estimate the steady-state probability of a set of
+ * states within precision r at confidence s.
+ *
+ * Random stream (the paper leaves it open; fixed here so results are
+ * reproducible and independent of launch shapes): Philox4x32-10 with key =
+ * (seed low 32, seed high 32); for transition t (0-based) of chain c, the
+ * perturbation and selection uniforms of node i are 32-bit values
+ * (byte << 24) | low24 where byte is byte (i mod 16) of Philox((t, c, i/16, tag))
+ * and low24 the low 24 bits of word (i mod 4) of Philox((t, c, i/4, tag+1)),
+ * tag 0 (perturbation) or 2 (selection).  gamma_i = (u < floor(p 2^32)); the
+ * selected function is the first j with u < T_j, T_j = min(2^32-1,
+ * floor(2^32 (c_1+..+c_j))), else the last one.  Initial states: bit i of chain
+ * c is bit (i mod 32) of word (w mod 4) of Philox((0, c, w/4, 4)), w = i/32.
+ *
+ * Status codes: every int-returning call returns one of PBN_* below; details
+ * of the last error on the calling thread come from pbn_last_error().
+ */
+#ifndef PBNSSA_H
+#define PBNSSA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PBN_OK = 0,
+    PBN_EINVAL = 1,     /* bad argument (omega < 2, r <= 0, s not in (0,1), ...)      */
+    PBN_EFORMAT = 2,    /* malformed network text                                     */
+    PBN_ENOMEM = 3,     /* device buffer too small / server budget exhausted          */
+    PBN_EDEVICE = 4,    /* a HIP call failed (message in pbn_last_error)              */
+    PBN_ENOTCONV = 5,   /* result status: a chain-length cap was hit before the stop  */
+    PBN_ELIMIT = 6      /* a structural limit was exceeded (see the limits below)     */
+};
+
+enum { PBN_TWO_STATE = 0, PBN_SKART = 1 };
+
+/* Limits: n <= 65535 nodes, l(i) <= 64 functions per node, k <= 16 parents per
+ * function, at most PBN_MAX_PROPS state sets per simulation and
+ * PBN_MAX_TERMS (node, value) terms over all of them, transitions per chain
+ * below 2^32. */
+#define PBN_MAX_PROPS 8
+#define PBN_MAX_TERMS 64
+
+typedef struct pbn_net pbn_net;      /* parsed + compiled network (host memory, library-owned) */
+typedef struct pbn_sim pbn_sim;      /* omega chains of one network on one device buffer      */
+typedef struct pbn_server pbn_server;
+
+/* A set of states of interest (Sec. 3.1: meta state 1): the conjunction
+ * node[m] == val[m] over nterms terms (0-based node ids).  Caller-owned;
+ * copied by the call that takes it. */
+typedef struct {
+    uint32_t nterms;
+    const uint32_t *node;
+    const uint8_t *val;
+} pbn_pattern;
+
+typedef struct {
+    int method;                   /* PBN_TWO_STATE (Alg. 3) or PBN_SKART (Alg. 5)         */
+    uint64_t psi0;                /* initial Gelman-Rubin psi (Alg. 2); 0 -> 256          */
+    double psrf_max;              /* "close to 1": converged when R < psrf_max; 0 -> 1.1  */
+    double eps;                   /* Alg. 1's epsilon for M; 0 -> 1e-10                   */
+    uint64_t max_len;             /* cap on recorded positions per chain; 0 -> buffer cap */
+} pbn_opts;
+
+/* Result per state set.  prob is the estimate (two-state: ones in the final
+ * window / (omega n); Skart: grand batch mean).  ci_lo/ci_hi only for Skart.
+ * psi_gr: psi returned by Alg. 2; psi: final window start (after Alg. 3's
+ * burn-in re-runs); n: window length per chain; N, M: Alg. 1's sample size and
+ * burn-in of the last pass; kappa, batches: Skart batch size and count;
+ * chain_len: positions this state set needed; status: PBN_OK or PBN_ENOTCONV
+ * (prob then holds NaN or the last estimate). */
+typedef struct {
+    double prob, ci_lo, ci_hi, rhat;
+    uint64_t psi_gr, psi, n, N, M, kappa, batches, chain_len;
+    int status;
+    int reserved;
+} pbn_result;
+
+typedef struct {
+    uint32_t n, W, nfun, p_thr;   /* W = ceil(n/32) state words per chain                 */
+    uint32_t max_k, max_l;
+    uint64_t blob_bytes;          /* compiled network size on the device                  */
+    double density;               /* Sec. 2.2: total parents of all predictors / n        */
+} pbn_net_info;
+
+/* Window aggregates of one state set over positions [lo, hi) (0-based) of all
+ * chains: T1 = sum_c S_c, T2 = sum_c S_c^2 (S_c = ones of chain c in the
+ * window) and the counts of consecutive pairs (x_l, x_{l+1}) inside the window. */
+typedef struct {
+    int64_t T1, T2, n00, n01, n10, n11;
+} pbn_counts;
+
+/* ---------------------------------------------------------------- networks */
+
+/* Parse and compile a network given as canonical text (see pbnsynth):
+ *   "PBN n p" then per node "N i l" and l lines "F c k par_1..par_k tt_hex".
+ * Checks: n <= 65535, p in (0,1), c_j in [0,1] summing to 1 within 1e-12,
+ * 1 <= k <= 16, parents distinct and < n, truth table fits 2^k bits.
+ * Host only (no device call).  On success *out owns the network. */
+int pbn_load(const char *text, size_t len, pbn_net **out);
+void pbn_free(pbn_net *net);
+int pbn_net_get_info(const pbn_net *net, pbn_net_info *out);
+/* Thresholds T_1..T_l of node i (for tests); returns l or -1. */
+int pbn_net_thresholds(const pbn_net *net, uint32_t node, uint32_t *out, uint32_t cap);
+
+/* ------------------------------------------------------------ simulations */
+
+/* Device bytes needed for omega chains, up to max_props state sets and
+ * max_len recorded positions per chain (bit-streams, one bit per position). */
+size_t pbn_sim_bytes(const pbn_net *net, uint32_t omega, uint32_t max_props, uint64_t max_len);
+
+/* Create a simulation in a caller-owned device buffer (e.g. a torch tensor)
+ * of at least pbn_sim_bytes(...) bytes, on the given HIP stream (NULL = the
+ * default stream).  Uploads the compiled network and initialises the chains
+ * (transition counter 0, no recorded positions, no state sets).  The buffer
+ * must outlive the simulation.  Errors: PBN_EINVAL (omega < 1), PBN_ENOMEM
+ * (buffer too small), PBN_EDEVICE. */
+int pbn_sim_create(const pbn_net *net, uint32_t omega, uint64_t seed, uint32_t max_props,
+                   uint64_t max_len, void *dev_buf, size_t dev_bytes, void *hip_stream,
+                   pbn_sim **out);
+void pbn_sim_free(pbn_sim *sim);
+
+/* Restart the chains from s(0) (transition counter 0) and record the given
+ * state sets from now on (nprops <= max_props).  Asynchronous on the stream. */
+int pbn_sim_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops);
+
+/* Advance every chain: burn_in transitions unrecorded, then `steps` recorded
+ * positions, each taken after `thin` transitions (Sec. 4: the chains are
+ * extended in parallel).  Asynchronous on the stream.  Errors: PBN_ELIMIT if
+ * the bit-stream capacity or the 2^32 transition limit would be exceeded. */
+int run_chains(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin);
+
+/* Gelman-Rubin R (Alg. 2) of state set `prop` over the last psi recorded
+ * positions of every chain (positions len-psi+1..len).  Synchronises.
+ * *rhat = +inf when the within-chain variance W is 0. */
+int psrf(pbn_sim *sim, uint32_t prop, uint64_t psi, double *rhat);
+
+/* Window aggregates over positions [lo, hi) of state set prop.  Synchronises. */
+int pbn_window_counts(pbn_sim *sim, uint32_t prop, uint64_t lo, uint64_t hi, pbn_counts *out);
+
+/* Batch sums for Skart: for each chain c and batch b < m, the ones in
+ * positions [base + b kappa, base + (b+1) kappa); out[c*m + b].  Synchronises. */
+int pbn_batch_sums(pbn_sim *sim, uint32_t prop, uint64_t base, uint64_t kappa, uint64_t m,
+                   int32_t *out);
+
+/* Current chain states, packed: out[c*W + w] bit b = node 32w+b.  Synchronises. */
+int pbn_sim_read_state(pbn_sim *sim, uint32_t *out);
+/* Recorded indicators of prop for positions [pos0, pos0+npos): out[c*npos + k]. */
+int pbn_sim_read_bits(pbn_sim *sim, uint32_t prop, uint64_t pos0, uint64_t npos, uint8_t *out);
+/* Recorded positions per chain and transitions done so far. */
+int pbn_sim_position(const pbn_sim *sim, uint64_t *len, uint64_t *transitions);
+int pbn_sim_sync(pbn_sim *sim);
+
+/* Full estimate (Alg. 2 then Alg. 3 or Alg. 5) for nprops state sets sharing
+ * the chains (Sec. 4.2, multiple properties): the chains restart from s(0);
+ * each set runs its own procedure; the chains are extended to the smallest
+ * pending requirement.  confidence is s (two-state) or 1 - alpha (Skart); for
+ * Skart r is H*.  out[nprops].  Returns PBN_OK even when a set ends with
+ * status PBN_ENOTCONV. */
+int estimate_prob(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops, double r,
+                  double confidence, const pbn_opts *opts, pbn_result *out);
+
+/* ---------------------------------------------------------------- batched */
+
+/* Advance `count` simulations by steps[i] recorded positions each (thin 1,
+ * no burn-in) in one launch on `hip_stream`. */
+int pbn_batch_run(pbn_sim *const *sims, uint32_t count, const uint64_t *steps, void *hip_stream);
+
+/* Estimate for `count` simulations at once: each simulation i has nprops[i]
+ * state sets starting at props[prop_off[i]], precision r[i] and confidence
+ * conf[i]; every round extends all pending simulations in one launch and
+ * reduces all pending windows in one launch.  out[prop_off[i] + q].
+ * Each result equals that of estimate_prob on the simulation alone. */
+int pbn_batch_estimate(pbn_sim *const *sims, uint32_t count, const pbn_pattern *props,
+                       const uint32_t *nprops, const uint32_t *prop_off, const double *r,
+                       const double *conf, const pbn_opts *opts, void *hip_stream,
+                       pbn_result *out);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A server owns a caller-provided device arena of arena_bytes.  Requests are
+ * admitted when their footprint (pbn_sim_bytes) fits in the free arena; their
+ * chains stay on the device across extension rounds; each call to
+ * pbn_server_step runs one round for every active request (one batched
+ * extension launch, one batched reduction launch) and admits waiting requests
+ * into freed space at the round boundary (continuous batching). */
+int pbn_server_create(void *dev_arena, size_t arena_bytes, void *hip_stream, pbn_server **out);
+void pbn_server_free(pbn_server *srv);
+/* Queue a request (the network is copied).  *id receives its handle. */
+int pbn_server_submit(pbn_server *srv, const pbn_net *net, uint32_t omega, uint64_t seed,
+                      const pbn_pattern *props, uint32_t nprops, double r, double confidence,
+                      const pbn_opts *opts, uint64_t max_len, uint64_t *id);
+/* One round.  *active / *waiting / *done receive the counts after the round. */
+int pbn_server_step(pbn_server *srv, uint32_t *active, uint32_t *waiting, uint32_t *done);
+/* Results of a finished request: returns PBN_OK and fills out[nprops] once
+ * done, PBN_ENOTCONV-free; returns PBN_EINVAL for unknown ids, and sets
+ * *ready = 0 while the request is still queued or running. */
+int pbn_server_poll(pbn_server *srv, uint64_t id, int *ready, pbn_result *out);
+/* Bytes of the arena currently in use and the peak so far. */
+int pbn_server_memory(const pbn_server *srv, size_t *in_use, size_t *peak);
+
+/* ---------------------------------------------------------------- misc */
+
+/* Phi^{-1}(p) (AS 241) and the Student-t quantile used by the statistics. */
+double pbn_normal_quantile(double p);
+double pbn_t_quantile(double p, double nu);
+const char *pbn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

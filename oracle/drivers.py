@@ -126,10 +126,10 @@ def von_neumann_passes(Y: np.ndarray, level: float = 0.20) -> bool:
     omega, m = Y.shape
     if m < 2:
         return True
+    if np.all(Y == Y.flat[0]):
+        return True
     ybar = float(np.sum(Y)) / Y.size
     den = float(np.sum((Y - ybar) ** 2))
-    if den == 0.0:
-        return True
     num = float(np.sum((Y[:, 1:] - Y[:, :-1]) ** 2))
     npairs = omega * (m - 1)
     C = 1.0 - (num / npairs) / (2.0 * den / (Y.size - 1))
@@ -141,10 +141,10 @@ def adjusted_ci(Y: np.ndarray, alpha: float):
     omega, m = Y.shape
     pp = Y.size
     mu = float(np.sum(Y)) / pp
+    if np.all(Y == Y.flat[0]):
+        return mu, mu, mu
     dev = Y - mu
     ss = float(np.sum(dev ** 2))
-    if ss == 0.0:
-        return mu, mu, mu
     S2 = ss / (pp - 1)
     phi = 0.0
     if m >= 2:
@@ -176,10 +176,16 @@ def estimate_ci_in_parallel(ch: Chains, q: int, psi0: int, psrf_max: float, H_st
     base = psi
     eta0 = _cdiv(1280, omega) * omega
     m0 = eta0 // omega
+    if base + m0 > cap:
+        res.update(status=NOT_CONVERGED, chain_len=ch.length)
+        return res
     ch.extend_to(base + m0)
     B = stats.skewness(ch.bits[q][:, base: base + m0].reshape(-1))
     kappa = 16 if abs(B) > 4.0 else 1
     p = eta0
+    if base + kappa * (p // omega) > cap:
+        res.update(status=NOT_CONVERGED, chain_len=ch.length)
+        return res
     Y = _batch_means(ch, q, base, kappa, p)
     tries = 0
     while not von_neumann_passes(Y) and tries < 10:

@@ -1,0 +1,509 @@
+// C ABI of libpbnssa: networks, simulations, the plain and batched estimate
+// entry points and the serving loop.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "pbn_driver.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int sync(hipStream_t s)
+{
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(PBN_EDEVICE, std::string("sync: ") + hipGetErrorString(e));
+    return PBN_OK;
+}
+
+// Window aggregates of one sim, synchronously, through its own workspace.
+int window_query(pbn_sim *sim, uint32_t prop, uint64_t lo, uint64_t hi, pbn::WindowResult *out)
+{
+    std::string err;
+    if (prop >= sim->nprops) return fail(PBN_EINVAL, "state set index out of range");
+    if (!(lo < hi) || hi > sim->len) return fail(PBN_EINVAL, "window outside the recorded positions");
+    int rc = sim->ws.ensure(0, 1, 0, err);
+    if (rc) return fail(rc, err);
+    pbn::Query q{};
+    q.sim = sim->d_desc;
+    q.prop = prop;
+    q.kind = pbn::kQueryWindow;
+    q.lo = lo;
+    q.hi = hi;
+    *sim->ws.h_queries = q;
+    if (hipMemcpyAsync(sim->ws.d_queries, sim->ws.h_queries, sizeof q, hipMemcpyHostToDevice, sim->stream) != hipSuccess)
+        return fail(PBN_EDEVICE, "query upload");
+    if ((rc = pbn::launch_reduce(sim->ws.d_queries, 1, sim->ws.d_win, sim->ws.d_bsum, sim->stream, err)))
+        return fail(rc, err);
+    if (hipMemcpyAsync(sim->ws.h_win, sim->ws.d_win, sizeof(pbn::WindowResult), hipMemcpyDeviceToHost,
+                       sim->stream) != hipSuccess)
+        return fail(PBN_EDEVICE, "result download");
+    if ((rc = sync(sim->stream))) return rc;
+    *out = *sim->ws.h_win;
+    return PBN_OK;
+}
+
+bool valid_patterns(const pbn_pattern *props, uint32_t nprops)
+{
+    if (nprops && !props) return false;
+    for (uint32_t q = 0; q < nprops; ++q)
+        if (props[q].nterms && (!props[q].node || !props[q].val)) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pbn_last_error(void) { return g_last_error.c_str(); }
+
+int pbn_load(const char *text, size_t len, pbn_net **out)
+{
+    if (!text || !out) return fail(PBN_EINVAL, "null argument");
+    std::unique_ptr<pbn_net> net(new pbn_net());
+    std::string err;
+    int rc = pbn::parse_and_compile(text, len, net->net, err);
+    if (rc) return fail(rc, err);
+    *out = net.release();
+    return PBN_OK;
+}
+
+void pbn_free(pbn_net *net) { delete net; }
+
+int pbn_net_get_info(const pbn_net *net, pbn_net_info *out)
+{
+    if (!net || !out) return fail(PBN_EINVAL, "null argument");
+    const pbn::Net &n = net->net;
+    out->n = n.n;
+    out->W = n.W;
+    out->nfun = n.F;
+    out->p_thr = n.p_thr;
+    out->max_k = n.max_k;
+    out->max_l = n.max_l;
+    out->blob_bytes = n.blob_bytes;
+    out->density = n.density;
+    return PBN_OK;
+}
+
+int pbn_net_thresholds(const pbn_net *net, uint32_t node, uint32_t *out, uint32_t cap)
+{
+    if (!net || node >= net->net.n) return -1;
+    const uint32_t a = net->net.nd_first[node], b = net->net.nd_first[node + 1];
+    for (uint32_t j = a; j < b && j - a < cap; ++j) out[j - a] = net->net.fn_thr[j];
+    return (int)(b - a);
+}
+
+size_t pbn_sim_bytes(const pbn_net *net, uint32_t omega, uint32_t max_props, uint64_t max_len)
+{
+    if (!net) return 0;
+    return pbn::sim_bytes(net->net, omega, max_props, max_len);
+}
+
+int pbn_sim_create(const pbn_net *net, uint32_t omega, uint64_t seed, uint32_t max_props, uint64_t max_len,
+                   void *dev_buf, size_t dev_bytes, void *hip_stream, pbn_sim **out)
+{
+    if (!net || !out) return fail(PBN_EINVAL, "null argument");
+    std::unique_ptr<pbn_sim> sim(new pbn_sim());
+    std::string err;
+    int rc = pbn::sim_setup(sim.get(), net->net, omega, seed, max_props, max_len, dev_buf, dev_bytes,
+                            (hipStream_t)hip_stream, err);
+    if (rc) return fail(rc, err);
+    *out = sim.release();
+    return PBN_OK;
+}
+
+void pbn_sim_free(pbn_sim *sim)
+{
+    if (!sim) return;
+    (void)hipStreamSynchronize(sim->stream);
+    delete sim;
+}
+
+int pbn_sim_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops)
+{
+    if (!sim || !valid_patterns(props, nprops)) return fail(PBN_EINVAL, "bad argument");
+    std::string err;
+    int rc = pbn::sim_reset(sim, props, nprops, err);
+    return rc ? fail(rc, err) : PBN_OK;
+}
+
+int run_chains(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin)
+{
+    if (!sim || thin < 1) return fail(PBN_EINVAL, "bad argument");
+    if (sim->len + steps > sim->words_cap * 32 - 32) return fail(PBN_ELIMIT, "bit-stream capacity exceeded");
+    if (sim->t_done + burn_in + steps * (uint64_t)thin >= (1ull << 32))
+        return fail(PBN_ELIMIT, "transition index limit (2^32)");
+    if (burn_in + steps * (uint64_t)thin >= (1ull << 32)) return fail(PBN_ELIMIT, "too many transitions");
+    std::vector<pbn::StepItem> items;
+    pbn::sim_extend_items(sim, burn_in, steps, thin, items);
+    std::string err;
+    int rc = pbn::launch_items(items, sim->ws, sim->stream, err);
+    return rc ? fail(rc, err) : PBN_OK;
+}
+
+int psrf(pbn_sim *sim, uint32_t prop, uint64_t psi, double *rhat)
+{
+    if (!sim || !rhat || psi < 2 || psi > sim->len || sim->omega < 2) return fail(PBN_EINVAL, "bad argument");
+    pbn::WindowResult w;
+    int rc = window_query(sim, prop, sim->len - psi, sim->len, &w);
+    if (rc) return rc;
+    bool defined;
+    *rhat = pbn::rhat_from_sums(w.T1, w.T2, sim->omega, psi, &defined);
+    return PBN_OK;
+}
+
+int pbn_window_counts(pbn_sim *sim, uint32_t prop, uint64_t lo, uint64_t hi, pbn_counts *out)
+{
+    if (!sim || !out) return fail(PBN_EINVAL, "null argument");
+    pbn::WindowResult w;
+    int rc = window_query(sim, prop, lo, hi, &w);
+    if (rc) return rc;
+    out->T1 = w.T1; out->T2 = w.T2; out->n00 = w.n00; out->n01 = w.n01; out->n10 = w.n10; out->n11 = w.n11;
+    return PBN_OK;
+}
+
+int pbn_batch_sums(pbn_sim *sim, uint32_t prop, uint64_t base, uint64_t kappa, uint64_t m, int32_t *out)
+{
+    if (!sim || !out || kappa < 1 || m < 1) return fail(PBN_EINVAL, "bad argument");
+    if (prop >= sim->nprops || base + kappa * m > sim->len) return fail(PBN_EINVAL, "batches outside the recorded positions");
+    std::string err;
+    const uint64_t total = (uint64_t)sim->omega * m;
+    int rc = sim->ws.ensure(0, 1, total, err);
+    if (rc) return fail(rc, err);
+    pbn::Query q{};
+    q.sim = sim->d_desc;
+    q.prop = prop;
+    q.kind = pbn::kQueryBatch;
+    q.lo = base;
+    q.hi = base + kappa * m;
+    q.kappa = kappa;
+    q.m = m;
+    *sim->ws.h_queries = q;
+    if (hipMemcpyAsync(sim->ws.d_queries, sim->ws.h_queries, sizeof q, hipMemcpyHostToDevice, sim->stream) != hipSuccess)
+        return fail(PBN_EDEVICE, "query upload");
+    if ((rc = pbn::launch_reduce(sim->ws.d_queries, 1, sim->ws.d_win, sim->ws.d_bsum, sim->stream, err)))
+        return fail(rc, err);
+    if (hipMemcpyAsync(sim->ws.h_bsum, sim->ws.d_bsum, total * 4, hipMemcpyDeviceToHost, sim->stream) != hipSuccess)
+        return fail(PBN_EDEVICE, "download");
+    if ((rc = sync(sim->stream))) return rc;
+    std::memcpy(out, sim->ws.h_bsum, total * 4);
+    return PBN_OK;
+}
+
+int pbn_sim_read_state(pbn_sim *sim, uint32_t *out)
+{
+    if (!sim || !out) return fail(PBN_EINVAL, "null argument");
+    const size_t words = (size_t)sim->net.W * sim->omega;
+    std::vector<uint32_t> tmp(words);
+    if (hipMemcpyAsync(tmp.data(), sim->desc.state, words * 4, hipMemcpyDeviceToHost, sim->stream) != hipSuccess)
+        return fail(PBN_EDEVICE, "download");
+    int rc = sync(sim->stream);
+    if (rc) return rc;
+    for (uint32_t c = 0; c < sim->omega; ++c)
+        for (uint32_t w = 0; w < sim->net.W; ++w) out[(size_t)c * sim->net.W + w] = tmp[(size_t)w * sim->omega + c];
+    return PBN_OK;
+}
+
+int pbn_sim_read_bits(pbn_sim *sim, uint32_t prop, uint64_t pos0, uint64_t npos, uint8_t *out)
+{
+    if (!sim || !out || prop >= sim->nprops || pos0 + npos > sim->len) return fail(PBN_EINVAL, "bad argument");
+    if (npos == 0) return PBN_OK;
+    const uint64_t w0 = pos0 / 32, w1 = (pos0 + npos + 31) / 32;
+    const size_t words = (size_t)(w1 - w0) * sim->omega;
+    std::vector<uint32_t> tmp(words);
+    const uint32_t *src = sim->desc.bits + ((size_t)prop * sim->words_cap + w0) * sim->omega;
+    if (hipMemcpyAsync(tmp.data(), src, words * 4, hipMemcpyDeviceToHost, sim->stream) != hipSuccess)
+        return fail(PBN_EDEVICE, "download");
+    int rc = sync(sim->stream);
+    if (rc) return rc;
+    for (uint32_t c = 0; c < sim->omega; ++c)
+        for (uint64_t k = 0; k < npos; ++k) {
+            const uint64_t pos = pos0 + k;
+            out[(size_t)c * npos + k] = (tmp[(size_t)(pos / 32 - w0) * sim->omega + c] >> (pos % 32)) & 1u;
+        }
+    return PBN_OK;
+}
+
+int pbn_sim_position(const pbn_sim *sim, uint64_t *len, uint64_t *transitions)
+{
+    if (!sim) return fail(PBN_EINVAL, "null argument");
+    if (len) *len = sim->len;
+    if (transitions) *transitions = sim->t_done;
+    return PBN_OK;
+}
+
+int pbn_sim_sync(pbn_sim *sim)
+{
+    if (!sim) return fail(PBN_EINVAL, "null argument");
+    return sync(sim->stream);
+}
+
+int estimate_prob(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops, double r, double confidence,
+                  const pbn_opts *opts, pbn_result *out)
+{
+    uint32_t off = 0;
+    return pbn_batch_estimate(&sim, 1, props, &nprops, &off, &r, &confidence, opts, sim ? sim->stream : nullptr,
+                              out);
+}
+
+int pbn_batch_run(pbn_sim *const *sims, uint32_t count, const uint64_t *steps, void *hip_stream)
+{
+    if (!sims || !steps) return fail(PBN_EINVAL, "null argument");
+    std::vector<pbn::StepItem> items;
+    for (uint32_t i = 0; i < count; ++i) {
+        pbn_sim *s = sims[i];
+        if (!s) return fail(PBN_EINVAL, "null simulation");
+        if (s->len + steps[i] > s->words_cap * 32 - 32) return fail(PBN_ELIMIT, "bit-stream capacity exceeded");
+        if (s->t_done + steps[i] >= (1ull << 32)) return fail(PBN_ELIMIT, "transition index limit (2^32)");
+    }
+    for (uint32_t i = 0; i < count; ++i)
+        if (steps[i]) pbn::sim_extend_items(sims[i], 0, steps[i], 1, items);
+    static thread_local pbn::Workspace ws;
+    std::string err;
+    int rc = pbn::launch_items(items, ws, (hipStream_t)hip_stream, err);
+    if (rc) return fail(rc, err);
+    return sync((hipStream_t)hip_stream);
+}
+
+int pbn_batch_estimate(pbn_sim *const *sims, uint32_t count, const pbn_pattern *props, const uint32_t *nprops,
+                       const uint32_t *prop_off, const double *r, const double *conf, const pbn_opts *opts,
+                       void *hip_stream, pbn_result *out)
+{
+    if (!sims || !nprops || !prop_off || !r || !conf || !out) return fail(PBN_EINVAL, "null argument");
+    std::vector<pbn::SimRun> runs(count);
+    std::string err;
+    for (uint32_t i = 0; i < count; ++i) {
+        pbn_sim *s = sims[i];
+        if (!s) return fail(PBN_EINVAL, "null simulation");
+        if (s->omega < 2) return fail(PBN_EINVAL, "Gelman-Rubin needs omega >= 2 chains");
+        if (!(r[i] > 0.0) || !(conf[i] > 0.0 && conf[i] < 1.0)) return fail(PBN_EINVAL, "r must be > 0 and s in (0,1)");
+        if (nprops[i] < 1 || !valid_patterns(props + prop_off[i], nprops[i])) return fail(PBN_EINVAL, "bad state sets");
+        int rc = pbn::sim_reset(s, props + prop_off[i], nprops[i], err);
+        if (rc) return fail(rc, err);
+        runs[i].sim = s;
+        const pbn::MachineParams P = pbn::make_params(s, opts, r[i], conf[i]);
+        for (uint32_t q = 0; q < nprops[i]; ++q) runs[i].machines.emplace_back(P, q);
+    }
+    std::vector<pbn::SimRun *> ptrs;
+    for (auto &x : runs) ptrs.push_back(&x);
+    hipStream_t stream = (hipStream_t)hip_stream;
+    // every simulation of one batch runs on the batch's stream
+    for (uint32_t i = 0; i < count; ++i)
+        if (sims[i]->stream != stream) {
+            int rc = sync(sims[i]->stream);
+            if (rc) return rc;
+        }
+    static thread_local pbn::Workspace ws;
+    pbn::Workspace &w = count == 1 ? sims[0]->ws : ws;
+    int rc = pbn::run_to_completion(ptrs, w, stream, err);
+    if (rc) return fail(rc, err);
+    for (uint32_t i = 0; i < count; ++i)
+        for (uint32_t q = 0; q < nprops[i]; ++q) out[prop_off[i] + q] = runs[i].machines[q].result();
+    return PBN_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ serving
+
+namespace {
+
+// First-fit arena over the caller's device buffer (256-byte granules).
+struct Arena {
+    size_t size = 0, in_use = 0, peak = 0;
+    std::map<size_t, size_t> free_;   // offset -> length
+    void init(size_t bytes) { size = bytes & ~size_t(255); free_.clear(); free_[0] = size; in_use = peak = 0; }
+    bool alloc(size_t bytes, size_t *off)
+    {
+        bytes = (bytes + 255) & ~size_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes;
+            const size_t noff = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[noff] = rest;
+            in_use += bytes;
+            peak = std::max(peak, in_use);
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        bytes = (bytes + 255) & ~size_t(255);
+        in_use -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct ServeReq {
+    uint64_t id = 0;
+    pbn::Net net;
+    uint32_t omega = 0;
+    uint64_t seed = 0, max_len = 0;
+    std::vector<std::vector<uint32_t>> nodes;
+    std::vector<std::vector<uint8_t>> vals;
+    double r = 0, conf = 0;
+    pbn_opts opts{};
+    size_t bytes = 0, off = 0;
+    int state = 0;   // 0 queued, 1 active, 2 done
+    std::unique_ptr<pbn_sim> sim;
+    pbn::SimRun run;
+    std::vector<pbn_result> results;
+};
+
+}  // namespace
+
+struct pbn_server {
+    uint8_t *arena_base = nullptr;
+    Arena arena;
+    hipStream_t stream = nullptr;
+    pbn::Workspace ws;
+    uint64_t next_id = 1;
+    std::deque<ServeReq *> queue;
+    std::vector<ServeReq *> active;
+    std::map<uint64_t, std::unique_ptr<ServeReq>> all;
+    uint32_t done = 0;
+};
+
+extern "C" {
+
+int pbn_server_create(void *dev_arena, size_t arena_bytes, void *hip_stream, pbn_server **out)
+{
+    if (!dev_arena || !out) return fail(PBN_EINVAL, "null argument");
+    pbn_server *s = new pbn_server();
+    s->arena_base = (uint8_t *)dev_arena;
+    s->arena.init(arena_bytes);
+    s->stream = (hipStream_t)hip_stream;
+    *out = s;
+    return PBN_OK;
+}
+
+void pbn_server_free(pbn_server *srv)
+{
+    if (!srv) return;
+    (void)hipStreamSynchronize(srv->stream);
+    delete srv;
+}
+
+int pbn_server_submit(pbn_server *srv, const pbn_net *net, uint32_t omega, uint64_t seed, const pbn_pattern *props,
+                      uint32_t nprops, double r, double confidence, const pbn_opts *opts, uint64_t max_len,
+                      uint64_t *id)
+{
+    if (!srv || !net || !id || nprops < 1 || nprops > PBN_MAX_PROPS || !valid_patterns(props, nprops))
+        return fail(PBN_EINVAL, "bad argument");
+    if (omega < 2 || !(r > 0.0) || !(confidence > 0.0 && confidence < 1.0)) return fail(PBN_EINVAL, "bad parameters");
+    auto rq = std::make_unique<ServeReq>();
+    rq->id = srv->next_id++;
+    rq->net = net->net;
+    rq->omega = omega;
+    rq->seed = seed;
+    rq->max_len = max_len;
+    rq->r = r;
+    rq->conf = confidence;
+    if (opts) rq->opts = *opts;
+    for (uint32_t q = 0; q < nprops; ++q) {
+        rq->nodes.emplace_back(props[q].node, props[q].node + props[q].nterms);
+        rq->vals.emplace_back(props[q].val, props[q].val + props[q].nterms);
+    }
+    rq->bytes = pbn::sim_bytes(rq->net, omega, nprops, max_len);
+    if (rq->bytes > srv->arena.size) return fail(PBN_ENOMEM, "request larger than the whole arena");
+    *id = rq->id;
+    srv->queue.push_back(rq.get());
+    srv->all[rq->id] = std::move(rq);
+    return PBN_OK;
+}
+
+int pbn_server_step(pbn_server *srv, uint32_t *active, uint32_t *waiting, uint32_t *done)
+{
+    if (!srv) return fail(PBN_EINVAL, "null argument");
+    std::string err;
+    // admission at the round boundary: first fit, in arrival order
+    for (auto it = srv->queue.begin(); it != srv->queue.end();) {
+        ServeReq *rq = *it;
+        size_t off;
+        if (!srv->arena.alloc(rq->bytes, &off)) { ++it; continue; }
+        rq->off = off;
+        rq->sim.reset(new pbn_sim());
+        int rc = pbn::sim_setup(rq->sim.get(), rq->net, rq->omega, rq->seed, (uint32_t)rq->nodes.size(), rq->max_len,
+                                srv->arena_base + off, rq->bytes, srv->stream, err);
+        std::vector<pbn_pattern> pats(rq->nodes.size());
+        for (size_t q = 0; q < pats.size(); ++q) pats[q] = {(uint32_t)rq->nodes[q].size(), rq->nodes[q].data(), rq->vals[q].data()};
+        if (!rc) rc = pbn::sim_reset(rq->sim.get(), pats.data(), (uint32_t)pats.size(), err);
+        if (rc) return fail(rc, err);
+        rq->run.sim = rq->sim.get();
+        const pbn::MachineParams P = pbn::make_params(rq->sim.get(), &rq->opts, rq->r, rq->conf);
+        for (uint32_t q = 0; q < pats.size(); ++q) rq->run.machines.emplace_back(P, q);
+        rq->state = 1;
+        srv->active.push_back(rq);
+        it = srv->queue.erase(it);
+    }
+    std::vector<pbn::SimRun *> runs;
+    for (ServeReq *rq : srv->active) runs.push_back(&rq->run);
+    if (!runs.empty()) {
+        int rc = pbn::run_round(runs, srv->ws, srv->stream, err);
+        if (rc) return fail(rc, err);
+    }
+    // retire finished requests and free their memory for the next admission
+    for (auto it = srv->active.begin(); it != srv->active.end();) {
+        ServeReq *rq = *it;
+        if (!rq->run.finished()) { ++it; continue; }
+        for (auto &m : rq->run.machines) rq->results.push_back(m.result());
+        rq->run.machines.clear();
+        rq->sim.reset();
+        srv->arena.release(rq->off, rq->bytes);
+        rq->state = 2;
+        ++srv->done;
+        it = srv->active.erase(it);
+    }
+    if (active) *active = (uint32_t)srv->active.size();
+    if (waiting) *waiting = (uint32_t)srv->queue.size();
+    if (done) *done = srv->done;
+    return PBN_OK;
+}
+
+int pbn_server_poll(pbn_server *srv, uint64_t id, int *ready, pbn_result *out)
+{
+    if (!srv || !ready) return fail(PBN_EINVAL, "null argument");
+    auto it = srv->all.find(id);
+    if (it == srv->all.end()) return fail(PBN_EINVAL, "unknown request");
+    ServeReq *rq = it->second.get();
+    *ready = rq->state == 2;
+    if (*ready && out) std::copy(rq->results.begin(), rq->results.end(), out);
+    return PBN_OK;
+}
+
+int pbn_server_memory(const pbn_server *srv, size_t *in_use, size_t *peak)
+{
+    if (!srv) return fail(PBN_EINVAL, "null argument");
+    if (in_use) *in_use = srv->arena.in_use;
+    if (peak) *peak = srv->arena.peak;
+    return PBN_OK;
+}
+
+}  // extern "C"

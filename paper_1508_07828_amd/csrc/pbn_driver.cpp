@@ -1,0 +1,619 @@
+// Host control of the method (Alg. 2, Alg. 3, Alg. 5 and the multi-property
+// scheme of Sec. 4.2) over device-resident chains.
+//
+// Readings of the paper that this file implements (it is silent or garbled on
+// them):
+//   Alg. 2  the monitored scalar is the state set's 0-1 indicator; s_i uses the
+//           denominator psi-1; the chains reach 2*psi0 positions first and each
+//           check uses positions psi+1..2psi; converged when R < psrf_max; a
+//           check with W = 0 is "not converged"; the returned psi is the last
+//           one checked.
+//   Alg. 3  the first pass uses the existing second halves without extending;
+//           the extension is ceil((N - omega n)/omega) and the pass loop ends
+//           when it is <= 0; alpha and beta come from all consecutive pairs
+//           inside each chain's window; if either is undefined the window
+//           doubles; a re-run happens when M > psi and moves the window start
+//           to M (psi := M), refilling it to the Gelman-Rubin psi if it
+//           became empty; the estimate is the fraction of ones in the window.
+//   Alg. 5  (Skart-P) eta0 = ceil(1280/omega) omega first observations;
+//           batch size 16 if |skewness| > 4 else 1; p/omega consecutive
+//           batches per chain; von Neumann randomness test on within-chain
+//           adjacent batch means at level 0.2, on failure kappa :=
+//           ceil(sqrt 2 kappa) and p := ceil(0.9 p) rounded up to a multiple of
+//           omega (at most 10 times); CI skewness- (Willink) and lag-1
+//           autoregression-adjusted; if the half-width H > H* the batch size
+//           grows to ceil(kappa (H/H*)^2).
+//   Sec. 4.2  every state set runs its own machine on the shared chains;
+//           the chains grow to the smallest pending requirement.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "pbn_driver.h"
+
+namespace pbn {
+
+// ------------------------------------------------------------ workspace
+
+int Workspace::ensure(size_t items, size_t queries, size_t bsum, std::string &err)
+{
+    auto grow = [&](auto *&d, auto *&h, size_t &cap, size_t need, size_t elem) -> int {
+        if (need <= cap) return PBN_OK;
+        size_t nc = std::max<size_t>(need, 2 * cap);
+        if (d) (void)hipFree(d);
+        if (h) (void)hipHostFree(h);
+        d = nullptr; h = nullptr; cap = 0;
+        if (hipMalloc((void **)&d, nc * elem) != hipSuccess) { err = "workspace hipMalloc"; return PBN_ENOMEM; }
+        if (hipHostMalloc((void **)&h, nc * elem, hipHostMallocDefault) != hipSuccess) {
+            err = "workspace hipHostMalloc";
+            return PBN_ENOMEM;
+        }
+        cap = nc;
+        return PBN_OK;
+    };
+    int rc;
+    if ((rc = grow(d_items, h_items, cap_items, std::max<size_t>(items, 1), sizeof(StepItem)))) return rc;
+    size_t qcap = cap_q;
+    if ((rc = grow(d_queries, h_queries, cap_q, std::max<size_t>(queries, 1), sizeof(Query)))) return rc;
+    if (cap_q != qcap || !d_win) {
+        if (d_win) (void)hipFree(d_win);
+        if (h_win) (void)hipHostFree(h_win);
+        d_win = nullptr; h_win = nullptr;
+        if (hipMalloc((void **)&d_win, cap_q * sizeof(WindowResult)) != hipSuccess ||
+            hipHostMalloc((void **)&h_win, cap_q * sizeof(WindowResult), hipHostMallocDefault) != hipSuccess) {
+            err = "workspace results";
+            return PBN_ENOMEM;
+        }
+    }
+    if ((rc = grow(d_bsum, h_bsum, cap_bsum, std::max<size_t>(bsum, 1), sizeof(int32_t)))) return rc;
+    return PBN_OK;
+}
+
+void Workspace::release()
+{
+    if (d_items) (void)hipFree(d_items);
+    if (h_items) (void)hipHostFree(h_items);
+    if (d_queries) (void)hipFree(d_queries);
+    if (h_queries) (void)hipHostFree(h_queries);
+    if (d_win) (void)hipFree(d_win);
+    if (h_win) (void)hipHostFree(h_win);
+    if (d_bsum) (void)hipFree(d_bsum);
+    if (h_bsum) (void)hipHostFree(h_bsum);
+    d_items = h_items = nullptr;
+    d_queries = h_queries = nullptr;
+    d_win = h_win = nullptr;
+    d_bsum = h_bsum = nullptr;
+    cap_items = cap_q = cap_bsum = 0;
+}
+
+// ------------------------------------------------------------ formulas
+
+namespace {
+
+int64_t cdiv(int64_t a, int64_t b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); }
+
+// Alg. 1's N (before the ceiling): ab(2-a-b)/(a+b)^3 * z^2/r^2.
+double formula_N(double a, double b, double z, double r)
+{
+    double x = (a * b * ((2.0 - a) - b)) / ((a + b) * (a + b) * (a + b));
+    return x * ((z * z) / (r * r));
+}
+
+// Alg. 1's M: ceil(log(eps (a+b)/max(a,b)) / log|1-a-b|), 0 when |1-a-b| is 0 or 1.
+uint64_t formula_M(double a, double b, double eps)
+{
+    double lam = std::fabs((1.0 - a) - b);
+    if (lam == 0.0 || lam == 1.0) return 0;
+    double v = std::ceil(std::log(eps * (a + b) / std::max(a, b)) / std::log(lam));
+    return v <= 0.0 ? 0 : (uint64_t)v;
+}
+
+// Skewness adjustment of a t critical value (Willink): ((1+6b(z-b))^{1/3}-1)/(2b);
+// the cube root minus one is expm1(log1p(x)/3) for |x| < 1/2.
+double willink(double zeta, double beta)
+{
+    if (beta == 0.0) return zeta;
+    double x = 6.0 * beta * (zeta - beta);
+    double d = std::fabs(x) < 0.5 ? std::expm1(std::log1p(x) / 3.0) : std::cbrt(1.0 + x) - 1.0;
+    return d / (2.0 * beta);
+}
+
+bool all_equal(const int32_t *v, uint64_t count)
+{
+    for (uint64_t i = 1; i < count; ++i)
+        if (v[i] != v[0]) return false;
+    return true;
+}
+
+// Von Neumann ratio over within-chain adjacent batch means, one-sided at level 0.2.
+bool randomness_passes(const int32_t *bsum, uint32_t omega, uint64_t m, uint64_t kappa)
+{
+    if (m < 2) return true;
+    const uint64_t size = (uint64_t)omega * m;
+    if (all_equal(bsum, size)) return true;
+    const double k = (double)kappa;
+    double sum = 0.0;
+    for (uint64_t e = 0; e < size; ++e) sum += (double)bsum[e] / k;
+    const double ybar = sum / (double)size;
+    double den = 0.0, num = 0.0;
+    for (uint64_t e = 0; e < size; ++e) {
+        double d = (double)bsum[e] / k - ybar;
+        den += d * d;
+    }
+    for (uint32_t c = 0; c < omega; ++c)
+        for (uint64_t b = 0; b + 1 < m; ++b) {
+            double d = (double)bsum[c * m + b + 1] / k - (double)bsum[c * m + b] / k;
+            num += d * d;
+        }
+    const double npairs = (double)((uint64_t)omega * (m - 1));
+    const double C = 1.0 - (num / npairs) / (2.0 * den / (double)(size - 1));
+    return C <= normal_quantile(1.0 - 0.2) * std::sqrt(1.0 / npairs);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ machine
+
+Machine::Machine(const MachineParams &p, uint32_t prop) : P_(p), prop_(prop)
+{
+    res_.prob = res_.ci_lo = res_.ci_hi = res_.rhat = NAN;
+    res_.status = PBN_OK;
+    z_ = normal_quantile(0.5 * (1.0 + P_.conf));
+    psi_ = P_.psi0;
+    if (2 * psi_ > P_.cap) not_converged(0);
+    else ask_window(psi_, 2 * psi_);
+}
+
+void Machine::ask_window(uint64_t lo, uint64_t hi)
+{
+    req_ = Request{kQueryWindow, lo, hi, 0, 0, hi};
+}
+
+void Machine::ask_batch()
+{
+    const uint64_t m = p_ / P_.omega;
+    req_ = Request{kQueryBatch, base_, base_ + kappa_ * m, kappa_, m, base_ + kappa_ * m};
+}
+
+void Machine::not_converged(uint64_t chain_len)
+{
+    res_.status = PBN_ENOTCONV;
+    res_.psi = psi_;
+    res_.n = n_;
+    res_.chain_len = chain_len;
+    done_ = true;
+}
+
+void Machine::feed_window(const WindowResult &w, uint64_t chain_len)
+{
+    const uint32_t omega = P_.omega;
+    switch (st_) {
+    case kGR: {
+        bool defined;
+        double R = rhat_from_sums(w.T1, w.T2, omega, psi_, &defined);
+        if (defined && R < P_.psrf_max) {
+            res_.psi_gr = psi_;
+            res_.rhat = R;
+            psi_gr_ = psi_;
+            if (P_.method == PBN_TWO_STATE) {
+                n_ = psi_;
+                st_ = kTwoState;
+                if (psi_ + n_ > P_.cap) return not_converged(chain_len);
+                ask_window(psi_, psi_ + n_);
+            } else {
+                res_.psi = psi_;
+                base_ = psi_;
+                const uint64_t eta0 = (uint64_t)cdiv(1280, omega) * omega;
+                st_ = kSkartSkew;
+                if (base_ + eta0 / omega > P_.cap) return not_converged(chain_len);
+                ask_window(base_, base_ + eta0 / omega);
+            }
+        } else {
+            psi_ *= 2;
+            if (2 * psi_ > P_.cap) return not_converged(chain_len);
+            ask_window(psi_, 2 * psi_);
+        }
+        return;
+    }
+    case kTwoState: {
+        int64_t extend_by;
+        const bool undefined = (w.n00 + w.n01 == 0) || (w.n10 + w.n11 == 0);
+        double a = 0.0, b = 0.0;
+        if (!undefined) {
+            a = (double)w.n01 / (double)(w.n00 + w.n01);
+            b = (double)w.n10 / (double)(w.n10 + w.n11);
+        }
+        if (undefined || a + b == 0.0) {
+            extend_by = (int64_t)n_;
+        } else {
+            a_ = a;
+            b_ = b;
+            const double Nf = std::ceil(formula_N(a, b, z_, P_.r));
+            if (!(Nf < 9.0e15)) return not_converged(chain_len);
+            N_ = (uint64_t)Nf;
+            extend_by = cdiv((int64_t)N_ - (int64_t)omega * (int64_t)n_, omega);
+            if (extend_by <= 0) {
+                const uint64_t M = formula_M(a_, b_, P_.eps);
+                res_.M = M;
+                if (M > psi_) {
+                    int64_t n = (int64_t)n_ - (int64_t)(M - psi_);
+                    psi_ = M;
+                    n_ = n <= 0 ? psi_gr_ : (uint64_t)n;
+                    if (psi_ + n_ > P_.cap) return not_converged(chain_len);
+                    ask_window(psi_, psi_ + n_);
+                    return;
+                }
+                return finish_two_state(w.T1);
+            }
+        }
+        n_ += (uint64_t)extend_by;
+        if (psi_ + n_ > P_.cap) return not_converged(chain_len);
+        ask_window(psi_, psi_ + n_);
+        return;
+    }
+    case kSkartSkew: {
+        const uint64_t eta0 = (uint64_t)cdiv(1280, omega) * omega;
+        bool big;
+        if (w.T1 == 0 || (uint64_t)w.T1 == eta0) {
+            big = true;                          // zero variance: skewness unbounded
+        } else {
+            const double q = (double)w.T1 / (double)eta0;
+            const double B = (1.0 - 2.0 * q) / std::sqrt(q * (1.0 - q));
+            big = std::fabs(B) > 4.0;
+        }
+        kappa_ = big ? 16 : 1;
+        p_ = eta0;
+        tries_ = 0;
+        st_ = kSkartRandomness;
+        if (base_ + kappa_ * (p_ / omega) > P_.cap) return not_converged(chain_len);
+        ask_batch();
+        return;
+    }
+    default:
+        return;
+    }
+}
+
+void Machine::feed_batch(const int32_t *bsum, uint64_t chain_len)
+{
+    const uint32_t omega = P_.omega;
+    const uint64_t m = p_ / omega;
+    if (st_ == kSkartRandomness) {
+        if (randomness_passes(bsum, omega, m, kappa_) || tries_ >= 10) {
+            st_ = kSkartCI;
+            return skart_ci(bsum, chain_len);
+        }
+        kappa_ = (uint64_t)std::ceil(std::sqrt(2.0) * (double)kappa_);
+        const uint64_t p09 = (uint64_t)std::ceil(0.9 * (double)p_);
+        p_ = std::max<uint64_t>(omega, (uint64_t)cdiv((int64_t)p09, omega) * omega);
+        ++tries_;
+        if (base_ + kappa_ * (p_ / omega) > P_.cap) return not_converged(chain_len);
+        ask_batch();
+        return;
+    }
+    if (st_ == kSkartCI) skart_ci(bsum, chain_len);
+}
+
+void Machine::skart_ci(const int32_t *bsum, uint64_t chain_len)
+{
+    const uint32_t omega = P_.omega;
+    const uint64_t m = p_ / omega, pp = p_;
+    const double k = (double)kappa_;
+    double sum = 0.0;
+    for (uint64_t e = 0; e < pp; ++e) sum += (double)bsum[e] / k;
+    const double mu = sum / (double)pp;
+    double lo = mu, hi = mu;
+    if (!all_equal(bsum, pp)) {
+        double ss = 0.0, s3 = 0.0, lag = 0.0;
+        for (uint64_t e = 0; e < pp; ++e) {
+            const double d = (double)bsum[e] / k - mu;
+            ss += d * d;
+            s3 += d * d * d;
+        }
+        double phi = 0.0;
+        if (m >= 2) {
+            for (uint32_t c = 0; c < omega; ++c)
+                for (uint64_t b = 0; b + 1 < m; ++b)
+                    lag += ((double)bsum[c * m + b + 1] / k - mu) * ((double)bsum[c * m + b] / k - mu);
+            phi = (lag / (double)((uint64_t)omega * (m - 1))) / (ss / (double)pp);
+        }
+        const double A = phi > 0.0 ? (1.0 + phi) / (1.0 - phi) : 1.0;
+        const double S2 = ss / (double)(pp - 1);
+        const double skew = (s3 / (double)pp) / std::pow(ss / (double)pp, 1.5);
+        const double beta = skew / (6.0 * std::sqrt((double)pp));
+        const double alpha = 1.0 - P_.conf;
+        const double t_hi = t_quantile(1.0 - alpha / 2.0, (double)(pp - 1));
+        const double se = std::sqrt(A * S2 / (double)pp);
+        lo = mu - willink(t_hi, beta) * se;
+        hi = mu - willink(-t_hi, beta) * se;
+    }
+    const double H = std::max(mu - lo, hi - mu);
+    if (H > P_.r) {
+        const double ratio = H / P_.r;
+        kappa_ = (uint64_t)std::ceil((double)kappa_ * (ratio * ratio));
+        if (base_ + kappa_ * (p_ / omega) > P_.cap) return not_converged(chain_len);
+        ask_batch();
+        return;
+    }
+    res_.prob = mu;
+    res_.ci_lo = lo;
+    res_.ci_hi = hi;
+    res_.kappa = kappa_;
+    res_.batches = p_;
+    res_.n = kappa_ * m;
+    res_.chain_len = base_ + res_.n;
+    res_.psi = base_;
+    done_ = true;
+}
+
+void Machine::finish_two_state(int64_t T1)
+{
+    res_.psi = psi_;
+    res_.n = n_;
+    res_.N = N_;
+    res_.prob = (double)T1 / (double)((uint64_t)P_.omega * n_);
+    res_.chain_len = psi_ + n_;
+    done_ = true;
+}
+
+// ------------------------------------------------------------ simulations
+
+namespace {
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+}  // namespace
+
+size_t sim_bytes(const Net &net, uint32_t omega, uint32_t max_props, uint64_t max_len)
+{
+    const uint64_t words_cap = (max_len + 31) / 32 + 1;
+    return a256(sizeof(DevSim)) + a256(net.blob_bytes) + a256((size_t)net.W * omega * 4) +
+           a256((size_t)std::max<uint32_t>(max_props, 1) * words_cap * omega * 4);
+}
+
+int sim_setup(pbn_sim *sim, const Net &net, uint32_t omega, uint64_t seed, uint32_t max_props,
+              uint64_t max_len, void *dev_buf, size_t dev_bytes, hipStream_t stream, std::string &err)
+{
+    if (omega < 1) { err = "omega must be >= 1"; return PBN_EINVAL; }
+    if (max_props > kMaxProps) { err = "too many state sets"; return PBN_ELIMIT; }
+    if (2ull * 64 * (net.W | 1u) * 4 > 160ull * 1024) { err = "network too large for the LDS state rows"; return PBN_ELIMIT; }
+    const size_t need = sim_bytes(net, omega, max_props, max_len);
+    if (!dev_buf || dev_bytes < need) { err = "device buffer too small"; return PBN_ENOMEM; }
+    sim->net = net;
+    sim->omega = omega;
+    sim->max_props = max_props;
+    sim->seed = seed;
+    sim->max_len = max_len;
+    sim->words_cap = (max_len + 31) / 32 + 1;
+    sim->dbuf = (uint8_t *)dev_buf;
+    sim->dbytes = dev_bytes;
+    sim->stream = stream;
+    uint8_t *p = sim->dbuf;
+    sim->d_desc = (DevSim *)p;
+    p += a256(sizeof(DevSim));
+    uint8_t *blob = p;
+    p += a256(net.blob_bytes);
+    uint32_t *state = (uint32_t *)p;
+    p += a256((size_t)net.W * omega * 4);
+    uint32_t *bits = (uint32_t *)p;
+    DevSim &d = sim->desc;
+    std::memset(&d, 0, sizeof d);
+    d.nd_first = (const uint32_t *)(blob + net.off_nd_first);
+    d.fn_thr = (const uint32_t *)(blob + net.off_fn_thr);
+    d.fn_desc = (const uint32_t *)(blob + net.off_fn_desc);
+    d.fn_tt = (const uint32_t *)(blob + net.off_fn_tt);
+    d.tt_ext = (const uint32_t *)(blob + net.off_tt_ext);
+    d.par = (const uint16_t *)(blob + net.off_par);
+    d.state = state;
+    d.bits = bits;
+    d.words_cap = sim->words_cap;
+    d.n = net.n;
+    d.W = net.W;
+    d.p_thr = net.p_thr;
+    d.omega = omega;
+    d.key0 = (uint32_t)seed;
+    d.key1 = (uint32_t)(seed >> 32);
+    d.nprops = 0;
+    if (hipMemcpyAsync(blob, net.blob.data(), net.blob_bytes, hipMemcpyHostToDevice, stream) != hipSuccess) {
+        err = "blob upload";
+        return PBN_EDEVICE;
+    }
+    return sim_reset(sim, nullptr, 0, err);
+}
+
+int sim_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops, std::string &err)
+{
+    if (nprops > sim->max_props) { err = "more state sets than max_props"; return PBN_EINVAL; }
+    DevSim &d = sim->desc;
+    uint32_t nt = 0;
+    d.prop_off[0] = 0;
+    for (uint32_t q = 0; q < nprops; ++q) {
+        // group the terms of a conjunction by state word: (word, mask, value)
+        std::vector<std::pair<uint32_t, std::pair<uint32_t, uint32_t>>> words;
+        for (uint32_t m = 0; m < props[q].nterms; ++m) {
+            const uint32_t v = props[q].node[m];
+            if (v >= sim->net.n) { err = "state-set node out of range"; return PBN_EINVAL; }
+            const uint32_t w = v >> 5, bit = 1u << (v & 31);
+            auto it = std::find_if(words.begin(), words.end(), [&](auto &e) { return e.first == w; });
+            if (it == words.end()) { words.push_back({w, {0u, 0u}}); it = words.end() - 1; }
+            const uint32_t want = props[q].val[m] ? bit : 0u;
+            if ((it->second.first & bit) && ((it->second.second & bit) != want)) {
+                // contradictory terms: the set is empty; encode an impossible test
+                it->second.second |= bit;
+                it->second.first &= ~bit;
+                continue;
+            }
+            it->second.first |= bit;
+            it->second.second |= want;
+        }
+        for (auto &e : words) {
+            if (nt >= kMaxTerms) { err = "too many state-set terms"; return PBN_ELIMIT; }
+            d.term_word[nt] = e.first;
+            d.term_mask[nt] = e.second.first;
+            d.term_val[nt] = e.second.second;
+            ++nt;
+        }
+        d.prop_off[q + 1] = nt;
+    }
+    d.nprops = nprops;
+    d.nterms = nt;
+    sim->nprops = nprops;
+    sim->len = 0;
+    sim->t_done = 0;
+    if (hipMemcpyAsync(sim->d_desc, &d, sizeof(DevSim), hipMemcpyHostToDevice, sim->stream) != hipSuccess) {
+        err = "descriptor upload";
+        return PBN_EDEVICE;
+    }
+    // the descriptor copy is from pageable memory; make it complete before d goes away
+    if (hipStreamSynchronize(sim->stream) != hipSuccess) { err = "sync"; return PBN_EDEVICE; }
+    return launch_init(sim->d_desc, sim->omega, sim->net.W, sim->stream, err);
+}
+
+void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin,
+                      std::vector<StepItem> &items)
+{
+    for (uint32_t c0 = 0; c0 < sim->omega; c0 += 64) {
+        StepItem it{};
+        it.sim = sim->d_desc;
+        it.chain0 = c0;
+        it.nchains = std::min<uint32_t>(64, sim->omega - c0);
+        it.t0 = (uint32_t)sim->t_done;
+        it.nburn = (uint32_t)burn_in;
+        it.nrec = (uint32_t)steps;
+        it.thin = thin;
+        it.pos0 = sim->len;
+        it.nodes = sim->net.n;
+        items.push_back(it);
+    }
+    sim->t_done += burn_in + steps * thin;
+    sim->len += steps;
+}
+
+int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream, std::string &err)
+{
+    if (items.empty()) return PBN_OK;
+    // longest items first: the hardware dispatches blocks roughly in order
+    std::vector<std::pair<double, size_t>> order(items.size());
+    uint32_t maxW = 1;
+    int rc = ws.ensure(items.size(), 0, 0, err);
+    if (rc) return rc;
+    // cost ~ transitions x nodes
+    for (size_t i = 0; i < items.size(); ++i) {
+        const StepItem &it = items[i];
+        order[i].second = i;
+        order[i].first = -(double)(it.nburn + (uint64_t)it.nrec * it.thin) * (double)it.nodes;
+        maxW = std::max(maxW, (uint32_t)(it.nodes + 31) / 32);
+    }
+    std::stable_sort(order.begin(), order.end());
+    for (size_t i = 0; i < items.size(); ++i) ws.h_items[i] = items[order[i].second];
+    if (hipMemcpyAsync(ws.d_items, ws.h_items, items.size() * sizeof(StepItem), hipMemcpyHostToDevice,
+                       stream) != hipSuccess) {
+        err = "item upload";
+        return PBN_EDEVICE;
+    }
+    return launch_step(ws.d_items, (uint32_t)items.size(), maxW, stream, err);
+}
+
+// ------------------------------------------------------------ rounds
+
+bool SimRun::finished() const
+{
+    for (auto &m : machines)
+        if (!m.done()) return false;
+    return true;
+}
+
+MachineParams make_params(const pbn_sim *sim, const pbn_opts *opts, double r, double conf)
+{
+    MachineParams p{};
+    p.method = opts ? opts->method : PBN_TWO_STATE;
+    p.omega = sim->omega;
+    p.psi0 = (opts && opts->psi0) ? opts->psi0 : 256;
+    p.psrf_max = (opts && opts->psrf_max > 0.0) ? opts->psrf_max : 1.1;
+    p.eps = (opts && opts->eps > 0.0) ? opts->eps : 1e-10;
+    uint64_t cap = sim->max_len;
+    if (opts && opts->max_len && opts->max_len < cap) cap = opts->max_len;
+    p.cap = cap;
+    p.r = r;
+    p.conf = conf;
+    return p;
+}
+
+int run_round(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err)
+{
+    // 1. extensions for runs with no request ready at their current length
+    std::vector<StepItem> items;
+    for (SimRun *run : runs) {
+        if (run->finished()) continue;
+        pbn_sim *sim = run->sim;
+        bool ready = false;
+        uint64_t target = UINT64_MAX;
+        for (auto &m : run->machines) {
+            if (m.done()) continue;
+            if (m.request().need_len <= sim->len) ready = true;
+            target = std::min(target, m.request().need_len);
+        }
+        if (!ready) {
+            if (target > sim->max_len) { err = "request beyond the bit-stream capacity"; return PBN_ELIMIT; }
+            if (sim->t_done + (target - sim->len) >= (1ull << 32)) { err = "transition index limit"; return PBN_ELIMIT; }
+            sim_extend_items(sim, 0, target - sim->len, 1, items);
+        }
+    }
+    int rc = launch_items(items, ws, stream, err);
+    if (rc) return rc;
+    // 2. queries for every ready request
+    struct Owner { SimRun *run; size_t mi; uint64_t off; };
+    std::vector<Owner> owners;
+    std::vector<Query> qs;
+    uint64_t bsum_total = 0;
+    for (SimRun *run : runs) {
+        for (size_t mi = 0; mi < run->machines.size(); ++mi) {
+            Machine &m = run->machines[mi];
+            if (m.done() || m.request().need_len > run->sim->len) continue;
+            const Request &rq = m.request();
+            Query q{};
+            q.sim = run->sim->d_desc;
+            q.prop = m.prop();
+            q.kind = rq.kind;
+            q.lo = rq.lo;
+            q.hi = rq.hi;
+            q.kappa = rq.kappa;
+            q.m = rq.m;
+            q.out_off = bsum_total;
+            if (rq.kind == kQueryBatch) bsum_total += (uint64_t)run->sim->omega * rq.m;
+            owners.push_back({run, mi, q.out_off});
+            qs.push_back(q);
+        }
+    }
+    if (qs.empty()) return PBN_OK;
+    if ((rc = ws.ensure(0, qs.size(), bsum_total, err))) return rc;
+    std::memcpy(ws.h_queries, qs.data(), qs.size() * sizeof(Query));
+    if (hipMemcpyAsync(ws.d_queries, ws.h_queries, qs.size() * sizeof(Query), hipMemcpyHostToDevice, stream) !=
+        hipSuccess) { err = "query upload"; return PBN_EDEVICE; }
+    if ((rc = launch_reduce(ws.d_queries, (uint32_t)qs.size(), ws.d_win, ws.d_bsum, stream, err))) return rc;
+    if (hipMemcpyAsync(ws.h_win, ws.d_win, qs.size() * sizeof(WindowResult), hipMemcpyDeviceToHost, stream) !=
+        hipSuccess) { err = "result download"; return PBN_EDEVICE; }
+    if (bsum_total && hipMemcpyAsync(ws.h_bsum, ws.d_bsum, bsum_total * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                     stream) != hipSuccess) { err = "batch download"; return PBN_EDEVICE; }
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) { err = std::string("round sync: ") + hipGetErrorString(e); return PBN_EDEVICE; }
+    for (size_t i = 0; i < owners.size(); ++i) {
+        Machine &m = owners[i].run->machines[owners[i].mi];
+        const uint64_t L = owners[i].run->sim->len;
+        if (qs[i].kind == kQueryWindow) m.feed_window(ws.h_win[i], L);
+        else m.feed_batch(ws.h_bsum + owners[i].off, L);
+    }
+    return PBN_OK;
+}
+
+int run_to_completion(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err)
+{
+    for (;;) {
+        bool all = true;
+        for (SimRun *r : runs)
+            if (!r->finished()) { all = false; break; }
+        if (all) return PBN_OK;
+        int rc = run_round(runs, ws, stream, err);
+        if (rc) return rc;
+    }
+}
+
+}  // namespace pbn

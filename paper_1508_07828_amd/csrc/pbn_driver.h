@@ -1,0 +1,122 @@
+// Host control of the method: one state machine per state set (property),
+// and the round loop that serves many simulations with one extension launch
+// and one reduction launch per round.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "pbn_internal.h"
+
+struct pbn_net {
+    pbn::Net net;
+};
+
+namespace pbn {
+
+// Device + pinned host scratch for one round's tables and results.
+struct Workspace {
+    StepItem *d_items = nullptr, *h_items = nullptr;
+    Query *d_queries = nullptr, *h_queries = nullptr;
+    WindowResult *d_win = nullptr, *h_win = nullptr;
+    int32_t *d_bsum = nullptr, *h_bsum = nullptr;
+    size_t cap_items = 0, cap_q = 0, cap_bsum = 0;
+    int ensure(size_t items, size_t queries, size_t bsum, std::string &err);
+    void release();
+    ~Workspace() { release(); }
+};
+
+// What a state machine needs next: a window or batch query on its property,
+// served once the chains hold need_len positions.
+struct Request {
+    uint32_t kind;              // kQueryWindow / kQueryBatch
+    uint64_t lo, hi, kappa, m;  // window [lo, hi) or m batches of kappa from lo
+    uint64_t need_len;
+};
+
+struct MachineParams {
+    int method;
+    uint32_t omega;
+    uint64_t psi0, cap;
+    double psrf_max, eps, r, conf;
+};
+
+class Machine {
+public:
+    Machine(const MachineParams &p, uint32_t prop);
+    bool done() const { return done_; }
+    const Request &request() const { return req_; }
+    uint32_t prop() const { return prop_; }
+    void feed_window(const WindowResult &w, uint64_t chain_len);
+    void feed_batch(const int32_t *bsum, uint64_t chain_len);
+    const pbn_result &result() const { return res_; }
+
+private:
+    enum State { kGR, kTwoState, kSkartSkew, kSkartRandomness, kSkartCI };
+    void ask_window(uint64_t lo, uint64_t hi);
+    void ask_batch();
+    void not_converged(uint64_t chain_len);
+    void finish_two_state(int64_t T1);
+    void skart_ci(const int32_t *bsum, uint64_t chain_len);
+
+    MachineParams P_;
+    uint32_t prop_;
+    State st_ = kGR;
+    bool done_ = false;
+    Request req_{};
+    pbn_result res_{};
+    double z_ = 0.0;
+    uint64_t psi_ = 0, psi_gr_ = 0, n_ = 0, N_ = 0;
+    double a_ = 0.0, b_ = 0.0;
+    // Skart-P
+    uint64_t base_ = 0, kappa_ = 0, p_ = 0;
+    int tries_ = 0;
+};
+
+}  // namespace pbn
+
+struct pbn_sim {
+    pbn::Net net;
+    uint32_t omega = 0, max_props = 0, nprops = 0;
+    uint64_t seed = 0, max_len = 0, words_cap = 0;
+    uint8_t *dbuf = nullptr;
+    size_t dbytes = 0;
+    hipStream_t stream = nullptr;
+    pbn::DevSim desc{};
+    pbn::DevSim *d_desc = nullptr;
+    uint64_t len = 0, t_done = 0;
+    pbn::Workspace ws;
+};
+
+namespace pbn {
+
+size_t sim_bytes(const Net &net, uint32_t omega, uint32_t max_props, uint64_t max_len);
+int sim_setup(pbn_sim *sim, const Net &net, uint32_t omega, uint64_t seed, uint32_t max_props,
+              uint64_t max_len, void *dev_buf, size_t dev_bytes, hipStream_t stream, std::string &err);
+int sim_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops, std::string &err);
+// Append the step items that extend sim by `steps` recorded positions.
+void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin,
+                      std::vector<StepItem> &items);
+
+// A simulation together with the machines of its state sets.
+struct SimRun {
+    pbn_sim *sim = nullptr;
+    std::vector<Machine> machines;
+    bool finished() const;
+};
+
+MachineParams make_params(const pbn_sim *sim, const pbn_opts *opts, double r, double conf);
+
+// One round over all runs: extension launch for the runs that wait for
+// positions, reduction launch for every ready request, one synchronisation.
+int run_round(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err);
+// Rounds until every run is finished.
+int run_to_completion(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err);
+
+// Launch step items for several sims (sorted by cost) on stream.
+int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream, std::string &err);
+
+}  // namespace pbn

@@ -1,0 +1,96 @@
+// Internal structures of libpbnssa shared by the host runtime and the kernels.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pbnssa.h"
+
+namespace pbn {
+
+constexpr uint32_t kTagPert = 0, kTagSel = 2, kTagInit = 4;
+constexpr uint32_t kMaxProps = PBN_MAX_PROPS;
+constexpr uint32_t kMaxTerms = PBN_MAX_TERMS;
+
+// Compiled network (host copy; uploaded verbatim as one blob).
+//   nd_first[n+1]  first function of node i (l(i) = nd_first[i+1]-nd_first[i])
+//   fn_thr[F]      cumulative selection threshold T_j (unused for the last one)
+//   fn_desc[F]     k | (offset of its parents in par[]) << 5
+//   fn_tt[F]       truth table for k <= 5, else word offset into tt_ext
+//   par[]          parent node ids (u16)
+//   tt_ext[]       truth tables of functions with k > 5 (ceil(2^k/32) words)
+struct Net {
+    uint32_t n = 0, W = 0, F = 0, p_thr = 0, max_k = 0, max_l = 0;
+    double p = 0.0, density = 0.0;
+    std::vector<uint32_t> nd_first, fn_thr, fn_desc, fn_tt, tt_ext;
+    std::vector<uint16_t> par;
+    // blob layout (byte offsets)
+    size_t off_nd_first = 0, off_fn_thr = 0, off_fn_desc = 0, off_fn_tt = 0, off_tt_ext = 0,
+           off_par = 0, blob_bytes = 0;
+    std::vector<uint8_t> blob;
+};
+
+int parse_and_compile(const char *text, size_t len, Net &out, std::string &err);
+
+// Device-side description of one simulation (lives in the simulation's device
+// buffer; kernels receive its device address).
+struct DevSim {
+    const uint32_t *nd_first;
+    const uint32_t *fn_thr;
+    const uint32_t *fn_desc;
+    const uint32_t *fn_tt;
+    const uint32_t *tt_ext;
+    const uint16_t *par;
+    uint32_t *state;            // [W][omega]
+    uint32_t *bits;             // [max_props][words_cap][omega]
+    uint64_t words_cap;
+    uint32_t n, W, p_thr, omega;
+    uint32_t key0, key1;
+    uint32_t nprops, nterms;
+    uint32_t prop_off[kMaxProps + 1];
+    uint32_t term_word[kMaxTerms];
+    uint32_t term_mask[kMaxTerms];
+    uint32_t term_val[kMaxTerms];
+};
+
+// One unit of step-kernel work: chains [chain0, chain0+nchains) of one sim.
+struct StepItem {
+    const DevSim *sim;
+    uint32_t chain0, nchains;
+    uint32_t t0;                 // transition index of the first transition
+    uint32_t nburn, nrec, thin;  // unrecorded transitions, recorded positions, spacing
+    uint32_t nodes;              // network size (host-side cost and LDS sizing)
+    uint64_t pos0;               // first recorded position (0-based)
+};
+
+enum QueryKind : uint32_t { kQueryWindow = 0, kQueryBatch = 1 };
+
+// One reduction query over a sim's bit-streams.
+struct Query {
+    const DevSim *sim;
+    uint32_t prop, kind;
+    uint64_t lo, hi;             // window [lo, hi) (0-based positions)
+    uint64_t kappa, m;           // batch query: m batches of kappa from lo
+    uint64_t out_off;            // batch query: output offset (int32 units)
+};
+
+// Results of a window query.
+struct WindowResult {
+    int64_t T1, T2, n00, n01, n10, n11, pad0, pad1;
+};
+
+// ------------------------------------------------------------ launches (.hip)
+int launch_init(const DevSim *dsim, uint32_t omega, uint32_t W, void *stream, std::string &err);
+int launch_step(const StepItem *d_items, uint32_t nitems, uint32_t max_W, void *stream,
+                std::string &err);
+int launch_reduce(const Query *d_queries, uint32_t nq, WindowResult *d_win, int32_t *d_bsum,
+                  void *stream, std::string &err);
+
+// ------------------------------------------------------------ statistics
+double normal_quantile(double p);
+double t_quantile(double p, double nu);
+double rhat_from_sums(int64_t T1, int64_t T2, uint64_t omega, uint64_t psi, bool *defined);
+
+}  // namespace pbn

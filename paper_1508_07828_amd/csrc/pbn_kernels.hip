@@ -1,0 +1,406 @@
+// Device kernels of libpbnssa for gfx950 (CDNA4, wave64).
+//
+//   k_init     s(0) of every chain from the Philox stream (tag 4)
+//   k_step     trajectories: each lane advances one chain; one 64-lane block
+//              per (simulation, 64-chain slice) work item, so one launch serves
+//              any number of simulations of different sizes (batched form)
+//   k_reduce   window aggregates (popcount sums, sums of squares, pair counts)
+//              and Skart batch sums over the recorded indicator bit-streams
+//
+// Everything on the device is integer arithmetic; FP64 only happens on the
+// host from the exact aggregates.
+#include <hip/hip_runtime.h>
+
+#include "pbn_internal.h"
+
+namespace pbn {
+
+// ------------------------------------------------------------------ Philox
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32->64 products,
+// key bumped by the Weyl constants between rounds.
+struct Key {
+    uint32_t k0, k1;
+};
+
+__device__ __forceinline__ void philox4(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        Key key, uint32_t out[4])
+{
+    uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+__device__ __forceinline__ uint32_t pick4(const uint32_t w[4], uint32_t j)
+{
+    uint32_t v = w[0];
+    v = (j == 1) ? w[1] : v;
+    v = (j == 2) ? w[2] : v;
+    v = (j == 3) ? w[3] : v;
+    return v;
+}
+
+// Low 24 bits of the refinement word of node i (tag + 1).
+__device__ __forceinline__ uint32_t refine24(Key key, uint32_t t, uint32_t c, uint32_t i, uint32_t tag)
+{
+    uint32_t w[4];
+    philox4(t, c, i >> 2, tag + 1, key, w);
+    return pick4(w, i & 3) & 0xFFFFFFu;
+}
+
+// Any byte of x strictly below m (1 <= m <= 128): classic SWAR test.
+__device__ __forceinline__ bool has_byte_below(uint32_t x, uint32_t m)
+{
+    return ((x - 0x01010101u * m) & ~x & 0x80808080u) != 0;
+}
+
+// ------------------------------------------------------------------ init
+__global__ void k_init(const DevSim *__restrict__ sim)
+{
+    const uint32_t omega = sim->omega, W = sim->W, n = sim->n;
+    const uint32_t quads = (W + 3) / 4;
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= omega * quads) return;
+    const uint32_t c = gid % omega, q = gid / omega;
+    uint32_t w4[4];
+    philox4(0u, c, q, kTagInit, Key{sim->key0, sim->key1}, w4);
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) {
+        uint32_t w = 4 * q + j;
+        if (w >= W) break;
+        uint32_t v = w4[j];
+        uint32_t nb = n - 32 * w;
+        if (nb < 32) v &= (1u << nb) - 1u;
+        sim->state[(size_t)w * omega + c] = v;
+    }
+}
+
+// ------------------------------------------------------------------ step
+
+// Perturbation pass over all nodes of one chain at transition t.  With
+// APPLY = false it counts perturbed nodes and remembers the first four; with
+// APPLY = true it XORs every perturbed node into the state row.
+template <bool APPLY>
+__device__ __forceinline__ uint32_t perturb_scan(const DevSim &sm, Key key, uint32_t t, uint32_t c,
+                                                 uint32_t *row, uint32_t slot[4])
+{
+    const uint32_t n = sm.n, p_thr = sm.p_thr;
+    const uint32_t thr8 = p_thr >> 24;
+    const bool swar = thr8 < 127u;
+    uint32_t nf = 0;
+    const uint32_t nblk = (n + 15) >> 4;
+    for (uint32_t b = 0; b < nblk; ++b) {
+        uint32_t w[4];
+        philox4(t, c, b, kTagPert, key, w);
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+            const uint32_t node0 = b * 16 + q * 4;
+            if (node0 >= n) break;
+            const uint32_t nvalid = min(4u, n - node0);
+            uint32_t x = w[q];
+            if (nvalid < 4) x |= 0xFFFFFFFFu << (8 * nvalid);
+            if (swar && !has_byte_below(x, thr8 + 1)) continue;
+            for (uint32_t bb = 0; bb < nvalid; ++bb) {
+                const uint32_t byte = (x >> (8 * bb)) & 0xFFu;
+                bool g;
+                if (byte != thr8) {
+                    g = byte < thr8;
+                } else {
+                    const uint32_t i = node0 + bb;
+                    g = ((byte << 24) | refine24(key, t, c, i, kTagPert)) < p_thr;
+                }
+                if (g) {
+                    const uint32_t i = node0 + bb;
+                    if (APPLY) {
+                        row[i >> 5] ^= 1u << (i & 31);
+                    } else {
+                        if (nf == 0) slot[0] = i;
+                        else if (nf == 1) slot[1] = i;
+                        else if (nf == 2) slot[2] = i;
+                        else if (nf == 3) slot[3] = i;
+                    }
+                    ++nf;
+                }
+            }
+        }
+    }
+    return nf;
+}
+
+// Synchronous update with one predictor drawn per node: reads cur, writes nxt.
+__device__ __forceinline__ void function_update(const DevSim &sm, Key key, uint32_t t, uint32_t c,
+                                                const uint32_t *cur, uint32_t *nxt)
+{
+    const uint32_t n = sm.n;
+    const uint32_t *__restrict__ nd_first = sm.nd_first;
+    const uint32_t *__restrict__ fn_thr = sm.fn_thr;
+    const uint32_t *__restrict__ fn_desc = sm.fn_desc;
+    const uint32_t *__restrict__ fn_tt = sm.fn_tt;
+    const uint32_t *__restrict__ tt_ext = sm.tt_ext;
+    const uint16_t *__restrict__ par = sm.par;
+    uint32_t sw[4] = {0, 0, 0, 0};
+    uint32_t have_blk = 0xFFFFFFFFu;
+    uint32_t acc = 0;
+    uint32_t first = nd_first[0];
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint32_t next_first = nd_first[i + 1];
+        const uint32_t l = next_first - first;
+        uint32_t j = l - 1;
+        if (l > 1) {
+            const uint32_t blk = i >> 4;
+            if (blk != have_blk) {
+                philox4(t, c, blk, kTagSel, key, sw);
+                have_blk = blk;
+            }
+            const uint32_t byte = (pick4(sw, (i >> 2) & 3) >> (8 * (i & 3))) & 0xFFu;
+            uint32_t u = 0;
+            bool have_u = false;
+            for (uint32_t jj = 0; jj + 1 < l; ++jj) {
+                const uint32_t T = fn_thr[first + jj];
+                const uint32_t tb = T >> 24;
+                bool lt;
+                if (byte != tb) {
+                    lt = byte < tb;
+                } else {
+                    if (!have_u) {
+                        u = (byte << 24) | refine24(key, t, c, i, kTagSel);
+                        have_u = true;
+                    }
+                    lt = u < T;
+                }
+                if (lt) { j = jj; break; }
+            }
+        }
+        const uint32_t f = first + j;
+        const uint32_t desc = fn_desc[f];
+        const uint32_t k = desc & 31u, po = desc >> 5;
+        uint32_t idx = 0;
+        for (uint32_t m = 0; m < k; ++m) {
+            const uint32_t v = par[po + m];
+            idx |= ((cur[v >> 5] >> (v & 31)) & 1u) << m;
+        }
+        uint32_t bit;
+        if (k <= 5) bit = (fn_tt[f] >> idx) & 1u;
+        else bit = (tt_ext[fn_tt[f] + (idx >> 5)] >> (idx & 31)) & 1u;
+        acc |= bit << (i & 31);
+        if ((i & 31) == 31 || i + 1 == n) {
+            nxt[i >> 5] = acc;
+            acc = 0;
+        }
+        first = next_first;
+    }
+}
+
+__device__ __forceinline__ uint32_t prop_value(const DevSim &sm, uint32_t q, const uint32_t *row)
+{
+    uint32_t ok = 1;
+    for (uint32_t m = sm.prop_off[q]; m < sm.prop_off[q + 1]; ++m)
+        ok &= ((row[sm.term_word[m]] & sm.term_mask[m]) == sm.term_val[m]) ? 1u : 0u;
+    return ok;
+}
+
+extern __shared__ uint32_t lds_rows[];
+
+// One 64-lane block per work item; lane = chain.  Two LDS rows per lane
+// (current and next state) of stride S words (S odd: conflict-free rows).
+__global__ void __launch_bounds__(64) k_step(const StepItem *__restrict__ items, uint32_t S)
+{
+    const StepItem it = items[blockIdx.x];
+    const DevSim &sm = *it.sim;
+    const uint32_t lane = threadIdx.x;
+    if (lane >= it.nchains) return;
+    const uint32_t c = it.chain0 + lane;
+    const uint32_t W = sm.W, omega = sm.omega, nprops = sm.nprops;
+    const Key key{sm.key0, sm.key1};
+    uint32_t *cur = lds_rows + lane * S;
+    uint32_t *nxt = lds_rows + (64 + lane) * S;
+    for (uint32_t w = 0; w < W; ++w) cur[w] = sm.state[(size_t)w * omega + c];
+
+    uint32_t acc[kMaxProps];
+    uint64_t pos = it.pos0;
+#pragma unroll
+    for (uint32_t q = 0; q < kMaxProps; ++q) {
+        acc[q] = 0;
+        if (q < nprops && it.nrec > 0 && (pos & 31)) {
+            const uint32_t old = sm.bits[((size_t)q * sm.words_cap + (pos >> 5)) * omega + c];
+            acc[q] = old & ((1u << (pos & 31)) - 1u);
+        }
+    }
+
+    const uint32_t total = it.nburn + it.nrec * it.thin;
+    uint32_t since = 0;
+    for (uint32_t s = 0; s < total; ++s) {
+        const uint32_t t = it.t0 + s;
+        uint32_t slot[4];
+        const uint32_t nf = perturb_scan<false>(sm, key, t, c, cur, slot);
+        if (nf > 0) {
+            if (nf <= 4) {
+                cur[slot[0] >> 5] ^= 1u << (slot[0] & 31);
+                if (nf > 1) cur[slot[1] >> 5] ^= 1u << (slot[1] & 31);
+                if (nf > 2) cur[slot[2] >> 5] ^= 1u << (slot[2] & 31);
+                if (nf > 3) cur[slot[3] >> 5] ^= 1u << (slot[3] & 31);
+            } else {
+                perturb_scan<true>(sm, key, t, c, cur, slot);
+            }
+        } else {
+            function_update(sm, key, t, c, cur, nxt);
+            uint32_t *tmp = cur; cur = nxt; nxt = tmp;
+        }
+        if (s >= it.nburn && ++since == it.thin) {
+            since = 0;
+            const uint32_t b = (uint32_t)(pos & 31);
+#pragma unroll
+            for (uint32_t q = 0; q < kMaxProps; ++q)
+                if (q < nprops) acc[q] |= prop_value(sm, q, cur) << b;
+            if (b == 31) {
+#pragma unroll
+                for (uint32_t q = 0; q < kMaxProps; ++q)
+                    if (q < nprops) {
+                        sm.bits[((size_t)q * sm.words_cap + (pos >> 5)) * omega + c] = acc[q];
+                        acc[q] = 0;
+                    }
+            }
+            ++pos;
+        }
+    }
+    if (it.nrec > 0 && (pos & 31)) {
+#pragma unroll
+        for (uint32_t q = 0; q < kMaxProps; ++q)
+            if (q < nprops) sm.bits[((size_t)q * sm.words_cap + (pos >> 5)) * omega + c] = acc[q];
+    }
+    for (uint32_t w = 0; w < W; ++w) sm.state[(size_t)w * omega + c] = cur[w];
+}
+
+// ------------------------------------------------------------------ reduce
+
+// Bits [lo, hi) of a word starting at position 32*wi, as a mask.
+__device__ __forceinline__ uint32_t range_mask(uint64_t wi, uint64_t lo, uint64_t hi)
+{
+    const uint64_t base = wi * 32;
+    const uint64_t a = lo > base ? lo - base : 0;
+    const uint64_t b = hi - base >= 32 ? 32 : hi - base;
+    if (b <= a) return 0;
+    const uint32_t upto = b == 32 ? 0xFFFFFFFFu : ((1u << b) - 1u);
+    return upto & ~((1u << a) - 1u);
+}
+
+__device__ __forceinline__ int64_t block_sum(int64_t v, int64_t *scratch)
+{
+    // wave64 reduction then across the 4 waves of a 256-thread block
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) scratch[wave] = v;
+    __syncthreads();
+    int64_t tot = 0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += scratch[w];
+    __syncthreads();
+    return tot;
+}
+
+// One 256-thread block per query.
+__global__ void __launch_bounds__(256) k_reduce(const Query *__restrict__ qs, WindowResult *__restrict__ win,
+                                                int32_t *__restrict__ bsum)
+{
+    __shared__ int64_t scratch[8];
+    const Query qy = qs[blockIdx.x];
+    const DevSim &sm = *qy.sim;
+    const uint32_t omega = sm.omega;
+    const uint32_t *bits = sm.bits + (size_t)qy.prop * sm.words_cap * omega;
+    if (qy.kind == kQueryWindow) {
+        int64_t T1 = 0, T2 = 0, n01 = 0, n10 = 0, n11 = 0;
+        const uint64_t lo = qy.lo, hi = qy.hi;
+        const uint64_t w0 = lo >> 5, w1 = (hi + 31) >> 5;
+        for (uint32_t c = threadIdx.x; c < omega; c += blockDim.x) {
+            int64_t S = 0;
+            uint32_t x = w0 < w1 ? bits[w0 * omega + c] : 0u;
+            for (uint64_t wi = w0; wi < w1; ++wi) {
+                const uint32_t nx = (wi + 1 < w1) ? bits[(wi + 1) * omega + c] : 0u;
+                const uint32_t m = range_mask(wi, lo, hi);
+                S += __popc(x & m);
+                // pair (l, l+1) counted at l when both lie in [lo, hi)
+                const uint32_t pm = range_mask(wi, lo, hi - 1 > lo ? hi - 1 : lo);
+                const uint32_t y = (x >> 1) | (nx << 31);
+                n11 += __popc(x & y & pm);
+                n10 += __popc(x & ~y & pm);
+                n01 += __popc(~x & y & pm);
+                x = nx;
+            }
+            T1 += S;
+            T2 += S * S;
+        }
+        T1 = block_sum(T1, scratch);
+        T2 = block_sum(T2, scratch);
+        n01 = block_sum(n01, scratch);
+        n10 = block_sum(n10, scratch);
+        n11 = block_sum(n11, scratch);
+        if (threadIdx.x == 0) {
+            const int64_t pairs = hi > lo ? (int64_t)(hi - lo - 1) * omega : 0;
+            WindowResult r;
+            r.T1 = T1; r.T2 = T2; r.n01 = n01; r.n10 = n10; r.n11 = n11;
+            r.n00 = pairs - n01 - n10 - n11;
+            r.pad0 = r.pad1 = 0;
+            win[blockIdx.x] = r;
+        }
+    } else {
+        const uint64_t m = qy.m, kappa = qy.kappa;
+        const uint64_t total = (uint64_t)omega * m;
+        for (uint64_t e = threadIdx.x; e < total; e += blockDim.x) {
+            const uint32_t c = (uint32_t)(e / m);
+            const uint64_t b = e % m;
+            const uint64_t lo = qy.lo + b * kappa, hi = lo + kappa;
+            int32_t S = 0;
+            for (uint64_t wi = lo >> 5; wi < ((hi + 31) >> 5); ++wi)
+                S += __popc(bits[wi * omega + c] & range_mask(wi, lo, hi));
+            bsum[qy.out_off + e] = S;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launches
+
+static int check(hipError_t e, const char *what, std::string &err)
+{
+    if (e == hipSuccess) return PBN_OK;
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return PBN_EDEVICE;
+}
+
+int launch_init(const DevSim *dsim, uint32_t omega, uint32_t W, void *stream, std::string &err)
+{
+    const uint32_t total = omega * ((W + 3) / 4);
+    hipLaunchKernelGGL(k_init, dim3((total + 255) / 256), dim3(256), 0, (hipStream_t)stream, dsim);
+    return check(hipGetLastError(), "k_init launch", err);
+}
+
+int launch_step(const StepItem *d_items, uint32_t nitems, uint32_t max_W, void *stream, std::string &err)
+{
+    if (nitems == 0) return PBN_OK;
+    const uint32_t S = max_W | 1u;
+    const size_t lds = (size_t)2 * 64 * S * 4;
+    if (lds > 160 * 1024) {
+        err = "state rows exceed LDS";
+        return PBN_ELIMIT;
+    }
+    hipLaunchKernelGGL(k_step, dim3(nitems), dim3(64), lds, (hipStream_t)stream, d_items, S);
+    return check(hipGetLastError(), "k_step launch", err);
+}
+
+int launch_reduce(const Query *d_queries, uint32_t nq, WindowResult *d_win, int32_t *d_bsum, void *stream,
+                  std::string &err)
+{
+    if (nq == 0) return PBN_OK;
+    hipLaunchKernelGGL(k_reduce, dim3(nq), dim3(256), 0, (hipStream_t)stream, d_queries, d_win, d_bsum);
+    return check(hipGetLastError(), "k_reduce launch", err);
+}
+
+}  // namespace pbn

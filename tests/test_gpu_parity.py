@@ -1,0 +1,248 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded inputs.
+
+Bit-exact: initial states, chain states after every extension, recorded
+indicator bits, window sums and pair counts, Skart batch sums, and every
+integer decision of the procedures (psi, n, N, M, kappa, batches, chain
+length, status).  Floating point (R, the estimates, the Skart CI): within
+1e-12 relative, the tolerance stated for this path.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1508_07828_amd as pkg
+import pbnsynth as ps
+from oracle import drivers, stats
+
+pytestmark = pytest.mark.gpu
+
+INT_KEYS = ("status", "psi_gr", "psi", "n", "N", "M", "kappa", "batches", "chain_len")
+FP_KEYS = ("prob", "rhat", "ci_lo", "ci_hi")
+CAP = 1 << 15
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def close(a, b, rel=1e-12):
+    if np.isnan(a) and np.isnan(b):
+        return True
+    return abs(a - b) <= rel * max(1.0, abs(b))
+
+
+def assert_same_result(got, want, tag=""):
+    for k in INT_KEYS:
+        assert got[k] == want[k], (tag, k, got[k], want[k])
+    for k in FP_KEYS:
+        assert close(got[k], want[k]), (tag, k, got[k], want[k])
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pkg.lib()
+    yield
+
+
+def _ragged_net(n=37, p=0.05, seed=5, k_max=7):
+    return ps.small_network(seed, n, l_max=4, k_max=k_max, p=p)
+
+
+CASES = {
+    "tiny": lambda: (ps.tiny().net, 8, ps.tiny().patterns),
+    "medium": lambda: (ps.medium().net, 256, ps.medium().patterns),
+    "ragged_k7_p05": lambda: (_ragged_net(), 100, [((0, 1), (5, 0)), ((36, 1),)]),
+    "high_p": lambda: (_ragged_net(20, 0.6, 9, 4), 70, [((3, 1),)]),
+    "one_node": lambda: (ps.small_network(2, 1, l_max=2, k_max=1, p=0.3), 65, [((0, 1),)]),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_trajectories_bit_exact(case):
+    net, omega, pats = CASES[case]()
+    text = ps.to_text(net)
+    say("trajectories {} n={} omega={}".format(case, net.n, omega))
+    sim = pkg.Simulation(pkg.Network(text), omega, 7828, max_props=len(pats), max_len=4096)
+    sim.reset(pats)
+    ch = oracle.Chains(oracle.Net(text), omega, 7828, pats)
+    assert np.array_equal(sim.read_state(), ch.states)
+    for steps in (37, 100, 63, 1):
+        sim.run(steps)
+        ch.extend(steps)
+        assert np.array_equal(sim.read_state(), ch.states), steps
+    L = ch.length
+    for q in range(len(pats)):
+        assert np.array_equal(sim.read_bits(q, 0, L), ch.bits[q]), q
+    assert sim.position() == (L, L)
+
+
+def test_burn_in_and_thinning():
+    net, omega, pats = CASES["ragged_k7_p05"]()
+    text = ps.to_text(net)
+    say("burn-in/thin")
+    sim = pkg.Simulation(pkg.Network(text), omega, 99, max_props=2, max_len=1024)
+    sim.reset(pats)
+    sim.run(50, burn_in=13, thin=3)
+    ch = oracle.Chains(oracle.Net(text), omega, 99, pats)
+    ch.extend(13 + 150)
+    assert np.array_equal(sim.read_state(), ch.states)
+    idx = 13 + 3 * np.arange(50) + 2
+    for q in range(2):
+        assert np.array_equal(sim.read_bits(q, 0, 50), ch.bits[q][:, idx])
+    assert sim.position() == (50, 163)
+
+
+def test_large_sampled_chains():
+    job = ps.large()
+    text = ps.to_text(job.net)
+    say("large: 8192 chains x 2000 nodes, 24 steps, sampled oracle chains")
+    sim = pkg.Simulation(pkg.Network(text), job.chains, job.seed, max_props=5, max_len=256)
+    sim.reset(job.patterns)
+    init = sim.read_state()
+    sim.run(24)
+    st = sim.read_state()
+    bits = [sim.read_bits(q, 0, 24) for q in range(5)]
+    onet = oracle.Net(text)
+    for c0 in (0, 4031, 8128):
+        ch = oracle.Chains(onet, 64, job.seed, job.patterns, chain0=c0)
+        assert np.array_equal(init[c0:c0 + 64], ch.states)
+        ch.extend(24)
+        assert np.array_equal(st[c0:c0 + 64], ch.states), c0
+        for q in range(5):
+            assert np.array_equal(bits[q][c0:c0 + 64], ch.bits[q]), (c0, q)
+
+
+def test_window_counts_batch_sums_psrf():
+    job = ps.medium()
+    text = ps.to_text(job.net)
+    pats = job.patterns + [((0, 1),)]
+    say("window counts / batch sums / psrf on medium")
+    sim = pkg.Simulation(pkg.Network(text), 256, 31, max_props=2, max_len=2048)
+    sim.reset(pats)
+    sim.run(700)
+    ch = oracle.Chains(oracle.Net(text), 256, 31, pats)
+    ch.extend(700)
+    for q in range(2):
+        x = ch.bits[q].astype(np.int64)
+        for lo, hi in ((0, 700), (5, 6), (31, 33), (64, 128), (100, 613), (699, 700)):
+            got = sim.window_counts(q, lo, hi)
+            S = x[:, lo:hi].sum(axis=1)
+            n00, n01, n10, n11 = stats.transition_counts(x[:, lo:hi])
+            want = dict(T1=int(S.sum()), T2=int((S * S).sum()), n00=n00, n01=n01, n10=n10, n11=n11)
+            assert got == want, (q, lo, hi)
+        for base, kappa, m in ((0, 1, 700), (17, 16, 5), (256, 33, 13)):
+            got = sim.batch_sums(q, base, kappa, m)
+            want = x[:, base: base + kappa * m].reshape(256, m, kappa).sum(axis=2)
+            assert np.array_equal(got, want)
+        for psi in (2, 64, 350):
+            assert close(sim.psrf(q, psi), stats.psrf(x[:, 700 - psi:]))
+
+
+@pytest.mark.parametrize("name", ["tiny", "medium"])
+def test_estimate_two_state(name):
+    job = getattr(ps, name)()
+    text = ps.to_text(job.net)
+    say("estimate two-state " + name)
+    sim = pkg.Simulation(pkg.Network(text), job.chains, job.seed, max_props=1, max_len=CAP)
+    got = sim.estimate(job.patterns, job.r, job.confidence, psrf_max=job.psrf_max)
+    want = drivers.solve(text, job.chains, job.seed, job.patterns, job.r, job.confidence, job.psrf_max, cap=CAP)
+    assert_same_result(got[0], want[0], name)
+
+
+def test_estimate_two_state_seeds_and_reruns():
+    # several seeds and a small psi0 so that Alg. 3's burn-in re-run (M > psi) occurs
+    job = ps.tiny()
+    text = ps.to_text(job.net)
+    net = pkg.Network(text)
+    reruns = 0
+    for seed in range(20):
+        say("tiny seed {}".format(seed))
+        sim = pkg.Simulation(net, 8, seed, max_props=1, max_len=CAP)
+        got = sim.estimate(job.patterns, 0.02, 0.95, psi0=4, psrf_max=1.1)[0]
+        want = drivers.solve(text, 8, seed, job.patterns, 0.02, 0.95, 1.1, psi0=4, cap=CAP)[0]
+        assert_same_result(got, want, seed)
+        reruns += got["psi"] != got["psi_gr"]
+    assert reruns > 0
+
+
+def test_estimate_skart():
+    job = ps.medium()
+    text = ps.to_text(job.net)
+    say("estimate skart on medium network, 64 chains")
+    pats = job.patterns + [((1, 1), (2, 0))]
+    sim = pkg.Simulation(pkg.Network(text), 64, 5, max_props=2, max_len=CAP)
+    got = sim.estimate(pats, 0.01, 0.95, method="skart", psrf_max=1.1)
+    want = drivers.solve(text, 64, 5, pats, 0.01, 0.95, 1.1, method="skart", cap=CAP)
+    for q in range(2):
+        assert_same_result(got[q], want[q], q)
+
+
+def test_multi_property_equals_solo():
+    job = ps.medium()
+    text = ps.to_text(job.net)
+    rng = np.random.default_rng(8)
+    pats = [ps.random_pattern(rng, 100, k) for k in (1, 2, 3, 1)]
+    say("multi-property")
+    sim = pkg.Simulation(pkg.Network(text), 128, 77, max_props=4, max_len=CAP)
+    got = sim.estimate(pats, 0.01, 0.95, psrf_max=1.1)
+    want = drivers.solve(text, 128, 77, pats, 0.01, 0.95, 1.1, cap=CAP)
+    for q in range(4):
+        assert_same_result(got[q], want[q], q)
+    # the shared chains are as long as the longest requirement
+    assert sim.position()[0] == max(w["chain_len"] for w in want)
+
+
+def test_batched_equals_oracle():
+    jobs = sorted(ps.batched(), key=lambda j: j.net.n * j.chains)[:10]
+    say("batched estimate of {} networks".format(len(jobs)))
+    nets = [pkg.Network(ps.to_text(j.net)) for j in jobs]
+    sims = [pkg.Simulation(nt, j.chains, j.seed, max_props=1, max_len=CAP) for nt, j in zip(nets, jobs)]
+    got = pkg.batch_estimate(sims, [j.patterns for j in jobs], [j.r for j in jobs],
+                             [j.confidence for j in jobs], psrf_max=1.1)
+    for j, g in zip(jobs, got):
+        want = drivers.solve(ps.to_text(j.net), j.chains, j.seed, j.patterns, j.r, j.confidence, 1.1, cap=CAP)
+        assert_same_result(g[0], want[0], j.name)
+
+
+def test_server_isolation():
+    jobs = sorted(ps.serving(limit=40), key=lambda j: j.net.n)[:8]
+    say("server with {} requests".format(len(jobs)))
+    nets = [pkg.Network(ps.to_text(j.net)) for j in jobs]
+    need = [nt.sim_bytes(64, 1, CAP) for nt in nets]
+    arena = sum(sorted(need)[-3:]) + (1 << 16)       # room for about three at a time
+    srv = pkg.Server(arena)
+    ids = [srv.submit(nt, 64, j.seed, j.patterns, j.r, j.confidence, max_len=CAP, psrf_max=1.1)
+           for nt, j in zip(nets, jobs)]
+    rounds = 0
+    while True:
+        active, waiting, done = srv.step()
+        rounds += 1
+        assert srv.memory()[0] <= arena
+        if done == len(jobs):
+            break
+        assert rounds < 10000
+    assert srv.memory()[1] <= arena
+    for rid, j in zip(ids, jobs):
+        got = srv.poll(rid)
+        want = drivers.solve(ps.to_text(j.net), 64, j.seed, j.patterns, j.r, j.confidence, 1.1, cap=CAP)
+        assert_same_result(got[0], want[0], j.name)
+
+
+def test_rejects_bad_arguments():
+    net = pkg.Network(ps.to_text(ps.tiny().net))
+    sim = pkg.Simulation(net, 1, 1, max_props=1, max_len=64)
+    with pytest.raises(pkg.PbnError):
+        sim.estimate([((0, 1),)], 0.01, 0.95)          # Gelman-Rubin needs two chains
+    sim2 = pkg.Simulation(net, 4, 1, max_props=1, max_len=64)
+    sim2.reset([((0, 1),)])
+    with pytest.raises(pkg.PbnError):
+        sim2.run(100)                                  # beyond the bit-stream capacity
+    with pytest.raises(pkg.PbnError):
+        sim2.window_counts(0, 0, 10)                   # nothing recorded yet
+    res = sim2.estimate([((0, 1),)], 1e-4, 0.95, psrf_max=1.1)[0]
+    assert res["status"] == pkg.PBN_ENOTCONV           # cap reached before N

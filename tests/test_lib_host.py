@@ -1,0 +1,99 @@
+"""Host-side checks of the HIP library that need no GPU.
+
+* The shared library loads and exports every function include/pbnssa.h declares.
+* Its network compiler agrees with the oracle's parser: same thresholds, same
+  rejections (both written independently from the canonical format).
+* Its quantiles are bit-identical to the oracle's (both evaluate AS 241 and the
+  Cornish-Fisher series in the same order), so sample sizes decided from them
+  agree exactly.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1508_07828_amd as pkg
+import pbnsynth as ps
+from oracle import stats
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def built():
+    if not os.path.exists(pkg.LIB_PATH):
+        from paper_1508_07828_amd import build
+        build.build()
+
+
+def test_exports_match_header():
+    hdr = open(os.path.join(ROOT, "include", "pbnssa.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    names = set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", hdr)) - {"sizeof", "if", "for", "while"}
+    names = {n for n in names if n.startswith("pbn_") or n in ("run_chains", "psrf", "estimate_prob")}
+    assert len(names) >= 25
+    L = pkg.lib()
+    for n in sorted(names):
+        assert hasattr(L, n), n
+    assert set(pkg.EXPORTS) <= names
+
+
+def _nets():
+    yield ps.to_text(ps.tiny().net)
+    yield ps.to_text(ps.medium().net)
+    for s in range(4):
+        yield ps.to_text(ps.small_network(s, 9, l_max=4, k_max=7))
+
+
+def test_thresholds_match_oracle():
+    for text in _nets():
+        a, b = pkg.Network(text), oracle.Net(text)
+        assert a.n == b.n and a.info.p_thr == b.p_thr
+        for i in range(a.n):
+            assert a.thresholds(i) == b.thresholds(i)
+
+
+def test_density_and_sizes():
+    job = ps.medium()
+    net = pkg.Network(ps.to_text(job.net))
+    assert abs(net.info.density - job.net.density()) < 1e-12
+    assert net.info.nfun == job.net.n_functions()
+    assert net.W == (job.net.n + 31) // 32
+    assert net.sim_bytes(256, 1, 1 << 12) > 256 * net.W * 4
+
+
+@pytest.mark.parametrize("bad", [
+    "PBN 2 0.5\nN 0 1\nF 1.0 1 0 2\nN 1 1\nF 0.9 1 0 1\n",
+    "PBN 2 0.5\nN 0 1\nF 1.0 2 1 1 6\nN 1 1\nF 1.0 1 0 1\n",
+    "PBN 2 0.5\nN 0 1\nF 1.0 1 2 2\nN 1 1\nF 1.0 1 0 1\n",
+    "PBN 2 1.5\nN 0 1\nF 1.0 1 1 2\nN 1 1\nF 1.0 1 0 1\n",
+    "PBN 2 0.5\nN 0 1\nF 1.0 1 1 1f\nN 1 1\nF 1.0 1 0 1\n",
+    "PBN 2 0.5\nN 1 1\nF 1.0 1 1 2\nN 0 1\nF 1.0 1 0 1\n",
+    "PBN 2 0.5\nN 0 1\nF 1.0 1 1 2\n",
+    "",
+])
+def test_rejects_like_oracle(bad):
+    with pytest.raises(pkg.PbnError):
+        pkg.Network(bad)
+    with pytest.raises(ValueError):
+        oracle.Net(bad)
+
+
+def test_limits():
+    big_k = "PBN 20 0.5\n" + "".join(
+        "N {} 1\nF 1.0 17 {} 0\n".format(i, " ".join(str(v) for v in range(17))) for i in range(20))
+    with pytest.raises(pkg.PbnError) as e:
+        pkg.Network(big_k)
+    assert e.value.code == pkg.PBN_ELIMIT
+
+
+def test_quantiles_bit_identical():
+    rng = np.random.default_rng(3)
+    ps_ = list(rng.uniform(1e-12, 1 - 1e-12, 2000)) + [0.975, 0.995, 0.8, 0.5, 1e-300, 0.025]
+    for p in ps_:
+        assert pkg.normal_quantile(p) == stats.normal_quantile(p)
+    for nu in (100, 1279, 5000, 8191):
+        for p in (0.975, 0.995, 0.9, 0.025):
+            assert pkg.t_quantile(p, nu) == stats.t_quantile(p, nu)
