@@ -1,0 +1,272 @@
+#!/usr/bin/env python3
+"""Benchmark: PBN node-updates/s, batched vs plain, plus p50/p99 query latency.
+
+One step = one end-to-end solve of the batched workload: 512 random PBNs
+(n log-uniform in 20..2000, 1-3 predictors per node, 1-5 parents, p in
+{1e-3, 1e-4}, 64-1024 chains each), every network estimating P(2-node state
+set) by Gelman-Rubin (R < 1.1) then the parallel two-state method at r = 0.01,
+95% confidence; all networks advance together (one trajectory launch and one
+reduction launch per round).  Inputs (compiled networks, device buffers) are
+resident before the timed region.
+
+Beside the timed line it measures, outside the timed region:
+  * plain: the same solves one network at a time (own launches per network) on a
+    fixed sample of the networks, as node-updates/s;
+  * serving: a Poisson stream (200 requests/s) of queries on PBNs with n
+    log-uniform in 50..5000 through the continuous-batching server, p50/p99
+    latency from arrival to result, and a serial-solve baseline on the first
+    requests of the same trace;
+  * roofline of the trajectory kernel from HIP-event-timed launches;
+  * cpu_baseline: the oracle's simulator on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import pbnsynth as ps  # noqa: E402
+
+METRIC = "PBN node-updates/s (batched vs plain) + p50/p99 query latency at r=0.01"
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz, one 32-bit integer op per lane per clock
+PEAK_INT32_OPS = 256 * 4 * 16 * 2.4e9
+MAX_LEN = 1 << 17
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_sims(pkg, jobs, max_len=MAX_LEN):
+    nets = [pkg.Network(ps.to_text(j.net)) for j in jobs]
+    sims = [pkg.Simulation(nt, j.chains, j.seed, max_props=len(j.patterns), max_len=max_len)
+            for nt, j in zip(nets, jobs)]
+    return nets, sims
+
+
+def batched_step(pkg, sims, jobs):
+    return pkg.batch_estimate(sims, [j.patterns for j in jobs], [j.r for j in jobs],
+                              [j.confidence for j in jobs], psrf_max=1.1)
+
+
+def node_updates_of(sims, jobs):
+    return float(sum(s.position()[1] * j.chains * j.net.n for s, j in zip(sims, jobs)))
+
+
+def run_serving(pkg, torch, seconds, rate, arena_bytes, serial_budget_s=20.0):
+    jobs = ps.serving(duration_s=seconds, rate=rate)
+    log("serving: {} requests over {:.1f} s".format(len(jobs), seconds))
+    nets = [pkg.Network(ps.to_text(j.net)) for j in jobs]
+    srv = pkg.Server(arena_bytes)
+    t0 = time.perf_counter()
+    nxt, ids, finish = 0, {}, {}
+    pkg.profile_reset()
+    rounds = 0
+    while len(finish) < len(jobs):
+        now = time.perf_counter() - t0
+        while nxt < len(jobs) and jobs[nxt].arrival <= now:
+            j = jobs[nxt]
+            ids[nxt] = srv.submit(nets[nxt], j.chains, j.seed, j.patterns, j.r, j.confidence,
+                                  max_len=MAX_LEN, psrf_max=1.1)
+            nxt += 1
+        active, waiting, done = srv.step()
+        rounds += 1
+        if rounds % 50 == 0:
+            log("  round {}: t={:.1f}s submitted {} active {} waiting {} done {}".format(
+                rounds, time.perf_counter() - t0, nxt, active, waiting, done))
+        if done > len(finish):
+            t_now = time.perf_counter() - t0
+            for i in list(ids):
+                if i in finish:
+                    continue
+                if srv.poll(ids[i]) is not None:
+                    finish[i] = t_now
+        if active == 0 and waiting == 0 and nxt < len(jobs):
+            time.sleep(max(0.0, jobs[nxt].arrival - (time.perf_counter() - t0)))
+    wall = time.perf_counter() - t0
+    prof = pkg.profile_read()
+    lat = np.array([finish[i] - jobs[i].arrival for i in range(len(jobs))])
+    results = [srv.poll(ids[i]) for i in range(len(jobs))]
+    _, peak_mem = srv.memory()
+    # serial baseline: the first requests solved one at a time in arrival order
+    # (as many as fit in the time budget)
+    k = 0
+    t_free, serial_lat = 0.0, []
+    t_serial = time.perf_counter()
+    for i in range(len(jobs)):
+        if time.perf_counter() - t_serial > serial_budget_s:
+            break
+        k += 1
+        j = jobs[i]
+        sim = pkg.Simulation(nets[i], j.chains, j.seed, max_props=1, max_len=MAX_LEN)
+        a = time.perf_counter()
+        sim.estimate(j.patterns, j.r, j.confidence, psrf_max=1.1)
+        service = time.perf_counter() - a
+        start = max(j.arrival, t_free)
+        t_free = start + service
+        serial_lat.append(t_free - j.arrival)
+        log("  serial {}: n={} {:.1f} ms".format(i, j.net.n, service * 1e3))
+        del sim
+    serial_lat = np.array(serial_lat)
+    return dict(
+        requests=len(jobs), arrival_rate_per_s=rate, arrival_seconds=seconds, wall_s=wall, rounds=rounds,
+        p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+        queries_per_s=len(jobs) / wall, node_updates_per_s=prof["node_updates"] / wall,
+        not_converged=int(sum(r[0]["status"] != 0 for r in results)),
+        arena_bytes=arena_bytes, arena_peak_bytes=peak_mem,
+        serial_first_k=k, serial_p50_ms=float(np.percentile(serial_lat, 50) * 1e3),
+        serial_p99_ms=float(np.percentile(serial_lat, 99) * 1e3),
+    )
+
+
+def cpu_baseline(jobs, budget_s: float):
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    done_nu, t_used, used = 0.0, 0.0, 0
+    steps = 256
+    for j in jobs:
+        if t_used >= budget_s:
+            break
+        ch = oracle.Chains(oracle.Net(ps.to_text(j.net)), j.chains, j.seed, j.patterns, threads=threads)
+        a = time.perf_counter()
+        ch.extend(steps)
+        t_used += time.perf_counter() - a
+        done_nu += float(steps) * j.chains * j.net.n
+        used += 1
+    return dict(value=done_nu / t_used, unit="node-updates/s", cores=threads, kind="oracle",
+                sample="first {} networks of the batched workload, all their chains, {} recorded steps each "
+                       "(CPU simulator with indicator recording, {} threads over chains, {:.1f} s)".format(
+                           used, steps, threads, t_used))
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--count", type=int, default=512)
+    ap.add_argument("--plain-sample", type=int, default=48)
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build runs every simulation on a single MI355X "
+              "(chains shard by id across GPUs by design, but no multi-GPU path is built)", file=sys.stderr)
+        return 2
+    import torch
+    import paper_1508_07828_amd as pkg
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    pkg.lib()
+
+    jobs = ps.batched(args.count)
+    log("setting up {} networks".format(len(jobs)))
+    nets, sims = make_sims(pkg, jobs)
+    torch.cuda.synchronize()
+
+    for w in range(args.warmup):
+        log("warmup {}".format(w))
+        batched_step(pkg, sims, jobs)
+    torch.cuda.synchronize()
+
+    pkg.profile_enable(True)
+    pkg.profile_reset()
+    times, nus = [], []
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        res = batched_step(pkg, sims, jobs)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - a)
+        nus.append(node_updates_of(sims, jobs))
+        log("step {}: {:.3f} s, {:.3e} node-updates".format(k, times[-1], nus[-1]))
+    prof = pkg.profile_read()
+    pkg.profile_enable(False)
+    total_t = sum(times)
+    value = sum(nus) / total_t
+    nconv = sum(r[0]["status"] != 0 for r in res)
+
+    launches = max(1, prof["launches"])
+    avg_launch_s = prof["kernel_ms"] / launches / 1e3
+    ops_per_launch = prof["alg_ops"] / launches
+    achieved = ops_per_launch / avg_launch_s
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32_OPS / 1e12, "unit": "Tops/s",
+                "frac": achieved / PEAK_INT32_OPS, "traffic": None,
+                "kernel": "k_step", "launches": int(prof["launches"]),
+                "avg_launch_ms": avg_launch_s * 1e3,
+                "kernel_node_updates_per_s": prof["node_updates"] / (prof["kernel_ms"] / 1e3),
+                "philox_evals_per_s": prof["philox_evals"] / (prof["kernel_ms"] / 1e3),
+                "kernel_share_of_step": prof["kernel_ms"] / 1e3 / total_t}
+    tr = os.path.join(ROOT, "profiles", "k_step_traffic.json")
+    if os.path.exists(tr):
+        info = json.load(open(tr))
+        if info.get("kernel_source_sha") == kernel_sha():
+            roofline["traffic"] = info.get("bytes_per_launch")
+
+    plain = None
+    if not args.no_plain:
+        idx = np.random.default_rng(1).choice(len(jobs), size=min(args.plain_sample, len(jobs)), replace=False)
+        sub = [jobs[i] for i in sorted(idx)]
+        _, psims = make_sims(pkg, sub)
+        for s, j in zip(psims, sub):                          # warm each once
+            pass
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for s, j in zip(psims, sub):
+            s.estimate(j.patterns, j.r, j.confidence, psrf_max=1.1)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - a
+        nu = node_updates_of(psims, sub)
+        plain = {"value": nu / tp, "unit": "node-updates/s", "networks": len(sub), "seconds": tp,
+                 "note": "one estimate per network, its own launches and synchronisations per round"}
+        del psims
+        log("plain: {:.3e} node-updates/s over {} networks".format(plain["value"], len(sub)))
+
+    serving = None
+    if not args.no_serve:
+        log("serving")
+        serving = run_serving(pkg, torch, args.serve_seconds, 200.0, 16 << 30)
+        log("serving: p50 {:.1f} ms p99 {:.1f} ms".format(serving["p50_ms"], serving["p99_ms"]))
+
+    cpu = None if args.no_cpu else cpu_baseline(jobs, args.cpu_seconds)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "node-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": total_t / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "batched: {} random PBNs, n log-uniform 20..2000, 1-3 predictors/node, "
+                               "1-5 parents, p in {{1e-3,1e-4}}, 64-1024 chains each; GR R<1.1 then "
+                               "two-state r=0.01 s=0.95 on a 2-node state set".format(len(jobs)),
+                   "networks": len(jobs), "chains_total": int(sum(j.chains for j in jobs)),
+                   "not_converged": int(nconv)},
+        "roofline": roofline,
+        "plain": plain,
+        "batched_vs_plain": (value / plain["value"]) if plain else None,
+        "serving": serving,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    return 0
+
+
+def kernel_sha() -> str:
+    import hashlib
+    src = os.path.join(ROOT, "paper_1508_07828_amd", "csrc", "pbn_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    sys.exit(main())

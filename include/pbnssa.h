@@ -219,6 +219,36 @@ int pbn_server_poll(pbn_server *srv, uint64_t id, int *ready, pbn_result *out);
 /* Bytes of the arena currently in use and the peak so far. */
 int pbn_server_memory(const pbn_server *srv, size_t *in_use, size_t *peak);
 
+/* ---------------------------------------------------------------- profiling */
+
+/* Per-launch timing of the trajectory kernel.  While enabled, every step
+ * launch is bracketed by HIP events recorded on the stream it runs on; the
+ * read call waits for the recorded events and returns the totals since the
+ * last reset.  alg_ops counts the algorithmic 32-bit integer operations of the
+ * launched chain-steps (Philox4x32-10 evaluations at 100 operations each, one
+ * comparison per uniform draw, and for function updates the selection
+ * comparisons, two operations per parent bit gathered and one per truth-table
+ * lookup), taken as expectations over the network's structure and p. */
+typedef struct {
+    uint64_t launches;
+    double kernel_ms;            /* sum of event-timed launch durations      */
+    double chain_steps;          /* transitions x chains                     */
+    double node_updates;         /* chain_steps x n                          */
+    double alg_ops;              /* see above                                */
+    double philox_evals;         /* expected Philox4x32-10 evaluations       */
+} pbn_profile;
+
+int pbn_profile_enable(int on);
+/* Trajectory-kernel selection for subsequent launches: mode 0 = automatic
+ * (bit-sliced kernel when every predictor has at most 6 parents and the
+ * bit-sliced state fits in LDS, else lane-per-chain), 1 = lane-per-chain only,
+ * 2 = bit-sliced where possible; waves = waves sharing one 64-chain block in
+ * the bit-sliced kernel (0 = chosen from n, else 1, 2 or 4).  Results do not
+ * depend on the choice. */
+int pbn_set_kernel(int mode, uint32_t waves);
+int pbn_profile_read(pbn_profile *out);
+int pbn_profile_reset(void);
+
 /* ---------------------------------------------------------------- misc */
 
 /* Phi^{-1}(p) (AS 241) and the Student-t quantile used by the statistics. */

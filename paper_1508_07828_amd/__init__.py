@@ -27,7 +27,7 @@ EXPORTS = (
     "pbn_sim_read_state", "pbn_sim_read_bits", "pbn_sim_position", "pbn_sim_sync", "estimate_prob",
     "pbn_batch_run", "pbn_batch_estimate", "pbn_server_create", "pbn_server_free", "pbn_server_submit",
     "pbn_server_step", "pbn_server_poll", "pbn_server_memory", "pbn_normal_quantile", "pbn_t_quantile",
-    "pbn_last_error",
+    "pbn_last_error", "pbn_profile_enable", "pbn_profile_read", "pbn_profile_reset", "pbn_set_kernel",
 )
 
 
@@ -62,6 +62,14 @@ class NetInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint32), ("W", ctypes.c_uint32), ("nfun", ctypes.c_uint32),
                 ("p_thr", ctypes.c_uint32), ("max_k", ctypes.c_uint32), ("max_l", ctypes.c_uint32),
                 ("blob_bytes", ctypes.c_uint64), ("density", ctypes.c_double)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64), ("kernel_ms", ctypes.c_double), ("chain_steps", ctypes.c_double),
+                ("node_updates", ctypes.c_double), ("alg_ops", ctypes.c_double), ("philox_evals", ctypes.c_double)]
+
+    def as_dict(self) -> Dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Counts(ctypes.Structure):
@@ -113,6 +121,10 @@ def lib():
         "pbn_normal_quantile": (dbl, [dbl]),
         "pbn_t_quantile": (dbl, [dbl, dbl]),
         "pbn_last_error": (ctypes.c_char_p, []),
+        "pbn_profile_enable": (i32, [i32]),
+        "pbn_profile_read": (i32, [ctypes.POINTER(Profile)]),
+        "pbn_profile_reset": (i32, []),
+        "pbn_set_kernel": (i32, [i32, u32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -133,6 +145,26 @@ def normal_quantile(p: float) -> float:
 
 def t_quantile(p: float, nu: float) -> float:
     return float(lib().pbn_t_quantile(p, nu))
+
+
+def set_kernel(mode: str = "auto", waves: int = 0) -> None:
+    """Trajectory-kernel choice: "auto", "lane" (lane per chain) or "bitsliced"."""
+    _check(lib().pbn_set_kernel({"auto": 0, "lane": 1, "bitsliced": 2}[mode], waves))
+
+
+def profile_enable(on: bool = True) -> None:
+    _check(lib().pbn_profile_enable(1 if on else 0))
+
+
+def profile_reset() -> None:
+    _check(lib().pbn_profile_reset())
+
+
+def profile_read() -> Dict:
+    """Totals of the event-timed trajectory-kernel launches since the last reset."""
+    p = Profile()
+    _check(lib().pbn_profile_read(ctypes.byref(p)))
+    return p.as_dict()
 
 
 # ------------------------------------------------------------ patterns

@@ -498,6 +498,34 @@ int pbn_server_poll(pbn_server *srv, uint64_t id, int *ready, pbn_result *out)
     return PBN_OK;
 }
 
+int pbn_set_kernel(int mode, uint32_t waves)
+{
+    if (mode < 0 || mode > 2 || (waves != 0 && waves != 1 && waves != 2 && waves != 4))
+        return fail(PBN_EINVAL, "mode must be 0..2 and waves 0, 1, 2 or 4");
+    pbn::set_kernel_mode(mode, waves);
+    return PBN_OK;
+}
+
+int pbn_profile_enable(int on)
+{
+    pbn::profile_set(on != 0);
+    return PBN_OK;
+}
+
+int pbn_profile_read(pbn_profile *out)
+{
+    if (!out) return fail(PBN_EINVAL, "null argument");
+    std::string err;
+    int rc = pbn::profile_collect(out, err);
+    return rc ? fail(rc, err) : PBN_OK;
+}
+
+int pbn_profile_reset(void)
+{
+    pbn::profile_clear();
+    return PBN_OK;
+}
+
 int pbn_server_memory(const pbn_server *srv, size_t *in_use, size_t *peak)
 {
     if (!srv) return fail(PBN_EINVAL, "null argument");

@@ -412,6 +412,19 @@ int sim_setup(pbn_sim *sim, const Net &net, uint32_t omega, uint64_t seed, uint3
     d.key0 = (uint32_t)seed;
     d.key1 = (uint32_t)(seed >> 32);
     d.nprops = 0;
+    d.nd_meta = (const uint32_t *)(blob + net.off_nd_meta);
+    d.nd_tb = (const uint32_t *)(blob + net.off_nd_tb);
+    d.blk_sel = (const uint32_t *)(blob + net.off_blk_sel);
+    d.fs_node = (const uint32_t *)(blob + net.off_fs_node);
+    d.fs_tt_lo = (const uint32_t *)(blob + net.off_fs_tt_lo);
+    d.fs_tt_hi = (const uint32_t *)(blob + net.off_fs_tt_hi);
+    d.fs_mlo = (const uint32_t *)(blob + net.off_fs_mlo);
+    d.fs_mhi = (const uint32_t *)(blob + net.off_fs_mhi);
+    d.fg_K = (const uint32_t *)(blob + net.off_fg_K);
+    d.fs_par = (const uint16_t *)(blob + net.off_fs_par);
+    d.F_pad = net.F_pad;
+    d.msel_total = net.msel_total;
+    d.nblk = net.nblk;
     if (hipMemcpyAsync(blob, net.blob.data(), net.blob_bytes, hipMemcpyHostToDevice, stream) != hipSuccess) {
         err = "blob upload";
         return PBN_EDEVICE;
@@ -453,6 +466,18 @@ int sim_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops, std::stri
         }
         d.prop_off[q + 1] = nt;
     }
+    // the same sets as (node, value) terms for the bit-sliced kernel
+    uint32_t nn = 0;
+    d.pn_off[0] = 0;
+    for (uint32_t q = 0; q < nprops; ++q) {
+        for (uint32_t m = 0; m < props[q].nterms; ++m) {
+            if (nn >= kMaxTerms) { err = "too many state-set terms"; return PBN_ELIMIT; }
+            d.pn_node[nn] = props[q].node[m];
+            d.pn_val[nn] = props[q].val[m] ? 1u : 0u;
+            ++nn;
+        }
+        d.pn_off[q + 1] = nn;
+    }
     d.nprops = nprops;
     d.nterms = nt;
     sim->nprops = nprops;
@@ -481,35 +506,233 @@ void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t t
         it.thin = thin;
         it.pos0 = sim->len;
         it.nodes = sim->net.n;
+        it.ops_per_step = (float)sim->net.ops_per_step;
+        it.philox_per_step = (float)sim->net.philox_per_step;
+        choose_kernel(sim->net, it);
         items.push_back(it);
     }
     sim->t_done += burn_in + steps * thin;
     sim->len += steps;
 }
 
+// Kernel choice per item: the bit-sliced kernel when every predictor has
+// k <= 6 and its LDS fits, with 1, 2 or 4 waves sharing one 64-chain block as n
+// grows (shorter critical path per transition); the lane-per-chain kernel
+// otherwise.  kernel_mode forces one of them (testing and tuning).
+namespace {
+int g_kernel_mode = 0;     // 0 auto, 1 lane-per-chain, 2 bit-sliced
+uint32_t g_waves_override = 0;
+}  // namespace
+
+void set_kernel_mode(int mode, uint32_t waves)
+{
+    g_kernel_mode = mode;
+    g_waves_override = waves;
+}
+
+void choose_kernel(const Net &net, StepItem &it)
+{
+    it.kernel = 0;
+    it.lds = 0;
+    if (g_kernel_mode == 1 || !net.bitsliced) return;
+    uint32_t G = net.n <= 256 ? 1 : (net.n <= 1024 ? 2 : 4);
+    if (g_waves_override) G = g_waves_override;
+    const size_t lds = bs_lds_bytes(net.n, net.msel_total, G);
+    if (lds > 160 * 1024) return;
+    it.kernel = G;
+    it.lds = (uint32_t)lds;
+}
+
+namespace {
+
+// Streams for concurrent launch groups (default priority, non-blocking).
+struct StreamPool {
+    static constexpr int kN = 4;
+    hipStream_t s[kN] = {};
+    hipEvent_t fork = nullptr, join[kN] = {};
+    bool ready = false;
+    int init(std::string &err)
+    {
+        if (ready) return PBN_OK;
+        for (int i = 0; i < kN; ++i) {
+            if (hipStreamCreateWithFlags(&s[i], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&join[i], hipEventDisableTiming) != hipSuccess) {
+                err = "stream pool";
+                return PBN_EDEVICE;
+            }
+        }
+        if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) { err = "stream pool"; return PBN_EDEVICE; }
+        ready = true;
+        return PBN_OK;
+    }
+};
+StreamPool &stream_pool()
+{
+    static StreamPool p;
+    return p;
+}
+
+uint32_t lds_class(uint32_t lds)
+{
+    static const uint32_t cls[] = {8u << 10, 16u << 10, 24u << 10, 32u << 10, 48u << 10, 64u << 10,
+                                   96u << 10, 128u << 10, 160u << 10};
+    for (uint32_t c : cls)
+        if (lds <= c) return c;
+    return lds;
+}
+
+}  // namespace
+
 int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream, std::string &err)
 {
     if (items.empty()) return PBN_OK;
-    // longest items first: the hardware dispatches blocks roughly in order
-    std::vector<std::pair<double, size_t>> order(items.size());
-    uint32_t maxW = 1;
     int rc = ws.ensure(items.size(), 0, 0, err);
     if (rc) return rc;
-    // cost ~ transitions x nodes
+    // groups of equal (kernel, LDS class); inside a group the longest items
+    // first, since the hardware dispatches blocks roughly in order
+    struct Key { uint32_t kernel, cls; double cost; size_t idx; };
+    std::vector<Key> keys(items.size());
     for (size_t i = 0; i < items.size(); ++i) {
         const StepItem &it = items[i];
-        order[i].second = i;
-        order[i].first = -(double)(it.nburn + (uint64_t)it.nrec * it.thin) * (double)it.nodes;
-        maxW = std::max(maxW, (uint32_t)(it.nodes + 31) / 32);
+        keys[i] = Key{it.kernel, it.kernel ? lds_class(it.lds) : 0u,
+                      (double)(it.nburn + (uint64_t)it.nrec * it.thin) * (double)it.nodes, i};
     }
-    std::stable_sort(order.begin(), order.end());
-    for (size_t i = 0; i < items.size(); ++i) ws.h_items[i] = items[order[i].second];
+    std::stable_sort(keys.begin(), keys.end(), [](const Key &a, const Key &b) {
+        if (a.kernel != b.kernel) return a.kernel < b.kernel;
+        if (a.cls != b.cls) return a.cls < b.cls;
+        return a.cost > b.cost;
+    });
+    struct Group { size_t first, count; uint32_t kernel, lds, maxW; double cost; };
+    std::vector<Group> groups;
+    for (size_t i = 0; i < keys.size(); ++i) {
+        const StepItem &it = items[keys[i].idx];
+        ws.h_items[i] = it;
+        if (groups.empty() || groups.back().kernel != keys[i].kernel ||
+            (keys[i].kernel && lds_class(groups.back().lds) != keys[i].cls)) {
+            groups.push_back(Group{i, 0, keys[i].kernel, 0, 1, 0.0});
+        }
+        Group &g = groups.back();
+        ++g.count;
+        g.lds = std::max(g.lds, it.lds);
+        g.maxW = std::max(g.maxW, (it.nodes + 31) / 32);
+        g.cost += keys[i].cost * it.nchains;
+    }
     if (hipMemcpyAsync(ws.d_items, ws.h_items, items.size() * sizeof(StepItem), hipMemcpyHostToDevice,
                        stream) != hipSuccess) {
         err = "item upload";
         return PBN_EDEVICE;
     }
-    return launch_step(ws.d_items, (uint32_t)items.size(), maxW, stream, err);
+    ProfileMark mark;
+    if (profiling()) {
+        for (const StepItem &it : items) {
+            const double cs = (double)(it.nburn + (uint64_t)it.nrec * it.thin) * it.nchains;
+            mark.chain_steps += cs;
+            mark.node_updates += cs * it.nodes;
+            mark.ops += cs * it.ops_per_step;
+            mark.philox += cs * it.philox_per_step;
+        }
+        profile_begin(mark, stream);
+    }
+    auto launch_group = [&](const Group &g, hipStream_t s) -> int {
+        const StepItem *d = ws.d_items + g.first;
+        if (g.kernel == 0) return launch_step(d, (uint32_t)g.count, g.maxW, s, err);
+        return launch_step_bs(d, (uint32_t)g.count, g.kernel, g.lds, s, err);
+    };
+    if (groups.size() == 1) {
+        rc = launch_group(groups[0], stream);
+    } else {
+        // largest groups first, spread over the pool's streams, joined back
+        std::sort(groups.begin(), groups.end(), [](const Group &a, const Group &b) { return a.cost > b.cost; });
+        StreamPool &P = stream_pool();
+        if ((rc = P.init(err))) return rc;
+        if (hipEventRecord(P.fork, stream) != hipSuccess) { err = "fork event"; return PBN_EDEVICE; }
+        const int used = std::min<int>(StreamPool::kN, (int)groups.size());
+        for (int k = 0; k < used; ++k)
+            if (hipStreamWaitEvent(P.s[k], P.fork, 0) != hipSuccess) { err = "fork wait"; return PBN_EDEVICE; }
+        for (size_t g = 0; g < groups.size() && !rc; ++g) rc = launch_group(groups[g], P.s[g % StreamPool::kN]);
+        for (int k = 0; k < used; ++k) {
+            if (hipEventRecord(P.join[k], P.s[k]) != hipSuccess ||
+                hipStreamWaitEvent(stream, P.join[k], 0) != hipSuccess) {
+                err = "join";
+                return PBN_EDEVICE;
+            }
+        }
+    }
+    if (profiling()) profile_end(mark, stream);
+    return rc;
+}
+
+// ------------------------------------------------------------ profiling
+
+namespace {
+struct ProfState {
+    bool on = false;
+    std::vector<ProfileMark> pending;
+    std::vector<hipEvent_t> pool;
+    pbn_profile acc{};
+};
+ProfState &prof()
+{
+    static ProfState p;
+    return p;
+}
+hipEvent_t get_event()
+{
+    ProfState &p = prof();
+    if (!p.pool.empty()) {
+        hipEvent_t e = p.pool.back();
+        p.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+}  // namespace
+
+bool profiling() { return prof().on; }
+
+void profile_begin(ProfileMark &m, hipStream_t stream)
+{
+    m.start = get_event();
+    m.stop = get_event();
+    (void)hipEventRecord(m.start, stream);
+}
+
+void profile_end(ProfileMark &m, hipStream_t stream)
+{
+    (void)hipEventRecord(m.stop, stream);
+    prof().pending.push_back(m);
+}
+
+int profile_collect(pbn_profile *out, std::string &err)
+{
+    ProfState &p = prof();
+    for (ProfileMark &m : p.pending) {
+        if (hipEventSynchronize(m.stop) != hipSuccess) { err = "profile event"; return PBN_EDEVICE; }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, m.start, m.stop);
+        p.acc.launches += 1;
+        p.acc.kernel_ms += ms;
+        p.acc.chain_steps += m.chain_steps;
+        p.acc.node_updates += m.node_updates;
+        p.acc.alg_ops += m.ops;
+        p.acc.philox_evals += m.philox;
+        p.pool.push_back(m.start);
+        p.pool.push_back(m.stop);
+    }
+    p.pending.clear();
+    if (out) *out = p.acc;
+    return PBN_OK;
+}
+
+void profile_set(bool on) { prof().on = on; }
+
+void profile_clear()
+{
+    std::string err;
+    profile_collect(nullptr, err);
+    prof().acc = pbn_profile{};
 }
 
 // ------------------------------------------------------------ rounds

@@ -116,6 +116,22 @@ int run_round(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
 // Rounds until every run is finished.
 int run_to_completion(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err);
 
+// Profiling of step launches (HIP events on the launch stream).
+struct ProfileMark {
+    hipEvent_t start = nullptr, stop = nullptr;
+    double chain_steps = 0, node_updates = 0, ops = 0, philox = 0;
+};
+bool profiling();
+void profile_begin(ProfileMark &m, hipStream_t stream);
+void profile_end(ProfileMark &m, hipStream_t stream);
+int profile_collect(pbn_profile *out, std::string &err);
+void profile_set(bool on);
+void profile_clear();
+
+// Kernel selection for a step item (see pbn_driver.cpp) and its override.
+void choose_kernel(const Net &net, StepItem &it);
+void set_kernel_mode(int mode, uint32_t waves);
+
 // Launch step items for several sims (sorted by cost) on stream.
 int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream, std::string &err);
 

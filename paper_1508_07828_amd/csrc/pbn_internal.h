@@ -24,13 +24,34 @@ constexpr uint32_t kMaxTerms = PBN_MAX_TERMS;
 struct Net {
     uint32_t n = 0, W = 0, F = 0, p_thr = 0, max_k = 0, max_l = 0;
     double p = 0.0, density = 0.0;
+    double ops_per_step = 0.0, philox_per_step = 0.0;   // expected, per chain-step
     std::vector<uint32_t> nd_first, fn_thr, fn_desc, fn_tt, tt_ext;
     std::vector<uint16_t> par;
+    // Bit-sliced schedule (networks with k <= 6):
+    //   nd_meta[n]   l(i) | (offset of node i's selection masks) << 8
+    //   nd_tb[n]     top bytes of T_1..T_3 (l <= 4), byte j = T_{j+1} >> 24
+    //   blk_sel[nb]  1 if 16-node block b holds a node with l > 1
+    //   predictor slots sorted by k, F_pad = 64 * ceil(F/64):
+    //   fs_node      node of the slot (kNoNode for padding)
+    //   fs_tt_lo/hi  truth table replicated to 2^K bits (K = the slot group's max k)
+    //   fs_par[m][s] parent m of slot s (padding parents: node 0)
+    //   fs_mlo/mhi   selection-mask indices of T_{j-1} and T_j (kNoMask: none)
+    //   fg_K[g]      K of slot group g (64 slots)
+    bool bitsliced = false;
+    uint32_t F_pad = 0, msel_total = 0, nblk = 0;
+    std::vector<uint32_t> nd_meta, nd_tb, blk_sel, fs_node, fs_tt_lo, fs_tt_hi, fs_mlo, fs_mhi, fg_K;
+    std::vector<uint16_t> fs_par;
     // blob layout (byte offsets)
     size_t off_nd_first = 0, off_fn_thr = 0, off_fn_desc = 0, off_fn_tt = 0, off_tt_ext = 0,
            off_par = 0, blob_bytes = 0;
+    size_t off_nd_meta = 0, off_nd_tb = 0, off_blk_sel = 0, off_fs_node = 0, off_fs_tt_lo = 0,
+           off_fs_tt_hi = 0, off_fs_mlo = 0, off_fs_mhi = 0, off_fg_K = 0, off_fs_par = 0;
     std::vector<uint8_t> blob;
 };
+
+constexpr uint32_t kNoNode = 0xFFFFFFFFu, kNoMask = 0xFFFFFFFFu;
+constexpr uint32_t kBsMaxK = 6;          // bit-sliced evaluation handles k <= 6
+constexpr uint32_t kQCap = 512;          // tie-queue entries per wave
 
 int parse_and_compile(const char *text, size_t len, Net &out, std::string &err);
 
@@ -53,6 +74,14 @@ struct DevSim {
     uint32_t term_word[kMaxTerms];
     uint32_t term_mask[kMaxTerms];
     uint32_t term_val[kMaxTerms];
+    // node-level form of the same state sets (bit-sliced kernel)
+    uint32_t pn_off[kMaxProps + 1];
+    uint32_t pn_node[kMaxTerms];
+    uint32_t pn_val[kMaxTerms];
+    // bit-sliced schedule
+    const uint32_t *nd_meta, *nd_tb, *blk_sel, *fs_node, *fs_tt_lo, *fs_tt_hi, *fs_mlo, *fs_mhi, *fg_K;
+    const uint16_t *fs_par;
+    uint32_t F_pad, msel_total, nblk, pad0;
 };
 
 // One unit of step-kernel work: chains [chain0, chain0+nchains) of one sim.
@@ -63,6 +92,9 @@ struct StepItem {
     uint32_t nburn, nrec, thin;  // unrecorded transitions, recorded positions, spacing
     uint32_t nodes;              // network size (host-side cost and LDS sizing)
     uint64_t pos0;               // first recorded position (0-based)
+    float ops_per_step, philox_per_step;   // host-side accounting only
+    uint32_t kernel;             // host-side: 0 = lane-per-chain, else waves per block (bit-sliced)
+    uint32_t lds;                // host-side: LDS bytes the bit-sliced kernel needs
 };
 
 enum QueryKind : uint32_t { kQueryWindow = 0, kQueryBatch = 1 };
@@ -85,6 +117,10 @@ struct WindowResult {
 int launch_init(const DevSim *dsim, uint32_t omega, uint32_t W, void *stream, std::string &err);
 int launch_step(const StepItem *d_items, uint32_t nitems, uint32_t max_W, void *stream,
                 std::string &err);
+// Bit-sliced trajectory kernel: G waves per 64-chain block, lds bytes of LDS.
+int launch_step_bs(const StepItem *d_items, uint32_t nitems, uint32_t G, size_t lds, void *stream,
+                   std::string &err);
+size_t bs_lds_bytes(uint32_t n, uint32_t msel_total, uint32_t G);
 int launch_reduce(const Query *d_queries, uint32_t nq, WindowResult *d_win, int32_t *d_bsum,
                   void *stream, std::string &err);
 

@@ -40,13 +40,13 @@ __device__ __forceinline__ void philox4(uint32_t c0, uint32_t c1, uint32_t c2, u
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+// w[j] for a per-lane j in 0..3, as two levels of selects (kept in registers).
 __device__ __forceinline__ uint32_t pick4(const uint32_t w[4], uint32_t j)
 {
-    uint32_t v = w[0];
-    v = (j == 1) ? w[1] : v;
-    v = (j == 2) ? w[2] : v;
-    v = (j == 3) ? w[3] : v;
-    return v;
+    const bool odd = (j & 1u) != 0, high = (j & 2u) != 0;
+    const uint32_t a = odd ? w[1] : w[0];
+    const uint32_t b = odd ? w[3] : w[2];
+    return high ? b : a;
 }
 
 // Low 24 bits of the refinement word of node i (tag + 1).
@@ -280,6 +280,275 @@ __global__ void __launch_bounds__(64) k_step(const StepItem *__restrict__ items,
     for (uint32_t w = 0; w < W; ++w) sm.state[(size_t)w * omega + c] = cur[w];
 }
 
+// ------------------------------------------------------------ bit-sliced step
+//
+// One block of G waves advances 64 chains.  State is bit-sliced in LDS: S[i]
+// holds node i of all 64 chains (bit = lane = chain).  Per transition:
+//   A  lane = chain: the waves share the 16-node blocks; each lane draws its
+//      chain's perturbation and selection bytes; wave ballots turn the byte
+//      comparisons into 64-chain masks (perturbation flips into Gm[i],
+//      selection masks m_j = [u < T_j] into M); byte ties that need the
+//      24-bit refinement are queued per wave and resolved 64 at a time
+//   B  lane = node: Gm[i] := P & (S[i] ^ gamma_i), P = perturbed chains
+//   C  lane = predictor slot (sorted by parent count): K-input multiplexer
+//      tree over the parents' masks, restricted to the chains that selected
+//      this predictor and were not perturbed, OR-ed into Gm[node]
+//   D  record the state-set indicators; clear S (next step's gamma); swap
+// LDS (u64 words): S[n], Gm[n], M[msel_total], Pw[G], then the u32 queues.
+
+__device__ __forceinline__ uint64_t bsel(uint64_t m, uint64_t a, uint64_t b)
+{
+    return (m & a) | (~m & b);          // a where m is set, else b
+}
+
+template <int K>
+__device__ __forceinline__ uint64_t mux_tree(uint32_t lo, uint32_t hi, const uint64_t *x)
+{
+    constexpr int L = 1 << K;
+    uint64_t r[L / 2];
+#pragma unroll
+    for (int m = 0; m < L / 2; ++m) {
+        const int e0 = 2 * m, e1 = 2 * m + 1;
+        const uint32_t w0 = e0 < 32 ? lo : hi, w1 = e1 < 32 ? lo : hi;
+        const uint64_t A = 0ull - (uint64_t)((w0 >> (e0 & 31)) & 1u);
+        const uint64_t B = 0ull - (uint64_t)((w1 >> (e1 & 31)) & 1u);
+        r[m] = bsel(x[0], B, A);
+    }
+#pragma unroll
+    for (int lev = 1; lev < K; ++lev) {
+#pragma unroll
+        for (int m = 0; m < (L >> (lev + 1)); ++m) r[m] = bsel(x[lev], r[2 * m + 1], r[2 * m]);
+    }
+    return r[0];
+}
+
+__device__ __forceinline__ uint64_t eval_slot(uint32_t K, uint32_t lo, uint32_t hi, const uint64_t *x)
+{
+    switch (K) {
+    case 1: return mux_tree<1>(lo, hi, x);
+    case 2: return mux_tree<2>(lo, hi, x);
+    case 3: return mux_tree<3>(lo, hi, x);
+    case 4: return mux_tree<4>(lo, hi, x);
+    case 5: return mux_tree<5>(lo, hi, x);
+    default: return mux_tree<6>(lo, hi, x);
+    }
+}
+
+// Queue entry: node (16 bits) | j (6) << 16 | kind (1) << 22 | lane (6) << 23.
+__device__ __forceinline__ void resolve_queue(const DevSim &sm, Key key, uint32_t t, uint32_t chain0,
+                                              uint32_t *Q, uint32_t qlen, uint64_t *Gm, uint64_t *M,
+                                              uint64_t *Pw_mine, uint32_t lane)
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (uint32_t e = lane; e < qlen; e += 64) {
+        const uint32_t ent = Q[e];
+        const uint32_t node = ent & 0xFFFFu, j = (ent >> 16) & 63u, kind = (ent >> 22) & 1u, cl = ent >> 23;
+        const uint64_t bit = 1ull << cl;
+        const uint32_t r24 = refine24(key, t, chain0 + cl, node, kind ? kTagSel : kTagPert);
+        if (kind == 0) {
+            if (r24 < (sm.p_thr & 0xFFFFFFu)) {
+                atomicOr((unsigned long long *)&Gm[node], (unsigned long long)bit);
+                atomicOr((unsigned long long *)Pw_mine, (unsigned long long)bit);
+            }
+        } else {
+            const uint32_t T = sm.fn_thr[sm.nd_first[node] + j];
+            if (r24 < (T & 0xFFFFFFu))
+                atomicOr((unsigned long long *)&M[(sm.nd_meta[node] >> 8) + j], (unsigned long long)bit);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+__device__ __forceinline__ void enqueue(uint64_t tie, uint32_t payload, uint32_t lane, uint32_t *Q, uint32_t &qlen,
+                                        const DevSim &sm, Key key, uint32_t t, uint32_t chain0, uint64_t *Gm,
+                                        uint64_t *M, uint64_t *Pw_mine)
+{
+    const uint32_t cnt = (uint32_t)__popcll(tie);
+    if (qlen + cnt > kQCap) {
+        resolve_queue(sm, key, t, chain0, Q, qlen, Gm, M, Pw_mine, lane);
+        qlen = 0;
+    }
+    if ((tie >> lane) & 1ull) {
+        const uint32_t pos = qlen + (uint32_t)__popcll(tie & ((1ull << lane) - 1ull));
+        Q[pos] = payload | (lane << 23);
+    }
+    qlen += cnt;
+}
+
+extern __shared__ uint64_t lds_bs[];
+
+template <int G>
+__global__ void __launch_bounds__(64 * G) k_step_bs(const StepItem *__restrict__ items)
+{
+    const StepItem it = items[blockIdx.x];
+    const DevSim &sm = *it.sim;
+    const uint32_t n = sm.n, W = sm.W, omega = sm.omega;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t chain0 = it.chain0;
+    const uint32_t c = chain0 + lane;
+    const bool active = lane < it.nchains;
+    const uint64_t amask = it.nchains >= 64 ? ~0ull : ((1ull << it.nchains) - 1ull);
+    const Key key{sm.key0, sm.key1};
+    uint64_t *S = lds_bs;
+    uint64_t *Gm = lds_bs + n;
+    uint64_t *M = lds_bs + 2 * n;
+    uint64_t *Pw = M + sm.msel_total;
+    uint32_t *Q = (uint32_t *)(Pw + G) + wave * kQCap;
+
+    // transpose the chains' packed words into node masks
+    for (uint32_t w = wave; w < W; w += G) {
+        const uint32_t word = active ? sm.state[(size_t)w * omega + c] : 0u;
+        const uint32_t nb = min(32u, n - 32 * w);
+        for (uint32_t b = 0; b < nb; ++b) {
+            const uint64_t m = __ballot((word >> b) & 1u);
+            if (lane == 0) S[32 * w + b] = m;
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < n; i += 64 * G) Gm[i] = 0ull;
+    if (threadIdx.x < G) Pw[threadIdx.x] = 0ull;
+
+    uint32_t acc[kMaxProps];
+    uint64_t pos = it.pos0;
+    const uint32_t nprops = sm.nprops;
+#pragma unroll
+    for (uint32_t q = 0; q < kMaxProps; ++q) {
+        acc[q] = 0;
+        if (wave == 0 && active && q < nprops && it.nrec > 0 && (pos & 31)) {
+            const uint32_t old = sm.bits[((size_t)q * sm.words_cap + (pos >> 5)) * omega + c];
+            acc[q] = old & ((1u << (pos & 31)) - 1u);
+        }
+    }
+    __syncthreads();
+
+    const uint32_t p_thr = sm.p_thr, thr8 = p_thr >> 24;
+    const uint32_t nblk = sm.nblk, F_pad = sm.F_pad;
+    const uint32_t total = it.nburn + it.nrec * it.thin;
+    uint32_t since = 0;
+    for (uint32_t s = 0; s < total; ++s) {
+        const uint32_t t = it.t0 + s;
+        // ---- A: draws, lane = chain
+        uint64_t P_acc = 0;
+        uint32_t qlen = 0;
+        for (uint32_t b = wave; b < nblk; b += G) {
+            const uint32_t i0 = 16 * b, ib = min(16u, n - i0);
+            uint32_t wp[4];
+            philox4(t, c, b, kTagPert, key, wp);
+#pragma unroll
+            for (uint32_t k = 0; k < 16; ++k) {
+                if (k >= ib) break;
+                const uint32_t byte = (wp[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+                if (thr8 > 0) {
+                    const uint64_t d1 = __ballot(byte < thr8) & amask;
+                    if (d1) {
+                        if (lane == 0) atomicOr((unsigned long long *)&Gm[i0 + k], (unsigned long long)d1);
+                        P_acc |= d1;
+                    }
+                }
+                const uint64_t tie = __ballot(byte == thr8) & amask;
+                if (tie) enqueue(tie, i0 + k, lane, Q, qlen, sm, key, t, chain0, Gm, M, &Pw[wave]);
+            }
+            if (sm.blk_sel[b]) {
+                uint32_t ws[4];
+                philox4(t, c, b, kTagSel, key, ws);
+#pragma unroll
+                for (uint32_t k = 0; k < 16; ++k) {
+                    if (k >= ib) break;
+                    const uint32_t i = i0 + k;
+                    const uint32_t meta = sm.nd_meta[i];
+                    const uint32_t l = meta & 0xFFu;
+                    if (l < 2) continue;
+                    const uint32_t moff = meta >> 8;
+                    const uint32_t byte = (ws[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+                    const uint32_t tbs = sm.nd_tb[i];
+                    for (uint32_t j = 0; j + 1 < l; ++j) {
+                        const uint32_t tb = j < 3 ? (tbs >> (8 * j)) & 0xFFu : sm.fn_thr[sm.nd_first[i] + j] >> 24;
+                        const uint64_t lt = __ballot(byte < tb) & amask;
+                        if (lane == 0) M[moff + j] = lt;
+                        const uint64_t eq = __ballot(byte == tb) & amask;
+                        if (eq) enqueue(eq, i | (j << 16) | (1u << 22), lane, Q, qlen, sm, key, t, chain0, Gm, M, &Pw[wave]);
+                    }
+                }
+            }
+        }
+        if (qlen) resolve_queue(sm, key, t, chain0, Q, qlen, Gm, M, &Pw[wave], lane);
+        if (P_acc && lane == 0) atomicOr((unsigned long long *)&Pw[wave], (unsigned long long)P_acc);
+        __syncthreads();
+
+        // ---- B: S' := P & (S ^ gamma), lane = node
+        uint64_t P = 0;
+#pragma unroll
+        for (int w = 0; w < G; ++w) P |= Pw[w];
+        for (uint32_t i = threadIdx.x; i < n; i += 64 * G) Gm[i] = P & (S[i] ^ Gm[i]);
+        __syncthreads();
+
+        // ---- C: predictor slots, lane = slot
+        const uint64_t nP = ~P;
+        for (uint32_t s0 = 64 * wave; s0 < F_pad; s0 += 64 * G) {
+            const uint32_t slot = s0 + lane;
+            const uint32_t K = sm.fg_K[s0 >> 6];
+            const uint32_t node = sm.fs_node[slot];
+            uint64_t x[6];
+#pragma unroll
+            for (uint32_t m = 0; m < 6; ++m) x[m] = (m < K) ? S[sm.fs_par[(size_t)m * F_pad + slot]] : 0ull;
+            const uint64_t f = eval_slot(K, sm.fs_tt_lo[slot], sm.fs_tt_hi[slot], x);
+            const uint32_t mlo = sm.fs_mlo[slot], mhi = sm.fs_mhi[slot];
+            const uint64_t below = mlo == kNoMask ? 0ull : M[mlo];
+            const uint64_t upto = mhi == kNoMask ? ~0ull : M[mhi];
+            if (node != kNoNode) {
+                const uint64_t v = f & upto & ~below & nP;
+                if (v) atomicOr((unsigned long long *)&Gm[node], (unsigned long long)v);
+            }
+        }
+        __syncthreads();
+
+        // ---- D: record, clear, swap (Pw was last read in B, before C's barrier)
+        if (s >= it.nburn && ++since == it.thin) {
+            since = 0;
+            if (wave == 0) {
+                const uint32_t bpos = (uint32_t)(pos & 31);
+#pragma unroll
+                for (uint32_t q = 0; q < kMaxProps; ++q) {
+                    if (q < nprops) {
+                        uint64_t xm = ~0ull;
+                        for (uint32_t m = sm.pn_off[q]; m < sm.pn_off[q + 1]; ++m) {
+                            const uint64_t v = Gm[sm.pn_node[m]];
+                            xm &= sm.pn_val[m] ? v : ~v;
+                        }
+                        acc[q] |= (uint32_t)((xm >> lane) & 1ull) << bpos;
+                    }
+                }
+                if (bpos == 31 && active) {
+#pragma unroll
+                    for (uint32_t q = 0; q < kMaxProps; ++q) {
+                        if (q < nprops) {
+                            sm.bits[((size_t)q * sm.words_cap + (pos >> 5)) * omega + c] = acc[q];
+                            acc[q] = 0;
+                        }
+                    }
+                }
+            }
+            ++pos;
+        }
+        for (uint32_t i = threadIdx.x; i < n; i += 64 * G) S[i] = 0ull;
+        if (threadIdx.x < G) Pw[threadIdx.x] = 0ull;
+        uint64_t *tmp = S; S = Gm; Gm = tmp;
+        __syncthreads();
+    }
+
+    if (wave == 0 && active && it.nrec > 0 && (pos & 31)) {
+#pragma unroll
+        for (uint32_t q = 0; q < kMaxProps; ++q)
+            if (q < nprops) sm.bits[((size_t)q * sm.words_cap + (pos >> 5)) * omega + c] = acc[q];
+    }
+    // transpose back
+    for (uint32_t w = wave; w < W; w += G) {
+        uint32_t word = 0;
+        const uint32_t nb = min(32u, n - 32 * w);
+        for (uint32_t b = 0; b < nb; ++b) word |= (uint32_t)((S[32 * w + b] >> lane) & 1ull) << b;
+        if (active) sm.state[(size_t)w * omega + c] = word;
+    }
+}
+
 // ------------------------------------------------------------------ reduce
 
 // Bits [lo, hi) of a word starting at position 32*wi, as a mask.
@@ -393,6 +662,38 @@ int launch_step(const StepItem *d_items, uint32_t nitems, uint32_t max_W, void *
     }
     hipLaunchKernelGGL(k_step, dim3(nitems), dim3(64), lds, (hipStream_t)stream, d_items, S);
     return check(hipGetLastError(), "k_step launch", err);
+}
+
+size_t bs_lds_bytes(uint32_t n, uint32_t msel_total, uint32_t G)
+{
+    return (size_t)8 * (2 * (size_t)n + msel_total + G) + (size_t)4 * kQCap * G;
+}
+
+template <int G>
+static int launch_bs_g(const StepItem *d_items, uint32_t nitems, size_t lds, hipStream_t s, std::string &err)
+{
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_step_bs<G>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return check(e, "k_step_bs LDS attribute", err);
+    }
+    hipLaunchKernelGGL(k_step_bs<G>, dim3(nitems), dim3(64 * G), lds, s, d_items);
+    return check(hipGetLastError(), "k_step_bs launch", err);
+}
+
+int launch_step_bs(const StepItem *d_items, uint32_t nitems, uint32_t G, size_t lds, void *stream, std::string &err)
+{
+    if (nitems == 0) return PBN_OK;
+    if (lds > 160 * 1024) {
+        err = "bit-sliced state exceeds LDS";
+        return PBN_ELIMIT;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    switch (G) {
+    case 1: return launch_bs_g<1>(d_items, nitems, lds, s, err);
+    case 2: return launch_bs_g<2>(d_items, nitems, lds, s, err);
+    default: return launch_bs_g<4>(d_items, nitems, lds, s, err);
+    }
 }
 
 int launch_reduce(const Query *d_queries, uint32_t nq, WindowResult *d_win, int32_t *d_bsum, void *stream,

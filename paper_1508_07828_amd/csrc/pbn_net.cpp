@@ -6,6 +6,7 @@
 // k <= 5 parents, ceil(2^k/32) words otherwise) and the selection
 // probabilities as cumulative 32-bit thresholds T_j = min(2^32-1,
 // floor(2^32 (c_1+..+c_j))), the running sum taken left to right in FP64.
+#include <algorithm>
 #include <cerrno>
 #include <cmath>
 #include <cstdlib>
@@ -68,6 +69,8 @@ int hexdigit(char c)
 size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
 }  // namespace
+
+void build_bitsliced_schedule(Net &net);
 
 int parse_and_compile(const char *text, size_t len, Net &net, std::string &err)
 {
@@ -146,22 +149,147 @@ int parse_and_compile(const char *text, size_t len, Net &net, std::string &err)
     if (net.par.empty()) net.par.push_back(0);
     net.density = double(total_par) / double(net.n);
 
+    // Expected algorithmic work per chain-step (accounting for the roofline):
+    // Philox evaluations of the stream (16 primaries per evaluation, a refinement
+    // when a primary byte ties a threshold's top byte), comparisons, parent-bit
+    // gathers and lookups of the function update (taken when no node is
+    // perturbed: probability (1-p)^n).
+    {
+        const double two32 = 4294967296.0;
+        const double pq = (double)net.p_thr / two32;
+        const double q_fn = std::pow(1.0 - pq, (double)net.n);
+        const uint32_t nblk = (net.n + 15) / 16;
+        uint32_t sel_blocks = 0;
+        double sel_ref = 0.0, fn_ops = 0.0;
+        for (uint32_t b = 0; b < nblk; ++b) {
+            bool any = false;
+            for (uint32_t i = 16 * b; i < std::min(net.n, 16 * b + 16); ++i)
+                if (net.nd_first[i + 1] - net.nd_first[i] > 1) any = true;
+            sel_blocks += any ? 1 : 0;
+        }
+        for (uint32_t i = 0; i < net.n; ++i) {
+            const uint32_t a = net.nd_first[i], l = net.nd_first[i + 1] - a;
+            sel_ref += (double)(l - 1) / 256.0;
+            double ek = 0.0, prev = 0.0;
+            for (uint32_t j = 0; j < l; ++j) {
+                const double T = (j + 1 == l) ? two32 : (double)net.fn_thr[a + j];
+                ek += (T - prev) / two32 * (double)(net.fn_desc[a + j] & 31u);
+                prev = T;
+            }
+            fn_ops += (double)(l - 1) + 2.0 * ek + 1.0;
+        }
+        net.philox_per_step = (double)nblk + (double)net.n / 256.0 + q_fn * ((double)sel_blocks + sel_ref);
+        net.ops_per_step = 100.0 * net.philox_per_step + (double)net.n + q_fn * fn_ops;
+    }
+
+    build_bitsliced_schedule(net);
+
     size_t off = 0;
-    net.off_nd_first = off; off = align16(off + 4 * net.nd_first.size());
-    net.off_fn_thr = off;   off = align16(off + 4 * net.fn_thr.size());
-    net.off_fn_desc = off;  off = align16(off + 4 * net.fn_desc.size());
-    net.off_fn_tt = off;    off = align16(off + 4 * net.fn_tt.size());
-    net.off_tt_ext = off;   off = align16(off + 4 * net.tt_ext.size());
-    net.off_par = off;      off = align16(off + 2 * net.par.size());
+    auto place = [&](size_t &field, size_t bytes) { field = off; off = align16(off + std::max<size_t>(bytes, 4)); };
+    place(net.off_nd_first, 4 * net.nd_first.size());
+    place(net.off_fn_thr, 4 * net.fn_thr.size());
+    place(net.off_fn_desc, 4 * net.fn_desc.size());
+    place(net.off_fn_tt, 4 * net.fn_tt.size());
+    place(net.off_tt_ext, 4 * net.tt_ext.size());
+    place(net.off_par, 2 * net.par.size());
+    place(net.off_nd_meta, 4 * net.nd_meta.size());
+    place(net.off_nd_tb, 4 * net.nd_tb.size());
+    place(net.off_blk_sel, 4 * net.blk_sel.size());
+    place(net.off_fs_node, 4 * net.fs_node.size());
+    place(net.off_fs_tt_lo, 4 * net.fs_tt_lo.size());
+    place(net.off_fs_tt_hi, 4 * net.fs_tt_hi.size());
+    place(net.off_fs_mlo, 4 * net.fs_mlo.size());
+    place(net.off_fs_mhi, 4 * net.fs_mhi.size());
+    place(net.off_fg_K, 4 * net.fg_K.size());
+    place(net.off_fs_par, 2 * net.fs_par.size());
     net.blob_bytes = off;
     net.blob.assign(off, 0);
-    std::memcpy(net.blob.data() + net.off_nd_first, net.nd_first.data(), 4 * net.nd_first.size());
-    std::memcpy(net.blob.data() + net.off_fn_thr, net.fn_thr.data(), 4 * net.fn_thr.size());
-    std::memcpy(net.blob.data() + net.off_fn_desc, net.fn_desc.data(), 4 * net.fn_desc.size());
-    std::memcpy(net.blob.data() + net.off_fn_tt, net.fn_tt.data(), 4 * net.fn_tt.size());
-    std::memcpy(net.blob.data() + net.off_tt_ext, net.tt_ext.data(), 4 * net.tt_ext.size());
-    std::memcpy(net.blob.data() + net.off_par, net.par.data(), 2 * net.par.size());
+    auto put = [&](size_t at, const void *src, size_t bytes) {
+        if (bytes) std::memcpy(net.blob.data() + at, src, bytes);
+    };
+    put(net.off_nd_first, net.nd_first.data(), 4 * net.nd_first.size());
+    put(net.off_fn_thr, net.fn_thr.data(), 4 * net.fn_thr.size());
+    put(net.off_fn_desc, net.fn_desc.data(), 4 * net.fn_desc.size());
+    put(net.off_fn_tt, net.fn_tt.data(), 4 * net.fn_tt.size());
+    put(net.off_tt_ext, net.tt_ext.data(), 4 * net.tt_ext.size());
+    put(net.off_par, net.par.data(), 2 * net.par.size());
+    put(net.off_nd_meta, net.nd_meta.data(), 4 * net.nd_meta.size());
+    put(net.off_nd_tb, net.nd_tb.data(), 4 * net.nd_tb.size());
+    put(net.off_blk_sel, net.blk_sel.data(), 4 * net.blk_sel.size());
+    put(net.off_fs_node, net.fs_node.data(), 4 * net.fs_node.size());
+    put(net.off_fs_tt_lo, net.fs_tt_lo.data(), 4 * net.fs_tt_lo.size());
+    put(net.off_fs_tt_hi, net.fs_tt_hi.data(), 4 * net.fs_tt_hi.size());
+    put(net.off_fs_mlo, net.fs_mlo.data(), 4 * net.fs_mlo.size());
+    put(net.off_fs_mhi, net.fs_mhi.data(), 4 * net.fs_mhi.size());
+    put(net.off_fg_K, net.fg_K.data(), 4 * net.fg_K.size());
+    put(net.off_fs_par, net.fs_par.data(), 2 * net.fs_par.size());
     return PBN_OK;
+}
+
+// Bit-sliced schedule: see the Net comment.  Predictor slots are sorted by
+// parent count so that each 64-slot group evaluates one K-input multiplexer
+// tree; a predictor with k < K has its table replicated over the extra index
+// bits, which makes the padding parents irrelevant.
+void build_bitsliced_schedule(Net &net)
+{
+    net.bitsliced = net.max_k <= kBsMaxK;
+    net.nblk = (net.n + 15) / 16;
+    net.nd_meta.assign(net.n, 0);
+    net.nd_tb.assign(net.n, 0);
+    net.blk_sel.assign(net.nblk, 0);
+    net.msel_total = 0;
+    for (uint32_t i = 0; i < net.n; ++i) {
+        const uint32_t a = net.nd_first[i], l = net.nd_first[i + 1] - a;
+        net.nd_meta[i] = l | (net.msel_total << 8);
+        uint32_t tb = 0;
+        for (uint32_t j = 0; j + 1 < l && j < 3; ++j) tb |= (net.fn_thr[a + j] >> 24) << (8 * j);
+        net.nd_tb[i] = tb;
+        if (l > 1) net.blk_sel[i / 16] = 1;
+        net.msel_total += l - 1;
+    }
+    if (!net.bitsliced) return;
+    std::vector<uint32_t> order(net.F);
+    for (uint32_t f = 0; f < net.F; ++f) order[f] = f;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t x, uint32_t y) { return (net.fn_desc[x] & 31u) < (net.fn_desc[y] & 31u); });
+    std::vector<uint32_t> fn_node(net.F), fn_j(net.F);
+    for (uint32_t i = 0; i < net.n; ++i)
+        for (uint32_t f = net.nd_first[i]; f < net.nd_first[i + 1]; ++f) {
+            fn_node[f] = i;
+            fn_j[f] = f - net.nd_first[i];
+        }
+    net.F_pad = (net.F + 63) / 64 * 64;
+    const uint32_t groups = net.F_pad / 64;
+    net.fs_node.assign(net.F_pad, kNoNode);
+    net.fs_tt_lo.assign(net.F_pad, 0);
+    net.fs_tt_hi.assign(net.F_pad, 0);
+    net.fs_mlo.assign(net.F_pad, kNoMask);
+    net.fs_mhi.assign(net.F_pad, kNoMask);
+    net.fs_par.assign((size_t)kBsMaxK * net.F_pad, 0);
+    net.fg_K.assign(groups, 1);
+    for (uint32_t g = 0; g < groups; ++g) {
+        uint32_t K = 1;
+        for (uint32_t s = 64 * g; s < std::min(net.F, 64 * g + 64); ++s) K = std::max(K, net.fn_desc[order[s]] & 31u);
+        net.fg_K[g] = K;
+        for (uint32_t s = 64 * g; s < std::min(net.F, 64 * g + 64); ++s) {
+            const uint32_t f = order[s], k = net.fn_desc[f] & 31u, po = net.fn_desc[f] >> 5;
+            const uint32_t i = fn_node[f], j = fn_j[f], l = net.nd_first[i + 1] - net.nd_first[i];
+            const uint32_t moff = net.nd_meta[i] >> 8;
+            net.fs_node[s] = i;
+            for (uint32_t m = 0; m < k; ++m) net.fs_par[(size_t)m * net.F_pad + s] = net.par[po + m];
+            // table over 2^K indices, bit e = f(e mod 2^k)
+            const uint64_t tt = (k <= 5) ? (uint64_t)net.fn_tt[f]
+                                         : ((uint64_t)net.tt_ext[net.fn_tt[f]] | ((uint64_t)net.tt_ext[net.fn_tt[f] + 1] << 32));
+            uint64_t rep = 0;
+            const uint32_t span = 1u << K, per = 1u << k;
+            for (uint32_t e = 0; e < span && e < 64; ++e) rep |= ((tt >> (e % per)) & 1ull) << e;
+            if (K <= 5) rep &= 0xFFFFFFFFull;
+            net.fs_tt_lo[s] = (uint32_t)rep;
+            net.fs_tt_hi[s] = (uint32_t)(rep >> 32);
+            net.fs_mlo[s] = j == 0 ? kNoMask : moff + j - 1;
+            net.fs_mhi[s] = j + 1 == l ? kNoMask : moff + j;
+        }
+    }
 }
 
 }  // namespace pbn

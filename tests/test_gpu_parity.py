@@ -57,16 +57,29 @@ CASES = {
     "tiny": lambda: (ps.tiny().net, 8, ps.tiny().patterns),
     "medium": lambda: (ps.medium().net, 256, ps.medium().patterns),
     "ragged_k7_p05": lambda: (_ragged_net(), 100, [((0, 1), (5, 0)), ((36, 1),)]),
+    "ragged_k6_p05": lambda: (_ragged_net(37, 0.05, 6, 6), 100, [((0, 1), (5, 0)), ((36, 1),), ((2, 0),)]),
     "high_p": lambda: (_ragged_net(20, 0.6, 9, 4), 70, [((3, 1),)]),
     "one_node": lambda: (ps.small_network(2, 1, l_max=2, k_max=1, p=0.3), 65, [((0, 1),)]),
+    "n300_l4": lambda: (ps.random_network(np.random.default_rng(4), 300, (1, 4), (1, 6), 0.004), 130,
+                        [((7, 1), (299, 0))]),
 }
+
+# (mode, waves): the lane-per-chain kernel and the bit-sliced kernel with 1, 2, 4 waves per block
+KERNELS = [("lane", 0), ("bitsliced", 1), ("bitsliced", 2), ("bitsliced", 4)]
+
+
+@pytest.fixture(params=KERNELS, ids=["lane", "bs1", "bs2", "bs4"])
+def kernel(request):
+    pkg.set_kernel(*request.param)
+    yield request.param
+    pkg.set_kernel("auto", 0)
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
-def test_trajectories_bit_exact(case):
+def test_trajectories_bit_exact(case, kernel):
     net, omega, pats = CASES[case]()
     text = ps.to_text(net)
-    say("trajectories {} n={} omega={}".format(case, net.n, omega))
+    say("trajectories {} n={} omega={} kernel={}".format(case, net.n, omega, kernel))
     sim = pkg.Simulation(pkg.Network(text), omega, 7828, max_props=len(pats), max_len=4096)
     sim.reset(pats)
     ch = oracle.Chains(oracle.Net(text), omega, 7828, pats)
@@ -81,10 +94,11 @@ def test_trajectories_bit_exact(case):
     assert sim.position() == (L, L)
 
 
-def test_burn_in_and_thinning():
-    net, omega, pats = CASES["ragged_k7_p05"]()
+def test_burn_in_and_thinning(kernel):
+    net, omega, pats = CASES["ragged_k6_p05"]()
+    pats = pats[:2]
     text = ps.to_text(net)
-    say("burn-in/thin")
+    say("burn-in/thin kernel={}".format(kernel))
     sim = pkg.Simulation(pkg.Network(text), omega, 99, max_props=2, max_len=1024)
     sim.reset(pats)
     sim.run(50, burn_in=13, thin=3)
@@ -97,10 +111,12 @@ def test_burn_in_and_thinning():
     assert sim.position() == (50, 163)
 
 
-def test_large_sampled_chains():
+@pytest.mark.parametrize("mode", [("lane", 0), ("auto", 0)], ids=["lane", "auto"])
+def test_large_sampled_chains(mode):
+    pkg.set_kernel(*mode)
     job = ps.large()
     text = ps.to_text(job.net)
-    say("large: 8192 chains x 2000 nodes, 24 steps, sampled oracle chains")
+    say("large: 8192 chains x 2000 nodes, 24 steps, sampled oracle chains, kernel {}".format(mode))
     sim = pkg.Simulation(pkg.Network(text), job.chains, job.seed, max_props=5, max_len=256)
     sim.reset(job.patterns)
     init = sim.read_state()
@@ -115,6 +131,7 @@ def test_large_sampled_chains():
         assert np.array_equal(st[c0:c0 + 64], ch.states), c0
         for q in range(5):
             assert np.array_equal(bits[q][c0:c0 + 64], ch.bits[q]), (c0, q)
+    pkg.set_kernel("auto", 0)
 
 
 def test_window_counts_batch_sums_psrf():
