@@ -159,6 +159,7 @@ def main() -> int:
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--waves", type=int, default=0, help="bit-sliced waves per block (0 = by n)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs every simulation on a single MI355X "
@@ -171,6 +172,8 @@ def main() -> int:
         return 1
     torch.cuda.set_device(0)
     pkg.lib()
+    if args.waves:
+        pkg.set_kernel("bitsliced", args.waves)
 
     jobs = ps.batched(args.count)
     log("setting up {} networks".format(len(jobs)))
@@ -196,6 +199,11 @@ def main() -> int:
     prof = pkg.profile_read()
     pkg.profile_enable(False)
     total_t = sum(times)
+    dump = os.environ.get("PBN_BENCH_DUMP")
+    if dump:
+        with open(dump, "w") as fh:
+            json.dump([dict(nodes=j.net.n, chains=j.chains, p=j.net.p, **{k: r[0][k] for k in
+                       ("psi_gr", "psi", "n", "N", "M", "chain_len", "prob")}) for j, r in zip(jobs, res)], fh)
     value = sum(nus) / total_t
     nconv = sum(r[0]["status"] != 0 for r in res)
 

@@ -243,7 +243,7 @@ int pbn_profile_enable(int on);
  * (bit-sliced kernel when every predictor has at most 6 parents and the
  * bit-sliced state fits in LDS, else lane-per-chain), 1 = lane-per-chain only,
  * 2 = bit-sliced where possible; waves = waves sharing one 64-chain block in
- * the bit-sliced kernel (0 = chosen from n, else 1, 2 or 4).  Results do not
+ * the bit-sliced kernel (0 = chosen from n, else 1, 2, 4, 8 or 16).  Results do not
  * depend on the choice. */
 int pbn_set_kernel(int mode, uint32_t waves);
 int pbn_profile_read(pbn_profile *out);

@@ -500,8 +500,8 @@ int pbn_server_poll(pbn_server *srv, uint64_t id, int *ready, pbn_result *out)
 
 int pbn_set_kernel(int mode, uint32_t waves)
 {
-    if (mode < 0 || mode > 2 || (waves != 0 && waves != 1 && waves != 2 && waves != 4))
-        return fail(PBN_EINVAL, "mode must be 0..2 and waves 0, 1, 2 or 4");
+    if (mode < 0 || mode > 2 || (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 16))
+        return fail(PBN_EINVAL, "mode must be 0..2 and waves 0, 1, 2, 4, 8 or 16");
     pbn::set_kernel_mode(mode, waves);
     return PBN_OK;
 }

@@ -412,16 +412,10 @@ int sim_setup(pbn_sim *sim, const Net &net, uint32_t omega, uint64_t seed, uint3
     d.key0 = (uint32_t)seed;
     d.key1 = (uint32_t)(seed >> 32);
     d.nprops = 0;
-    d.nd_meta = (const uint32_t *)(blob + net.off_nd_meta);
-    d.nd_tb = (const uint32_t *)(blob + net.off_nd_tb);
+    d.nd_info = (const uint32_t *)(blob + net.off_nd_info);
     d.blk_sel = (const uint32_t *)(blob + net.off_blk_sel);
-    d.fs_node = (const uint32_t *)(blob + net.off_fs_node);
-    d.fs_tt_lo = (const uint32_t *)(blob + net.off_fs_tt_lo);
-    d.fs_tt_hi = (const uint32_t *)(blob + net.off_fs_tt_hi);
-    d.fs_mlo = (const uint32_t *)(blob + net.off_fs_mlo);
-    d.fs_mhi = (const uint32_t *)(blob + net.off_fs_mhi);
+    d.fs_rec = (const uint32_t *)(blob + net.off_fs_rec);
     d.fg_K = (const uint32_t *)(blob + net.off_fg_K);
-    d.fs_par = (const uint16_t *)(blob + net.off_fs_par);
     d.F_pad = net.F_pad;
     d.msel_total = net.msel_total;
     d.nblk = net.nblk;

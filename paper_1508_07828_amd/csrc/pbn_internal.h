@@ -44,8 +44,7 @@ struct Net {
     // blob layout (byte offsets)
     size_t off_nd_first = 0, off_fn_thr = 0, off_fn_desc = 0, off_fn_tt = 0, off_tt_ext = 0,
            off_par = 0, blob_bytes = 0;
-    size_t off_nd_meta = 0, off_nd_tb = 0, off_blk_sel = 0, off_fs_node = 0, off_fs_tt_lo = 0,
-           off_fs_tt_hi = 0, off_fs_mlo = 0, off_fs_mhi = 0, off_fg_K = 0, off_fs_par = 0;
+    size_t off_nd_info = 0, off_blk_sel = 0, off_fs_rec = 0, off_fg_K = 0;
     std::vector<uint8_t> blob;
 };
 
@@ -79,8 +78,9 @@ struct DevSim {
     uint32_t pn_node[kMaxTerms];
     uint32_t pn_val[kMaxTerms];
     // bit-sliced schedule
-    const uint32_t *nd_meta, *nd_tb, *blk_sel, *fs_node, *fs_tt_lo, *fs_tt_hi, *fs_mlo, *fs_mhi, *fg_K;
-    const uint16_t *fs_par;
+    const uint32_t *nd_info;     // [n][2]: l | mask offset << 8, top bytes of T_1..T_3
+    const uint32_t *fs_rec;      // [F_pad][8]: node, tt lo, tt hi, mask below, mask up to, parents
+    const uint32_t *blk_sel, *fg_K;
     uint32_t F_pad, msel_total, nblk, pad0;
 };
 

@@ -192,16 +192,29 @@ int parse_and_compile(const char *text, size_t len, Net &net, std::string &err)
     place(net.off_fn_tt, 4 * net.fn_tt.size());
     place(net.off_tt_ext, 4 * net.tt_ext.size());
     place(net.off_par, 2 * net.par.size());
-    place(net.off_nd_meta, 4 * net.nd_meta.size());
-    place(net.off_nd_tb, 4 * net.nd_tb.size());
+    // interleaved records for the bit-sliced kernel: per node (meta, top bytes),
+    // per predictor slot (node, table lo, table hi, mask below, mask up to,
+    // parents 0|1, 2|3, 4|5 as u16 pairs)
+    std::vector<uint32_t> nd_info(2 * (size_t)net.nd_meta.size()), fs_rec(8 * (size_t)net.F_pad);
+    for (size_t i = 0; i < net.nd_meta.size(); ++i) {
+        nd_info[2 * i] = net.nd_meta[i];
+        nd_info[2 * i + 1] = net.nd_tb[i];
+    }
+    for (size_t s = 0; s < net.F_pad; ++s) {
+        uint32_t *r = &fs_rec[8 * s];
+        r[0] = net.fs_node[s];
+        r[1] = net.fs_tt_lo[s];
+        r[2] = net.fs_tt_hi[s];
+        r[3] = net.fs_mlo[s];
+        r[4] = net.fs_mhi[s];
+        for (uint32_t m = 0; m < 3; ++m)
+            r[5 + m] = (uint32_t)net.fs_par[(size_t)(2 * m) * net.F_pad + s] |
+                       ((uint32_t)net.fs_par[(size_t)(2 * m + 1) * net.F_pad + s] << 16);
+    }
+    place(net.off_nd_info, 4 * nd_info.size());
     place(net.off_blk_sel, 4 * net.blk_sel.size());
-    place(net.off_fs_node, 4 * net.fs_node.size());
-    place(net.off_fs_tt_lo, 4 * net.fs_tt_lo.size());
-    place(net.off_fs_tt_hi, 4 * net.fs_tt_hi.size());
-    place(net.off_fs_mlo, 4 * net.fs_mlo.size());
-    place(net.off_fs_mhi, 4 * net.fs_mhi.size());
+    place(net.off_fs_rec, 4 * fs_rec.size());
     place(net.off_fg_K, 4 * net.fg_K.size());
-    place(net.off_fs_par, 2 * net.fs_par.size());
     net.blob_bytes = off;
     net.blob.assign(off, 0);
     auto put = [&](size_t at, const void *src, size_t bytes) {
@@ -213,16 +226,10 @@ int parse_and_compile(const char *text, size_t len, Net &net, std::string &err)
     put(net.off_fn_tt, net.fn_tt.data(), 4 * net.fn_tt.size());
     put(net.off_tt_ext, net.tt_ext.data(), 4 * net.tt_ext.size());
     put(net.off_par, net.par.data(), 2 * net.par.size());
-    put(net.off_nd_meta, net.nd_meta.data(), 4 * net.nd_meta.size());
-    put(net.off_nd_tb, net.nd_tb.data(), 4 * net.nd_tb.size());
+    put(net.off_nd_info, nd_info.data(), 4 * nd_info.size());
     put(net.off_blk_sel, net.blk_sel.data(), 4 * net.blk_sel.size());
-    put(net.off_fs_node, net.fs_node.data(), 4 * net.fs_node.size());
-    put(net.off_fs_tt_lo, net.fs_tt_lo.data(), 4 * net.fs_tt_lo.size());
-    put(net.off_fs_tt_hi, net.fs_tt_hi.data(), 4 * net.fs_tt_hi.size());
-    put(net.off_fs_mlo, net.fs_mlo.data(), 4 * net.fs_mlo.size());
-    put(net.off_fs_mhi, net.fs_mhi.data(), 4 * net.fs_mhi.size());
+    put(net.off_fs_rec, fs_rec.data(), 4 * fs_rec.size());
     put(net.off_fg_K, net.fg_K.data(), 4 * net.fg_K.size());
-    put(net.off_fs_par, net.fs_par.data(), 2 * net.fs_par.size());
     return PBN_OK;
 }
 

@@ -65,10 +65,11 @@ CASES = {
 }
 
 # (mode, waves): the lane-per-chain kernel and the bit-sliced kernel with 1, 2, 4 waves per block
-KERNELS = [("lane", 0), ("bitsliced", 1), ("bitsliced", 2), ("bitsliced", 4)]
+KERNELS = [("lane", 0), ("bitsliced", 1), ("bitsliced", 2), ("bitsliced", 4), ("bitsliced", 8),
+           ("bitsliced", 16)]
 
 
-@pytest.fixture(params=KERNELS, ids=["lane", "bs1", "bs2", "bs4"])
+@pytest.fixture(params=KERNELS, ids=["lane", "bs1", "bs2", "bs4", "bs8", "bs16"])
 def kernel(request):
     pkg.set_kernel(*request.param)
     yield request.param
