@@ -135,7 +135,7 @@ int pbn_sim_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops)
 {
     if (!sim || !valid_patterns(props, nprops)) return fail(PBN_EINVAL, "bad argument");
     std::string err;
-    int rc = pbn::sim_reset(sim, props, nprops, err);
+    int rc = pbn::sim_reset(sim, props, nprops, sim->stream, err);
     return rc ? fail(rc, err) : PBN_OK;
 }
 
@@ -284,30 +284,33 @@ int pbn_batch_estimate(pbn_sim *const *sims, uint32_t count, const pbn_pattern *
     if (!sims || !nprops || !prop_off || !r || !conf || !out) return fail(PBN_EINVAL, "null argument");
     std::vector<pbn::SimRun> runs(count);
     std::string err;
+    hipStream_t stream = (hipStream_t)hip_stream;
     for (uint32_t i = 0; i < count; ++i) {
         pbn_sim *s = sims[i];
         if (!s) return fail(PBN_EINVAL, "null simulation");
         if (s->omega < 2) return fail(PBN_EINVAL, "Gelman-Rubin needs omega >= 2 chains");
         if (!(r[i] > 0.0) || !(conf[i] > 0.0 && conf[i] < 1.0)) return fail(PBN_EINVAL, "r must be > 0 and s in (0,1)");
         if (nprops[i] < 1 || !valid_patterns(props + prop_off[i], nprops[i])) return fail(PBN_EINVAL, "bad state sets");
-        int rc = pbn::sim_reset(s, props + prop_off[i], nprops[i], err);
-        if (rc) return fail(rc, err);
-        runs[i].sim = s;
-        const pbn::MachineParams P = pbn::make_params(s, opts, r[i], conf[i]);
+        // work already queued on a simulation's own stream finishes first
+        if (s->stream != stream) {
+            int rc = sync(s->stream);
+            if (rc) return rc;
+        }
+    }
+    static thread_local pbn::Workspace ws;
+    pbn::Workspace &w = count == 1 ? sims[0]->ws : ws;
+    int rc0 = count == 1 ? pbn::sim_reset(sims[0], props + prop_off[0], nprops[0], stream, err)
+                         : pbn::sims_reset_batch(sims, count, props, nprops, prop_off, w, stream, err);
+    if (rc0) return fail(rc0, err);
+    for (uint32_t i = 0; i < count; ++i) {
+        runs[i].sim = sims[i];
+        const pbn::MachineParams P = pbn::make_params(sims[i], opts, r[i], conf[i]);
         for (uint32_t q = 0; q < nprops[i]; ++q) runs[i].machines.emplace_back(P, q);
     }
     std::vector<pbn::SimRun *> ptrs;
     for (auto &x : runs) ptrs.push_back(&x);
-    hipStream_t stream = (hipStream_t)hip_stream;
-    // every simulation of one batch runs on the batch's stream
-    for (uint32_t i = 0; i < count; ++i)
-        if (sims[i]->stream != stream) {
-            int rc = sync(sims[i]->stream);
-            if (rc) return rc;
-        }
-    static thread_local pbn::Workspace ws;
-    pbn::Workspace &w = count == 1 ? sims[0]->ws : ws;
-    int rc = pbn::run_to_completion(ptrs, w, stream, err);
+    int rc = pbn::run_lanes(ptrs, w, stream, err);
+    if (!rc) rc = sync(stream);
     if (rc) return fail(rc, err);
     for (uint32_t i = 0; i < count; ++i)
         for (uint32_t q = 0; q < nprops[i]; ++q) out[prop_off[i] + q] = runs[i].machines[q].result();
@@ -454,7 +457,7 @@ int pbn_server_step(pbn_server *srv, uint32_t *active, uint32_t *waiting, uint32
                                 srv->arena_base + off, rq->bytes, srv->stream, err);
         std::vector<pbn_pattern> pats(rq->nodes.size());
         for (size_t q = 0; q < pats.size(); ++q) pats[q] = {(uint32_t)rq->nodes[q].size(), rq->nodes[q].data(), rq->vals[q].data()};
-        if (!rc) rc = pbn::sim_reset(rq->sim.get(), pats.data(), (uint32_t)pats.size(), err);
+        if (!rc) rc = pbn::sim_reset(rq->sim.get(), pats.data(), (uint32_t)pats.size(), srv->stream, err);
         if (rc) return fail(rc, err);
         rq->run.sim = rq->sim.get();
         const pbn::MachineParams P = pbn::make_params(rq->sim.get(), &rq->opts, rq->r, rq->conf);

@@ -26,8 +26,10 @@
 //   Sec. 4.2  every state set runs its own machine on the shared chains;
 //           the chains grow to the smallest pending requirement.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
+#include <thread>
 
 #include "pbn_driver.h"
 
@@ -69,8 +71,37 @@ int Workspace::ensure(size_t items, size_t queries, size_t bsum, std::string &er
     return PBN_OK;
 }
 
+int Workspace::ensure_stage(size_t count, std::string &err)
+{
+    if (count <= cap_stage) return PBN_OK;
+    const size_t nc = std::max<size_t>(count, 2 * cap_stage);
+    if (d_stage) (void)hipFree(d_stage);
+    if (h_stage) (void)hipHostFree(h_stage);
+    if (d_dst) (void)hipFree(d_dst);
+    if (h_dst) (void)hipHostFree(h_dst);
+    d_stage = h_stage = nullptr;
+    d_dst = h_dst = nullptr;
+    cap_stage = 0;
+    if (hipMalloc((void **)&d_stage, nc * sizeof(DevSim)) != hipSuccess ||
+        hipHostMalloc((void **)&h_stage, nc * sizeof(DevSim), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void **)&d_dst, nc * sizeof(DevSim *)) != hipSuccess ||
+        hipHostMalloc((void **)&h_dst, nc * sizeof(DevSim *), hipHostMallocDefault) != hipSuccess) {
+        err = "staging allocation";
+        return PBN_ENOMEM;
+    }
+    cap_stage = nc;
+    return PBN_OK;
+}
+
 void Workspace::release()
 {
+    if (d_stage) (void)hipFree(d_stage);
+    if (h_stage) (void)hipHostFree(h_stage);
+    if (d_dst) (void)hipFree(d_dst);
+    if (h_dst) (void)hipHostFree(h_dst);
+    d_stage = h_stage = nullptr;
+    d_dst = h_dst = nullptr;
+    cap_stage = 0;
     if (d_items) (void)hipFree(d_items);
     if (h_items) (void)hipHostFree(h_items);
     if (d_queries) (void)hipFree(d_queries);
@@ -423,10 +454,10 @@ int sim_setup(pbn_sim *sim, const Net &net, uint32_t omega, uint64_t seed, uint3
         err = "blob upload";
         return PBN_EDEVICE;
     }
-    return sim_reset(sim, nullptr, 0, err);
+    return sim_reset(sim, nullptr, 0, stream, err);
 }
 
-int sim_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops, std::string &err)
+int sim_prepare_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops, std::string &err)
 {
     if (nprops > sim->max_props) { err = "more state sets than max_props"; return PBN_EINVAL; }
     DevSim &d = sim->desc;
@@ -477,14 +508,41 @@ int sim_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops, std::stri
     sim->nprops = nprops;
     sim->len = 0;
     sim->t_done = 0;
-    if (hipMemcpyAsync(sim->d_desc, &d, sizeof(DevSim), hipMemcpyHostToDevice, sim->stream) != hipSuccess) {
+    return PBN_OK;
+}
+
+int sim_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops, hipStream_t stream, std::string &err)
+{
+    int rc = sim_prepare_reset(sim, props, nprops, err);
+    if (rc) return rc;
+    if (hipMemcpyAsync(sim->d_desc, &sim->desc, sizeof(DevSim), hipMemcpyHostToDevice, stream) != hipSuccess) {
         err = "descriptor upload";
         return PBN_EDEVICE;
     }
-    // the descriptor copy is from pageable memory; make it complete before d goes away
-    if (hipStreamSynchronize(sim->stream) != hipSuccess) { err = "sync"; return PBN_EDEVICE; }
-    return launch_init(sim->d_desc, sim->omega, sim->net.W, sim->stream, err);
+    // the copy reads pageable memory that the next reset rewrites
+    if (hipStreamSynchronize(stream) != hipSuccess) { err = "sync"; return PBN_EDEVICE; }
+    return launch_init(sim->d_desc, sim->omega, sim->net.W, stream, err);
 }
+
+int sims_reset_batch(pbn_sim *const *sims, uint32_t count, const pbn_pattern *props, const uint32_t *nprops,
+                     const uint32_t *prop_off, Workspace &ws, hipStream_t stream, std::string &err)
+{
+    int rc = ws.ensure_stage(count, err);
+    if (rc) return rc;
+    for (uint32_t i = 0; i < count; ++i) {
+        if ((rc = sim_prepare_reset(sims[i], props + prop_off[i], nprops[i], err))) return rc;
+        ws.h_stage[i] = sims[i]->desc;
+        ws.h_dst[i] = sims[i]->d_desc;
+    }
+    // h_stage is pinned and rewritten only by the next batch, after its predecessor synchronised
+    if (hipMemcpyAsync(ws.d_stage, ws.h_stage, count * sizeof(DevSim), hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(ws.d_dst, ws.h_dst, count * sizeof(DevSim *), hipMemcpyHostToDevice, stream) != hipSuccess) {
+        err = "descriptor upload";
+        return PBN_EDEVICE;
+    }
+    return launch_setup(ws.d_stage, ws.d_dst, count, stream, err);
+}
+
 
 void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin,
                       std::vector<StepItem> &items)
@@ -529,7 +587,11 @@ void choose_kernel(const Net &net, StepItem &it)
     it.kernel = 0;
     it.lds = 0;
     if (g_kernel_mode == 1 || !net.bitsliced) return;
-    uint32_t G = net.n <= 256 ? 1 : (net.n <= 1024 ? 2 : 4);
+    // about two 16-node blocks of draws per wave: the per-transition critical
+    // path shrinks with n while small networks keep single-wave blocks
+    const uint32_t nblk = (net.n + 15) / 16;
+    uint32_t G = 1;
+    while (G < 16 && 2 * G * 2 <= nblk) G *= 2;
     if (g_waves_override) G = g_waves_override;
     const size_t lds = bs_lds_bytes(net.n, net.msel_total, G);
     if (lds > 160 * 1024) return;
@@ -577,7 +639,8 @@ uint32_t lds_class(uint32_t lds)
 
 }  // namespace
 
-int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream, std::string &err)
+int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream, std::string &err,
+                 bool allow_fork)
 {
     if (items.empty()) return PBN_OK;
     int rc = ws.ensure(items.size(), 0, 0, err);
@@ -632,8 +695,8 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
         if (g.kernel == 0) return launch_step(d, (uint32_t)g.count, g.maxW, s, err);
         return launch_step_bs(d, (uint32_t)g.count, g.kernel, g.lds, s, err);
     };
-    if (groups.size() == 1) {
-        rc = launch_group(groups[0], stream);
+    if (groups.size() == 1 || !allow_fork) {
+        for (size_t g = 0; g < groups.size() && !rc; ++g) rc = launch_group(groups[g], stream);
     } else {
         // largest groups first, spread over the pool's streams, joined back
         std::sort(groups.begin(), groups.end(), [](const Group &a, const Group &b) { return a.cost > b.cost; });
@@ -754,8 +817,25 @@ MachineParams make_params(const pbn_sim *sim, const pbn_opts *opts, double r, do
     return p;
 }
 
-int run_round(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err)
+// Transitions of one slice: about tick_us of the step kernel for this network,
+// from a model of the per-transition latency of one 64-chain block (the
+// per-node work divided over the block's waves), in multiples of 32.
+uint64_t slice_len(const pbn_sim *sim, double tick_us)
 {
+    StepItem probe{};
+    choose_kernel(sim->net, probe);
+    const double n = sim->net.n;
+    const double lat_us = probe.kernel ? 1.0 + 0.35 * n / probe.kernel : 1.0 + 1.0 * n;
+    const double q = std::floor(tick_us / lat_us / 32.0) * 32.0;
+    return (uint64_t)std::max(32.0, q);
+}
+
+int round_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, RoundCtx &ctx, std::string &err,
+                bool allow_fork, double tick_us)
+{
+    ctx.owners.clear();
+    ctx.kinds.clear();
+    ctx.pending = false;
     // 1. extensions for runs with no request ready at their current length
     std::vector<StepItem> items;
     for (SimRun *run : runs) {
@@ -771,14 +851,14 @@ int run_round(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
         if (!ready) {
             if (target > sim->max_len) { err = "request beyond the bit-stream capacity"; return PBN_ELIMIT; }
             if (sim->t_done + (target - sim->len) >= (1ull << 32)) { err = "transition index limit"; return PBN_ELIMIT; }
-            sim_extend_items(sim, 0, target - sim->len, 1, items);
+            uint64_t ext = target - sim->len;
+            if (tick_us > 0.0) ext = std::min(ext, slice_len(sim, tick_us));
+            sim_extend_items(sim, 0, ext, 1, items);
         }
     }
-    int rc = launch_items(items, ws, stream, err);
+    int rc = launch_items(items, ws, stream, err, allow_fork);
     if (rc) return rc;
     // 2. queries for every ready request
-    struct Owner { SimRun *run; size_t mi; uint64_t off; };
-    std::vector<Owner> owners;
     std::vector<Query> qs;
     uint64_t bsum_total = 0;
     for (SimRun *run : runs) {
@@ -796,7 +876,8 @@ int run_round(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
             q.m = rq.m;
             q.out_off = bsum_total;
             if (rq.kind == kQueryBatch) bsum_total += (uint64_t)run->sim->omega * rq.m;
-            owners.push_back({run, mi, q.out_off});
+            ctx.owners.push_back({run, mi, q.out_off});
+            ctx.kinds.push_back(rq.kind);
             qs.push_back(q);
         }
     }
@@ -810,15 +891,39 @@ int run_round(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
         hipSuccess) { err = "result download"; return PBN_EDEVICE; }
     if (bsum_total && hipMemcpyAsync(ws.h_bsum, ws.d_bsum, bsum_total * sizeof(int32_t), hipMemcpyDeviceToHost,
                                      stream) != hipSuccess) { err = "batch download"; return PBN_EDEVICE; }
-    hipError_t e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) { err = std::string("round sync: ") + hipGetErrorString(e); return PBN_EDEVICE; }
-    for (size_t i = 0; i < owners.size(); ++i) {
-        Machine &m = owners[i].run->machines[owners[i].mi];
-        const uint64_t L = owners[i].run->sim->len;
-        if (qs[i].kind == kQueryWindow) m.feed_window(ws.h_win[i], L);
-        else m.feed_batch(ws.h_bsum + owners[i].off, L);
+    if (!ctx.done && hipEventCreateWithFlags(&ctx.done, hipEventDisableTiming) != hipSuccess) {
+        err = "round event";
+        return PBN_EDEVICE;
     }
+    if (hipEventRecord(ctx.done, stream) != hipSuccess) { err = "round event"; return PBN_EDEVICE; }
+    ctx.pending = true;
     return PBN_OK;
+}
+
+void round_end(Workspace &ws, RoundCtx &ctx)
+{
+    for (size_t i = 0; i < ctx.owners.size(); ++i) {
+        Machine &m = ctx.owners[i].run->machines[ctx.owners[i].mi];
+        const uint64_t L = ctx.owners[i].run->sim->len;
+        if (ctx.kinds[i] == kQueryWindow) m.feed_window(ws.h_win[i], L);
+        else m.feed_batch(ws.h_bsum + ctx.owners[i].off, L);
+    }
+    ctx.owners.clear();
+    ctx.kinds.clear();
+    ctx.pending = false;
+}
+
+int run_round(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err)
+{
+    RoundCtx ctx;
+    int rc = round_begin(runs, ws, stream, ctx, err);
+    if (!rc && ctx.pending) {
+        hipError_t e = hipEventSynchronize(ctx.done);
+        if (e != hipSuccess) { err = std::string("round sync: ") + hipGetErrorString(e); rc = PBN_EDEVICE; }
+        else round_end(ws, ctx);
+    }
+    if (ctx.done) (void)hipEventDestroy(ctx.done);
+    return rc;
 }
 
 int run_to_completion(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err)
@@ -831,6 +936,141 @@ int run_to_completion(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t st
         int rc = run_round(runs, ws, stream, err);
         if (rc) return rc;
     }
+}
+
+// Lanes: one stream each (three, the hardware queues left beside the caller's),
+// every lane with its own asynchronous round loop.  Networks go to lanes by
+// step-kernel class (16 waves, 8 waves, the rest), so one launch serves one
+// class; an empty lane takes half of the busiest one.  Rounds are time-sliced:
+// an extension advances at most about kTickUs of kernel time per round, so a
+// network that needs a long extension never holds back the decisions of the
+// others in its lane, and every round returns the results of the networks
+// whose extension completed in it.
+namespace {
+constexpr double kTickUs = 5000.0;
+struct Lane {
+    std::vector<SimRun *> runs;
+    hipStream_t stream = nullptr;
+    Workspace ws;
+    RoundCtx ctx;
+    bool finished() const
+    {
+        for (SimRun *r : runs)
+            if (!r->finished()) return false;
+        return true;
+    }
+};
+struct LanePool {
+    static constexpr int kN = 3;
+    hipEvent_t ev[kN] = {};
+    std::vector<std::unique_ptr<Lane>> lane;
+    bool ready = false;
+    int init(std::string &err)
+    {
+        if (ready) return PBN_OK;
+        for (int i = 0; i < kN; ++i) {
+            lane.emplace_back(new Lane());
+            if (hipStreamCreateWithFlags(&lane.back()->stream, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) {
+                err = "lane streams";
+                return PBN_EDEVICE;
+            }
+        }
+        ready = true;
+        return PBN_OK;
+    }
+};
+LanePool &lane_pool()
+{
+    static LanePool p;
+    return p;
+}
+}  // namespace
+
+int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err)
+{
+    if (runs.size() < 2) return run_to_completion(runs, ws, stream, err);
+    LanePool &P = lane_pool();
+    int rc = P.init(err);
+    if (rc) return rc;
+    const int nl = LanePool::kN;
+    for (int k = 0; k < nl; ++k) P.lane[k]->runs.clear();
+    std::vector<SimRun *> order(runs);
+    std::stable_sort(order.begin(), order.end(),
+                     [](const SimRun *a, const SimRun *b) { return a->sim->net.n < b->sim->net.n; });
+    for (SimRun *r : order) {
+        StepItem probe{};
+        choose_kernel(r->sim->net, probe);
+        const int k = probe.kernel == 16 ? 0 : probe.kernel == 8 ? 1 : 2;
+        P.lane[k]->runs.push_back(r);
+    }
+    auto work = [](const Lane &L) {
+        double w = 0.0;
+        for (const SimRun *r : L.runs) w += (double)r->sim->net.n * r->sim->omega;
+        return w;
+    };
+    for (int k = 0; k < nl; ++k) {
+        if (!P.lane[k]->runs.empty()) continue;
+        int big = 0;
+        for (int j = 1; j < nl; ++j)
+            if (work(*P.lane[j]) > work(*P.lane[big])) big = j;
+        std::vector<SimRun *> &from = P.lane[big]->runs;
+        if (from.size() < 2) continue;
+        std::vector<SimRun *> keep;
+        for (size_t i = 0; i < from.size(); ++i) (i % 2 ? P.lane[k]->runs : keep).push_back(from[i]);
+        from.swap(keep);
+    }
+    // lane streams start after everything queued so far on the caller's stream
+    hipEvent_t start;
+    if (hipEventCreateWithFlags(&start, hipEventDisableTiming) != hipSuccess) { err = "event"; return PBN_EDEVICE; }
+    (void)hipEventRecord(start, stream);
+    for (int k = 0; k < nl; ++k) (void)hipStreamWaitEvent(P.lane[k]->stream, start, 0);
+    for (;;) {
+        bool any_pending = false, all_done = true;
+        for (int k = 0; k < nl; ++k) {
+            Lane &L = *P.lane[k];
+            if (L.ctx.pending) { any_pending = true; all_done = false; continue; }
+            if (L.finished()) continue;
+            all_done = false;
+            if ((rc = round_begin(L.runs, L.ws, L.stream, L.ctx, err, false, kTickUs))) break;
+            if (L.ctx.pending) any_pending = true;
+        }
+        if (rc || all_done) break;
+        if (!any_pending) continue;
+        // wait for the first lane whose round completes
+        bool progressed = false;
+        while (!progressed) {
+            for (int k = 0; k < nl; ++k) {
+                Lane &L = *P.lane[k];
+                if (!L.ctx.pending) continue;
+                hipError_t e = hipEventQuery(L.ctx.done);
+                if (e == hipSuccess) {
+                    round_end(L.ws, L.ctx);
+                    progressed = true;
+                } else if (e != hipErrorNotReady) {
+                    err = std::string("lane round: ") + hipGetErrorString(e);
+                    rc = PBN_EDEVICE;
+                    progressed = true;
+                    break;
+                }
+            }
+            if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        }
+        if (rc) break;
+    }
+    // drain and join back into the caller's stream
+    for (int k = 0; k < nl; ++k) {
+        Lane &L = *P.lane[k];
+        if (L.ctx.pending) {
+            (void)hipEventSynchronize(L.ctx.done);
+            L.ctx.pending = false;
+        }
+        (void)hipEventRecord(P.ev[k], L.stream);
+        (void)hipStreamWaitEvent(stream, P.ev[k], 0);
+        L.runs.clear();
+    }
+    (void)hipEventDestroy(start);
+    return rc;
 }
 
 }  // namespace pbn

@@ -23,8 +23,11 @@ struct Workspace {
     Query *d_queries = nullptr, *h_queries = nullptr;
     WindowResult *d_win = nullptr, *h_win = nullptr;
     int32_t *d_bsum = nullptr, *h_bsum = nullptr;
-    size_t cap_items = 0, cap_q = 0, cap_bsum = 0;
+    DevSim *d_stage = nullptr, *h_stage = nullptr;
+    DevSim **d_dst = nullptr, **h_dst = nullptr;
+    size_t cap_items = 0, cap_q = 0, cap_bsum = 0, cap_stage = 0;
     int ensure(size_t items, size_t queries, size_t bsum, std::string &err);
+    int ensure_stage(size_t count, std::string &err);
     void release();
     ~Workspace() { release(); }
 };
@@ -96,7 +99,11 @@ namespace pbn {
 size_t sim_bytes(const Net &net, uint32_t omega, uint32_t max_props, uint64_t max_len);
 int sim_setup(pbn_sim *sim, const Net &net, uint32_t omega, uint64_t seed, uint32_t max_props,
               uint64_t max_len, void *dev_buf, size_t dev_bytes, hipStream_t stream, std::string &err);
-int sim_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops, std::string &err);
+int sim_prepare_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops, std::string &err);
+int sim_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops, hipStream_t stream, std::string &err);
+// Reset many simulations with one descriptor upload and one setup launch on stream.
+int sims_reset_batch(pbn_sim *const *sims, uint32_t count, const pbn_pattern *props, const uint32_t *nprops,
+                     const uint32_t *prop_off, Workspace &ws, hipStream_t stream, std::string &err);
 // Append the step items that extend sim by `steps` recorded positions.
 void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin,
                       std::vector<StepItem> &items);
@@ -112,7 +119,23 @@ MachineParams make_params(const pbn_sim *sim, const pbn_opts *opts, double r, do
 
 // One round over all runs: extension launch for the runs that wait for
 // positions, reduction launch for every ready request, one synchronisation.
+// round_begin enqueues a round and records ctx.done; round_end feeds the
+// results to the machines once ctx.done has completed.
+struct RoundCtx {
+    struct Owner { SimRun *run; size_t mi; uint64_t off; };
+    std::vector<Owner> owners;
+    std::vector<uint32_t> kinds;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+// tick_us > 0 limits each extension to a slice of about that much kernel time.
+int round_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, RoundCtx &ctx, std::string &err,
+                bool allow_fork = true, double tick_us = 0.0);
+void round_end(Workspace &ws, RoundCtx &ctx);
 int run_round(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err);
+// Many simulations: lanes by step-kernel class, each with its own stream and
+// asynchronous, time-sliced round loop (run_to_completion for one simulation).
+int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err);
 // Rounds until every run is finished.
 int run_to_completion(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err);
 
@@ -133,6 +156,7 @@ void choose_kernel(const Net &net, StepItem &it);
 void set_kernel_mode(int mode, uint32_t waves);
 
 // Launch step items for several sims (sorted by cost) on stream.
-int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream, std::string &err);
+int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream, std::string &err,
+                 bool allow_fork = true);
 
 }  // namespace pbn

@@ -30,7 +30,7 @@ struct Net {
     // Bit-sliced schedule (networks with k <= 6):
     //   nd_meta[n]   l(i) | (offset of node i's selection masks) << 8
     //   nd_tb[n]     top bytes of T_1..T_3 (l <= 4), byte j = T_{j+1} >> 24
-    //   blk_sel[nb]  1 if 16-node block b holds a node with l > 1
+    //   blk_sel[nb]  largest predictor count l of the 16-node block b
     //   predictor slots sorted by k, F_pad = 64 * ceil(F/64):
     //   fs_node      node of the slot (kNoNode for padding)
     //   fs_tt_lo/hi  truth table replicated to 2^K bits (K = the slot group's max k)
@@ -50,7 +50,7 @@ struct Net {
 
 constexpr uint32_t kNoNode = 0xFFFFFFFFu, kNoMask = 0xFFFFFFFFu;
 constexpr uint32_t kBsMaxK = 6;          // bit-sliced evaluation handles k <= 6
-constexpr uint32_t kQCap = 512;          // tie-queue entries per wave
+constexpr uint32_t kQCap = 192;          // tie-queue entries per wave (bit-sliced kernel)
 
 int parse_and_compile(const char *text, size_t len, Net &out, std::string &err);
 
@@ -115,6 +115,8 @@ struct WindowResult {
 
 // ------------------------------------------------------------ launches (.hip)
 int launch_init(const DevSim *dsim, uint32_t omega, uint32_t W, void *stream, std::string &err);
+// Descriptors staged in device memory copied to their simulations, initial states written.
+int launch_setup(const DevSim *d_staging, DevSim *const *d_dst, uint32_t count, void *stream, std::string &err);
 int launch_step(const StepItem *d_items, uint32_t nitems, uint32_t max_W, void *stream,
                 std::string &err);
 // Bit-sliced trajectory kernel: G waves per 64-chain block, lds bytes of LDS.

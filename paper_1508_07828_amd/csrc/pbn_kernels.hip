@@ -42,6 +42,34 @@ __global__ void k_init(const DevSim *__restrict__ sim)
     }
 }
 
+// Many simulations at once: block b copies descriptor b from a staging array
+// to its simulation's buffer and writes that simulation's initial states.
+__global__ void __launch_bounds__(256) k_setup(const DevSim *__restrict__ staging, DevSim *const *__restrict__ dst)
+{
+    const DevSim *src = staging + blockIdx.x;
+    DevSim *d = ((DevSim *const PBN_CAS *)dst)[blockIdx.x];
+    const PBN_CAS uint32_t *from = (const PBN_CAS uint32_t *)src;
+    PBN_GAS uint32_t *to = (PBN_GAS uint32_t *)d;
+    for (uint32_t w = threadIdx.x; w < sizeof(DevSim) / 4; w += blockDim.x) to[w] = from[w];
+    const View v = load_view(src);
+    const uint32_t omega = v.omega, W = v.W, n = v.n, quads = (W + 3) / 4;
+    for (uint32_t g = threadIdx.x; g < omega * quads; g += blockDim.x) {
+        const uint32_t c = g % omega, q = g / omega;
+        uint32_t w4[4];
+        philox4(0u, c, q, kTagInit, v.key, w4);
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+            const uint32_t w = 4 * q + j;
+            if (w < W) {
+                uint32_t val = w4[j];
+                const uint32_t nb = n - 32 * w;
+                if (nb < 32) val &= (1u << nb) - 1u;
+                v.state[(size_t)w * omega + c] = val;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ step
 
 // Perturbation pass over all nodes of one chain at transition t.  With
@@ -332,6 +360,13 @@ int launch_init(const DevSim *dsim, uint32_t omega, uint32_t W, void *stream, st
     const uint32_t total = omega * ((W + 3) / 4);
     hipLaunchKernelGGL(k_init, dim3((total + 255) / 256), dim3(256), 0, (hipStream_t)stream, dsim);
     return check(hipGetLastError(), "k_init launch", err);
+}
+
+int launch_setup(const DevSim *d_staging, DevSim *const *d_dst, uint32_t count, void *stream, std::string &err)
+{
+    if (count == 0) return PBN_OK;
+    hipLaunchKernelGGL(k_setup, dim3(count), dim3(256), 0, (hipStream_t)stream, d_staging, d_dst);
+    return check(hipGetLastError(), "k_setup launch", err);
 }
 
 int launch_step(const StepItem *d_items, uint32_t nitems, uint32_t max_W, void *stream, std::string &err)

@@ -251,7 +251,7 @@ void build_bitsliced_schedule(Net &net)
         uint32_t tb = 0;
         for (uint32_t j = 0; j + 1 < l && j < 3; ++j) tb |= (net.fn_thr[a + j] >> 24) << (8 * j);
         net.nd_tb[i] = tb;
-        if (l > 1) net.blk_sel[i / 16] = 1;
+        net.blk_sel[i / 16] = std::max(net.blk_sel[i / 16], l);
         net.msel_total += l - 1;
     }
     if (!net.bitsliced) return;

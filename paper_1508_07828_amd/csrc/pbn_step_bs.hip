@@ -1,24 +1,34 @@
 // Bit-sliced trajectory kernel (gfx950, wave64).
 //
-// One block of G waves advances 64 chains.  State is bit-sliced in LDS: S[i]
-// holds node i of all 64 chains (bit = lane = chain).  Per transition:
-//   A  lane = chain: the waves share the 16-node blocks; each lane draws its
-//      chain's perturbation and selection bytes; wave ballots turn the byte
-//      comparisons into 64-chain masks (perturbation flips into Gm[i],
-//      selection masks m_j = [u < T_j] into M); byte ties that need the
-//      24-bit refinement are queued per wave and resolved 64 at a time
+// One block of G waves (G = blockDim.x / 64, 1..16) advances 64 chains.  State
+// is bit-sliced in LDS: S[i] holds node i of all 64 chains (bit = lane =
+// chain).  Per transition:
+//   A  lane = chain: the waves share the 16-node blocks.  Each lane draws its
+//      chain's perturbation and selection bytes for the block (one Philox
+//      evaluation each).  Selection masks m_j = [u < T_j] come from one ballot
+//      per (node, threshold) and are written whole into M.  Perturbations are
+//      rare: bytes below the primary threshold flip at once (only when
+//      p >= 2^-8), bytes equal to it are ties.  Ties of either kind are
+//      queued per lane and block as bit flags and resolved with the 24-bit
+//      refinement words, 64 queue entries per pass
 //   B  lane = node: Gm[i] := P & (S[i] ^ gamma_i), P = perturbed chains
 //   C  lane = predictor slot (sorted by parent count): K-input multiplexer
 //      tree over the parents' masks, restricted to the chains that selected
 //      this predictor and were not perturbed, OR-ed into Gm[node]
-//   D  record the state-set indicators; clear S (next step's gamma) and M;
+//   D  record the state-set indicators; clear S (the next step's gamma);
 //      swap S and Gm
-// LDS (u64 words): S[n], Gm[n], M[msel_total], Pw[G], then the u32 queues.
+// LDS (u64 words): S[n], Gm[n], M[msel_total], Pw[G], then per wave a queue of
+// kQCap entries (three u32 arrays: header, flags low, flags high).
 // Lanes beyond the item's chain count run along on their own bit positions and
 // are never stored.
 #include "pbn_device.h"
 
 namespace pbn {
+
+// v_writelane: lane `lane` of `old` takes the wave-uniform value `src`.
+__device__ uint32_t amdgcn_writelane(uint32_t src, uint32_t lane, uint32_t old) __asm("llvm.amdgcn.writelane.i32");
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // What the bit-sliced kernel reads, with as few live pointers as possible.
 struct BsView {
@@ -94,61 +104,108 @@ __device__ __forceinline__ void lds_or(uint64_t *p, uint64_t v)
     atomicOr((unsigned long long *)p, (unsigned long long)v);
 }
 
-// Queue entry: node (16 bits) | j (6) << 16 | kind (1) << 22 | lane (6) << 23.
-__device__ __forceinline__ void resolve_queue(const BsView &v, uint32_t t, uint32_t chain0, uint32_t *Q, uint32_t qlen,
-                                              uint64_t *Gm, uint64_t *M, uint64_t *Pw_mine, uint32_t lane)
+// Bit 7 of byte j of the result is set iff byte j of x equals the byte m
+// (m4 = m * 0x01010101).  No carry crosses a byte, so every byte is exact.
+__device__ __forceinline__ uint32_t bytes_eq(uint32_t x, uint32_t m4)
 {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    for (uint32_t e = lane; e < qlen; e += 64) {
-        const uint32_t ent = Q[e];
-        const uint32_t node = ent & 0xFFFFu, j = (ent >> 16) & 63u, kind = (ent >> 22) & 1u, cl = ent >> 23;
-        const uint64_t bit = 1ull << cl;
-        const uint32_t r24 = refine24(v.key, t, chain0 + cl, node, kind ? kTagSel : kTagPert);
-        if (kind == 0) {
-            if (r24 < (v.p_thr & 0xFFFFFFu)) {
-                lds_or(&Gm[node], bit);
-                lds_or(Pw_mine, bit);
-            }
-        } else {
-            const uint32_t T = v.fn_thr[v.nd_first[node] + j];
-            if (r24 < (T & 0xFFFFFFu)) lds_or(&M[(v.nd_info[2 * node] >> 8) + j], bit);
+    const uint32_t y = x ^ m4;
+    return ~(((y & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | y | 0x7F7F7F7Fu);
+}
+
+// The four byte flags of bytes_eq as bits 0..3.
+__device__ __forceinline__ uint32_t gather4(uint32_t z)
+{
+    uint32_t b = (z >> 7) & 0x01010101u;   // bits 0, 8, 16, 24
+    b |= b >> 7;                            // + bits 1 (byte 1) and 17 (byte 3)
+    b |= b >> 14;                           // + bits 2 (byte 2) and 3 (byte 3)
+    return b & 0xFu;
+}
+
+// Set bit `pos` (compile-time after unrolling) of the 64-bit flag pair.
+__device__ __forceinline__ void set_flag(bool on, uint32_t pos, uint32_t &lo, uint32_t &hi)
+{
+    if (pos < 32) lo |= on ? (1u << pos) : 0u;
+    else hi |= on ? (1u << (pos - 32)) : 0u;
+}
+
+// Queue entry: header kind (1 bit) | lane (6) << 1 | block << 7, flags lo/hi.
+//   kind 0: perturbation ties, flag k = node 16 b + k
+//   kind 1: selection ties, flag 3 k + j = threshold j (< 3) of node 16 b + k
+__device__ __forceinline__ void push(bool mine, uint32_t hdr, uint32_t flo, uint32_t fhi, uint32_t *Q,
+                                     uint32_t &qlen)
+{
+    const uint64_t who = __ballot(mine);
+    if (who) {
+        if (mine) {
+            const uint32_t pos = qlen + __builtin_amdgcn_mbcnt_hi((uint32_t)(who >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)who, 0u));
+            Q[pos] = hdr;
+            Q[kQCap + pos] = flo;
+            Q[2 * kQCap + pos] = fhi;
         }
+        qlen += (uint32_t)__popcll(who);
+    }
+}
+
+// Resolve queued ties with the refinement words (stream tag + 1), lane = entry.
+__device__ __forceinline__ void resolve(const BsView &v, uint32_t t, uint32_t chain0, const uint32_t *Q,
+                                        uint32_t qlen, uint64_t *Gm, uint64_t *M, uint64_t *Pw_mine, uint32_t lane)
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const uint32_t pthr24 = v.p_thr & 0xFFFFFFu;
+    for (uint32_t e = lane; e < qlen; e += 64) {
+        const uint32_t hdr = Q[e];
+        const uint32_t kind = hdr & 1u, cl = (hdr >> 1) & 63u, b = hdr >> 7;
+        uint64_t f = (uint64_t)Q[kQCap + e] | ((uint64_t)Q[2 * kQCap + e] << 32);
+        const uint64_t bit = 1ull << cl;
+        const uint32_t tag = (kind ? kTagSel : kTagPert) + 1;
+        uint32_t rq = 0xFFFFFFFFu, r[4] = {0u, 0u, 0u, 0u};
+        bool flipped = false;
+        while (f) {
+            const uint32_t x = (uint32_t)__builtin_ctzll(f);
+            f &= f - 1;
+            const uint32_t k = kind ? x / 3 : x, j = kind ? x - 3 * k : 0u;
+            const uint32_t i = 16 * b + k;
+            if ((i >> 2) != rq) {
+                rq = i >> 2;
+                philox4(t, chain0 + cl, rq, tag, v.key, r);
+            }
+            const uint32_t r24 = pick4(r, i & 3u) & 0xFFFFFFu;
+            if (kind == 0) {
+                if (r24 < pthr24) {
+                    lds_or(&Gm[i], bit);
+                    flipped = true;
+                }
+            } else {
+                const uint32_t T = v.fn_thr[v.nd_first[i] + j];
+                if (r24 < (T & 0xFFFFFFu)) lds_or(&M[(v.nd_info[2 * i] >> 8) + j], bit);
+            }
+        }
+        if (flipped) lds_or(Pw_mine, bit);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-__device__ __forceinline__ void enqueue(uint64_t tie, uint32_t payload, uint32_t lane, uint32_t *Q, uint32_t &qlen,
-                                        const BsView &v, uint32_t t, uint32_t chain0, uint64_t *Gm, uint64_t *M,
-                                        uint64_t *Pw_mine)
+// Selection threshold j (< 3) of node k: the mask of chains whose byte lies
+// below the threshold's top byte goes to lane k of (al, ah); equal bytes are
+// ties (flag 3 k + j).
+__device__ __forceinline__ void sel_threshold(uint32_t byte, uint32_t tb, uint32_t k, uint32_t j, uint32_t &al,
+                                              uint32_t &ah, uint32_t &flo, uint32_t &fhi)
 {
-    const uint32_t cnt = (uint32_t)__popcll(tie);
-    if (qlen + cnt > kQCap) {
-        resolve_queue(v, t, chain0, Q, qlen, Gm, M, Pw_mine, lane);
-        qlen = 0;
-    }
-    if ((tie >> lane) & 1ull) {
-        const uint32_t pos = qlen + (uint32_t)__popcll(tie & ((1ull << lane) - 1ull));
-        Q[pos] = payload | (lane << 23);
-    }
-    qlen += cnt;
-}
-
-// Put the 64-bit uniform value m into lane k of (lo, hi).
-__device__ __forceinline__ void put_lane(uint32_t &lo, uint32_t &hi, uint64_t m, uint32_t k, uint32_t lane)
-{
-    const bool mine = lane == k;
-    lo = mine ? (uint32_t)m : lo;
-    hi = mine ? (uint32_t)(m >> 32) : hi;
+    const uint64_t lt = __ballot(byte < tb);
+    al = amdgcn_writelane((uint32_t)lt, k, al);
+    ah = amdgcn_writelane((uint32_t)(lt >> 32), k, ah);
+    set_flag(byte == tb, 3 * k + j, flo, fhi);
 }
 
 extern __shared__ uint64_t lds_bs[];
 
-template <int G>
-__global__ void __launch_bounds__(64 * G) k_step_bs(const StepItem *__restrict__ items)
+__global__ void __launch_bounds__(1024) k_step_bs(const StepItem *__restrict__ items)
 {
     const StepItem it = load_item(items, blockIdx.x);
     const BsView v = load_bs_view(it.sim);
     const uint32_t n = v.n, W = v.W, omega = v.omega;
+    const uint32_t G = blockDim.x >> 6;
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     const uint32_t chain0 = it.chain0;
     const uint32_t c = chain0 + lane;
@@ -157,7 +214,7 @@ __global__ void __launch_bounds__(64 * G) k_step_bs(const StepItem *__restrict__
     uint64_t *Gm = lds_bs + n;
     uint64_t *M = lds_bs + 2 * n;
     uint64_t *Pw = M + v.msel_total;
-    uint32_t *Q = (uint32_t *)(Pw + G) + wave * kQCap;
+    uint32_t *Q = (uint32_t *)(Pw + G) + wave * 3 * kQCap;
     const uint64_t words_cap = v.d->words_cap;
 
     // transpose the chains' packed words into node masks
@@ -190,7 +247,7 @@ __global__ void __launch_bounds__(64 * G) k_step_bs(const StepItem *__restrict__
     }
     __syncthreads();
 
-    const uint32_t p_thr = v.p_thr, thr8 = p_thr >> 24;
+    const uint32_t p_thr = v.p_thr, thr8 = p_thr >> 24, thr8x4 = thr8 * 0x01010101u;
     const uint32_t nblk = v.nblk, F_pad = v.F_pad;
     const uint32_t total = it.nburn + it.nrec * it.thin;
     uint32_t since = 0;
@@ -199,104 +256,97 @@ __global__ void __launch_bounds__(64 * G) k_step_bs(const StepItem *__restrict__
         // ---- A: draws, lane = chain
         uint64_t P_acc = 0;
         uint32_t qlen = 0;
-        for (uint32_t b = wave; b < nblk; b += G) {
+        for (uint32_t b = wave;; b += G) {
+            const bool last = b >= nblk;
+            // a block queues at most 128 entries: resolve before the queue could overflow
+            if (qlen != 0 && (last || qlen + 128 > kQCap)) {
+                resolve(v, t, chain0, Q, qlen, Gm, M, &Pw[wave], lane);
+                qlen = 0;
+            }
+            if (last) break;
             const uint32_t i0 = 16 * b, ib = min(16u, n - i0);
-            const uint32_t has_sel = v.blk_sel[b];
+            const uint32_t lmax = v.blk_sel[b];
             // node metadata of the block, one node per lane, fetched ahead of the draws
             uint32_t my_meta = 0, my_tb = 0;
-            if (lane < ib) {
+            if (lmax >= 2 && lane < ib) {
                 my_meta = v.nd_info[2 * (i0 + lane)];
                 my_tb = v.nd_info[2 * (i0 + lane) + 1];
             }
             uint32_t wp[4];
             philox4(t, c, b, kTagPert, v.key, wp);
+            uint32_t tie = 0;
 #pragma unroll
-            for (uint32_t q = 0; q < 4; ++q) {
-                if (4 * q < ib) {
-                    uint32_t x = wp[q];
-                    if (ib - 4 * q < 4) x |= 0xFFFFFFFFu << (8 * (ib - 4 * q));   // no such nodes
-                    // byte == thr8 needs the refinement, byte < thr8 perturbs outright
-                    bool any = true;
-                    if (thr8 == 0) any = __ballot(((x - 0x01010101u) & ~x & 0x80808080u) != 0) != 0;
-                    if (any) {
+            for (uint32_t q = 0; q < 4; ++q) tie |= gather4(bytes_eq(wp[q], thr8x4)) << (4 * q);
+            if (ib < 16) tie &= (1u << ib) - 1u;
+            if (thr8 > 0) {
+                // bytes below the primary threshold flip at once
 #pragma unroll
-                        for (uint32_t bb = 0; bb < 4; ++bb) {
-                            const uint32_t k = 4 * q + bb;
-                            if (k < ib) {
-                                const uint32_t byte = (x >> (8 * bb)) & 0xFFu;
-                                if (thr8 > 0) {
-                                    const uint64_t d1 = __ballot(byte < thr8);
-                                    if (d1) {
-                                        if (lane == 0) lds_or(&Gm[i0 + k], d1);
-                                        P_acc |= d1;
-                                    }
-                                }
-                                const uint64_t tie = __ballot(byte == thr8);
-                                if (tie) enqueue(tie, i0 + k, lane, Q, qlen, v, t, chain0, Gm, M, &Pw[wave]);
-                            }
+                for (uint32_t k = 0; k < 16; ++k) {
+                    if (k < ib) {
+                        const uint32_t byte = (wp[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+                        const uint64_t d1 = __ballot(byte < thr8);
+                        if (d1) {
+                            if (lane == 0) lds_or(&Gm[i0 + k], d1);
+                            P_acc |= d1;
                         }
                     }
                 }
             }
-            if (has_sel) {
+            push(tie != 0, (lane << 1) | (b << 7), tie, 0u, Q, qlen);
+            if (lmax >= 2) {
                 uint32_t ws[4];
                 philox4(t, c, b, kTagSel, v.key, ws);
-                // masks of thresholds 1..3 of node k collect in lane k
-                uint32_t m0l = 0, m0h = 0, m1l = 0, m1h = 0, m2l = 0, m2h = 0;
+                uint32_t a0l = 0, a0h = 0, a1l = 0, a1h = 0, a2l = 0, a2h = 0, flo = 0, fhi = 0;
 #pragma unroll
                 for (uint32_t k = 0; k < 16; ++k) {
                     if (k < ib) {
-                        const uint32_t meta = __builtin_amdgcn_readlane(my_meta, k);
-                        const uint32_t l = meta & 0xFFu;
+                        const uint32_t l = __builtin_amdgcn_readlane(my_meta, k) & 0xFFu;
                         if (l >= 2) {
-                            const uint32_t i = i0 + k;
                             const uint32_t tbs = __builtin_amdgcn_readlane(my_tb, k);
                             const uint32_t byte = (ws[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-                            {
-                                const uint32_t tb = tbs & 0xFFu;
-                                put_lane(m0l, m0h, __ballot(byte < tb), k, lane);
-                                const uint64_t eq = __ballot(byte == tb);
-                                if (eq) enqueue(eq, i | (1u << 22), lane, Q, qlen, v, t, chain0, Gm, M, &Pw[wave]);
-                            }
-                            if (l >= 3) {
-                                const uint32_t tb = (tbs >> 8) & 0xFFu;
-                                put_lane(m1l, m1h, __ballot(byte < tb), k, lane);
-                                const uint64_t eq = __ballot(byte == tb);
-                                if (eq) enqueue(eq, i | (1u << 16) | (1u << 22), lane, Q, qlen, v, t, chain0, Gm, M, &Pw[wave]);
-                            }
-                            if (l >= 4) {
-                                const uint32_t tb = (tbs >> 16) & 0xFFu;
-                                put_lane(m2l, m2h, __ballot(byte < tb), k, lane);
-                                const uint64_t eq = __ballot(byte == tb);
-                                if (eq) enqueue(eq, i | (2u << 16) | (1u << 22), lane, Q, qlen, v, t, chain0, Gm, M, &Pw[wave]);
-                            }
-                            // more than four predictors: thresholds 4.. straight from fn_thr
-                            for (uint32_t j = 3; j + 1 < l; ++j) {
-                                const uint32_t tb = v.fn_thr[v.nd_first[i] + j] >> 24;
-                                const uint64_t lt = __ballot(byte < tb);
-                                if (lane == 0) lds_or(&M[(meta >> 8) + j], lt);
-                                const uint64_t eq = __ballot(byte == tb);
-                                if (eq) enqueue(eq, i | (j << 16) | (1u << 22), lane, Q, qlen, v, t, chain0, Gm, M, &Pw[wave]);
-                            }
+                            sel_threshold(byte, tbs & 0xFFu, k, 0, a0l, a0h, flo, fhi);
+                            if (l >= 3) sel_threshold(byte, (tbs >> 8) & 0xFFu, k, 1, a1l, a1h, flo, fhi);
+                            if (l >= 4) sel_threshold(byte, (tbs >> 16) & 0xFFu, k, 2, a2l, a2h, flo, fhi);
                         }
                     }
                 }
                 if (lane < ib) {
                     const uint32_t l = my_meta & 0xFFu, moff = my_meta >> 8;
-                    if (l >= 2) lds_or(&M[moff], ((uint64_t)m0h << 32) | m0l);
-                    if (l >= 3) lds_or(&M[moff + 1], ((uint64_t)m1h << 32) | m1l);
-                    if (l >= 4) lds_or(&M[moff + 2], ((uint64_t)m2h << 32) | m2l);
+                    if (l >= 2) M[moff] = ((uint64_t)a0h << 32) | a0l;
+                    if (l >= 3) M[moff + 1] = ((uint64_t)a1h << 32) | a1l;
+                    if (l >= 4) M[moff + 2] = ((uint64_t)a2h << 32) | a2l;
+                }
+                push((flo | fhi) != 0, 1u | (lane << 1) | (b << 7), flo, fhi, Q, qlen);
+                if (lmax >= 5) {
+                    // thresholds 4.. of nodes with more than four predictors,
+                    // straight from fn_thr with their ties refined in place
+                    for (uint32_t k = 0; k < ib; ++k) {
+                        const uint32_t meta = __builtin_amdgcn_readlane(my_meta, k);
+                        const uint32_t l = meta & 0xFFu;
+                        if (l < 5) continue;
+                        const uint32_t i = i0 + k;
+                        const uint32_t byte = (pick4(ws, k >> 2) >> (8 * (k & 3))) & 0xFFu;
+                        for (uint32_t j = 3; j + 1 < l; ++j) {
+                            const uint32_t T = v.fn_thr[v.nd_first[i] + j];
+                            const uint32_t tb = T >> 24;
+                            bool below = byte < tb;
+                            const bool eq = byte == tb;
+                            if (__ballot(eq)) {
+                                if (eq) below = refine24(v.key, t, c, i, kTagSel) < (T & 0xFFFFFFu);
+                            }
+                            const uint64_t lt = __ballot(below);
+                            if (lane == 0) M[(meta >> 8) + j] = lt;
+                        }
+                    }
                 }
             }
         }
-        if (qlen) resolve_queue(v, t, chain0, Q, qlen, Gm, M, &Pw[wave], lane);
         if (P_acc && lane == 0) lds_or(&Pw[wave], P_acc);
         __syncthreads();
 
         // ---- B: S' := P & (S ^ gamma), lane = node
         uint64_t P = 0;
-#pragma unroll
-        for (int w = 0; w < G; ++w) P |= Pw[w];
+        for (uint32_t w = 0; w < G; ++w) P |= Pw[w];
         for (uint32_t i = threadIdx.x; i < n; i += 64 * G) Gm[i] = P & (S[i] ^ Gm[i]);
         __syncthreads();
 
@@ -305,9 +355,10 @@ __global__ void __launch_bounds__(64 * G) k_step_bs(const StepItem *__restrict__
         for (uint32_t s0 = 64 * wave; s0 < F_pad; s0 += 64 * G) {
             const uint32_t slot = s0 + lane;
             const uint32_t K = v.fg_K[s0 >> 6];
-            const cu32 rec = v.fs_rec + 8 * (size_t)slot;
-            const uint32_t node = rec[0], tlo = rec[1], thi = rec[2], mlo = rec[3], mhi = rec[4];
-            const uint32_t p01 = rec[5], p23 = rec[6], p45 = rec[7];
+            const PBN_CAS u32x4 *rec = (const PBN_CAS u32x4 *)(v.fs_rec + 8 * (size_t)slot);
+            const u32x4 r0 = rec[0], r1 = rec[1];
+            const uint32_t node = r0.x, tlo = r0.y, thi = r0.z, mlo = r0.w, mhi = r1.x;
+            const uint32_t p01 = r1.y, p23 = r1.z, p45 = r1.w;
             uint64_t x[6];
             x[0] = S[p01 & 0xFFFFu];
             x[1] = K > 1 ? S[p01 >> 16] : 0ull;
@@ -325,7 +376,8 @@ __global__ void __launch_bounds__(64 * G) k_step_bs(const StepItem *__restrict__
         }
         __syncthreads();
 
-        // ---- D: record, clear, swap (Pw and M were last read before C's barrier)
+        // ---- D: record, clear, swap (Pw was last read before C's barrier;
+        // every selection mask is rewritten whole in the next A)
         if (s >= it.nburn && ++since == it.thin) {
             since = 0;
             if (wave == 0) {
@@ -355,7 +407,6 @@ __global__ void __launch_bounds__(64 * G) k_step_bs(const StepItem *__restrict__
             ++pos;
         }
         for (uint32_t i = threadIdx.x; i < n; i += 64 * G) S[i] = 0ull;
-        for (uint32_t i = threadIdx.x; i < v.msel_total; i += 64 * G) M[i] = 0ull;
         if (threadIdx.x < G) Pw[threadIdx.x] = 0ull;
         uint64_t *tmp = S; S = Gm; Gm = tmp;
         __syncthreads();
@@ -386,36 +437,27 @@ static int check_bs(hipError_t e, const char *what, std::string &err)
 
 size_t bs_lds_bytes(uint32_t n, uint32_t msel_total, uint32_t G)
 {
-    return (size_t)8 * (2 * (size_t)n + msel_total + G) + (size_t)4 * kQCap * G;
-}
-
-template <int G>
-static int launch_bs_g(const StepItem *d_items, uint32_t nitems, size_t lds, hipStream_t s, std::string &err)
-{
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_step_bs<G>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
-        if (e != hipSuccess) return check_bs(e, "k_step_bs LDS attribute", err);
-    }
-    hipLaunchKernelGGL(k_step_bs<G>, dim3(nitems), dim3(64 * G), lds, s, d_items);
-    return check_bs(hipGetLastError(), "k_step_bs launch", err);
+    return (size_t)8 * (2 * (size_t)n + msel_total + G) + (size_t)4 * 3 * kQCap * G;
 }
 
 int launch_step_bs(const StepItem *d_items, uint32_t nitems, uint32_t G, size_t lds, void *stream, std::string &err)
 {
     if (nitems == 0) return PBN_OK;
+    if (G != 1 && G != 2 && G != 4 && G != 8 && G != 16) {
+        err = "bit-sliced kernel: waves per block must be 1, 2, 4, 8 or 16";
+        return PBN_EINVAL;
+    }
     if (lds > 160 * 1024) {
         err = "bit-sliced state exceeds LDS";
         return PBN_ELIMIT;
     }
-    hipStream_t s = (hipStream_t)stream;
-    switch (G) {
-    case 1: return launch_bs_g<1>(d_items, nitems, lds, s, err);
-    case 2: return launch_bs_g<2>(d_items, nitems, lds, s, err);
-    case 4: return launch_bs_g<4>(d_items, nitems, lds, s, err);
-    case 8: return launch_bs_g<8>(d_items, nitems, lds, s, err);
-    default: return launch_bs_g<16>(d_items, nitems, lds, s, err);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_step_bs, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return check_bs(e, "k_step_bs LDS attribute", err);
     }
+    hipLaunchKernelGGL(k_step_bs, dim3(nitems), dim3(64 * G), lds, (hipStream_t)stream, d_items);
+    return check_bs(hipGetLastError(), "k_step_bs launch", err);
 }
 
 }  // namespace pbn

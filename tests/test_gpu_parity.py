@@ -227,6 +227,24 @@ def test_batched_equals_oracle():
         assert_same_result(g[0], want[0], j.name)
 
 
+def test_batched_buckets_equal_oracle():
+    # enough networks for the asynchronous per-bucket rounds (16 or more)
+    jobs = sorted(ps.batched(), key=lambda j: j.net.n * j.chains)[:24]
+    say("bucketed batched estimate of {} networks".format(len(jobs)))
+    nets = [pkg.Network(ps.to_text(j.net)) for j in jobs]
+    sims = [pkg.Simulation(nt, j.chains, j.seed, max_props=1, max_len=CAP) for nt, j in zip(nets, jobs)]
+    got = pkg.batch_estimate(sims, [j.patterns for j in jobs], [j.r for j in jobs],
+                             [j.confidence for j in jobs], psrf_max=1.1)
+    for j, g in zip(jobs, got):
+        want = drivers.solve(ps.to_text(j.net), j.chains, j.seed, j.patterns, j.r, j.confidence, 1.1, cap=CAP)
+        assert_same_result(g[0], want[0], j.name)
+    # a second batch on the same simulations restarts them and gives the same results
+    again = pkg.batch_estimate(sims, [j.patterns for j in jobs], [j.r for j in jobs],
+                               [j.confidence for j in jobs], psrf_max=1.1)
+    for a, b in zip(got, again):
+        assert_same_result(b[0], a[0], "rerun")
+
+
 def test_server_isolation():
     jobs = sorted(ps.serving(limit=40), key=lambda j: j.net.n)[:8]
     say("server with {} requests".format(len(jobs)))
