@@ -71,6 +71,22 @@ int Workspace::ensure(size_t items, size_t queries, size_t bsum, std::string &er
     return PBN_OK;
 }
 
+int Workspace::before_write(hipEvent_t &ev, bool &in_flight, std::string &err)
+{
+    if (!in_flight) return PBN_OK;
+    if (hipEventSynchronize(ev) != hipSuccess) { err = "table copy"; return PBN_EDEVICE; }
+    in_flight = false;
+    return PBN_OK;
+}
+
+int Workspace::after_copy(hipEvent_t &ev, bool &in_flight, hipStream_t stream, std::string &err)
+{
+    if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) { err = "event"; return PBN_EDEVICE; }
+    if (hipEventRecord(ev, stream) != hipSuccess) { err = "event"; return PBN_EDEVICE; }
+    in_flight = true;
+    return PBN_OK;
+}
+
 int Workspace::ensure_stage(size_t count, std::string &err)
 {
     if (count <= cap_stage) return PBN_OK;
@@ -95,6 +111,10 @@ int Workspace::ensure_stage(size_t count, std::string &err)
 
 void Workspace::release()
 {
+    if (ev_items) (void)hipEventSynchronize(ev_items), (void)hipEventDestroy(ev_items);
+    if (ev_queries) (void)hipEventSynchronize(ev_queries), (void)hipEventDestroy(ev_queries);
+    ev_items = ev_queries = nullptr;
+    items_in_flight = queries_in_flight = false;
     if (d_stage) (void)hipFree(d_stage);
     if (h_stage) (void)hipHostFree(h_stage);
     if (d_dst) (void)hipFree(d_dst);
@@ -545,7 +565,7 @@ int sims_reset_batch(pbn_sim *const *sims, uint32_t count, const pbn_pattern *pr
 
 
 void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin,
-                      std::vector<StepItem> &items)
+                      std::vector<StepItem> &items, bool latency)
 {
     for (uint32_t c0 = 0; c0 < sim->omega; c0 += 64) {
         StepItem it{};
@@ -560,7 +580,7 @@ void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t t
         it.nodes = sim->net.n;
         it.ops_per_step = (float)sim->net.ops_per_step;
         it.philox_per_step = (float)sim->net.philox_per_step;
-        choose_kernel(sim->net, it);
+        choose_kernel(sim->net, it, latency);
         items.push_back(it);
     }
     sim->t_done += burn_in + steps * thin;
@@ -568,9 +588,12 @@ void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t t
 }
 
 // Kernel choice per item: the bit-sliced kernel when every predictor has
-// k <= 6 and its LDS fits, with 1, 2 or 4 waves sharing one 64-chain block as n
-// grows (shorter critical path per transition); the lane-per-chain kernel
-// otherwise.  kernel_mode forces one of them (testing and tuning).
+// k <= 6 and its LDS fits, else the lane-per-chain kernel.  The waves per
+// 64-chain block follow measured per-transition cost on the device: for
+// throughput (many blocks per CU) 2 waves below 40 nodes, 4 up to 600, 8
+// beyond; for latency (the chip holds every block of the work at once) 2, 8
+// or 16 waves, which shortens each transition's critical path.  kernel_mode
+// forces one kernel or wave count (testing and tuning).
 namespace {
 int g_kernel_mode = 0;     // 0 auto, 1 lane-per-chain, 2 bit-sliced
 uint32_t g_waves_override = 0;
@@ -582,17 +605,18 @@ void set_kernel_mode(int mode, uint32_t waves)
     g_waves_override = waves;
 }
 
-void choose_kernel(const Net &net, StepItem &it)
+uint32_t waves_for(uint32_t n, bool latency)
+{
+    if (latency) return n < 40 ? 2 : n < 150 ? 8 : 16;
+    return n < 40 ? 2 : n < 600 ? 4 : 8;
+}
+
+void choose_kernel(const Net &net, StepItem &it, bool latency)
 {
     it.kernel = 0;
     it.lds = 0;
     if (g_kernel_mode == 1 || !net.bitsliced) return;
-    // about two 16-node blocks of draws per wave: the per-transition critical
-    // path shrinks with n while small networks keep single-wave blocks
-    const uint32_t nblk = (net.n + 15) / 16;
-    uint32_t G = 1;
-    while (G < 16 && 2 * G * 2 <= nblk) G *= 2;
-    if (g_waves_override) G = g_waves_override;
+    uint32_t G = g_waves_override ? g_waves_override : waves_for(net.n, latency);
     const size_t lds = bs_lds_bytes(net.n, net.msel_total, G);
     if (lds > 160 * 1024) return;
     it.kernel = G;
@@ -628,14 +652,16 @@ StreamPool &stream_pool()
     return p;
 }
 
-uint32_t lds_class(uint32_t lds)
+// Launch class of a bit-sliced item: blocks per CU that its waves (at the
+// kernel's register use) and its LDS allow.  Items of one class share a launch
+// sized for the group's largest LDS without losing residency.
+uint32_t bs_class(uint32_t G, uint32_t lds)
 {
-    static const uint32_t cls[] = {8u << 10, 16u << 10, 24u << 10, 32u << 10, 48u << 10, 64u << 10,
-                                   96u << 10, 128u << 10, 160u << 10};
-    for (uint32_t c : cls)
-        if (lds <= c) return c;
-    return lds;
+    const uint32_t by_waves = std::max<uint32_t>(1, bs_waves_per_cu() / G);
+    const uint32_t by_lds = std::max<uint32_t>(1, (160u << 10) / std::max<uint32_t>(lds, 1));
+    return std::min(by_waves, by_lds);
 }
+
 
 }  // namespace
 
@@ -643,15 +669,16 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
                  bool allow_fork)
 {
     if (items.empty()) return PBN_OK;
-    int rc = ws.ensure(items.size(), 0, 0, err);
+    int rc = ws.before_write(ws.ev_items, ws.items_in_flight, err);
     if (rc) return rc;
+    if ((rc = ws.ensure(items.size(), 0, 0, err))) return rc;
     // groups of equal (kernel, LDS class); inside a group the longest items
     // first, since the hardware dispatches blocks roughly in order
     struct Key { uint32_t kernel, cls; double cost; size_t idx; };
     std::vector<Key> keys(items.size());
     for (size_t i = 0; i < items.size(); ++i) {
         const StepItem &it = items[i];
-        keys[i] = Key{it.kernel, it.kernel ? lds_class(it.lds) : 0u,
+        keys[i] = Key{it.kernel, it.kernel ? bs_class(it.kernel, it.lds) : 0u,
                       (double)(it.nburn + (uint64_t)it.nrec * it.thin) * (double)it.nodes, i};
     }
     std::stable_sort(keys.begin(), keys.end(), [](const Key &a, const Key &b) {
@@ -659,14 +686,13 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
         if (a.cls != b.cls) return a.cls < b.cls;
         return a.cost > b.cost;
     });
-    struct Group { size_t first, count; uint32_t kernel, lds, maxW; double cost; };
+    struct Group { size_t first, count; uint32_t kernel, cls, lds, maxW; double cost; };
     std::vector<Group> groups;
     for (size_t i = 0; i < keys.size(); ++i) {
         const StepItem &it = items[keys[i].idx];
         ws.h_items[i] = it;
-        if (groups.empty() || groups.back().kernel != keys[i].kernel ||
-            (keys[i].kernel && lds_class(groups.back().lds) != keys[i].cls)) {
-            groups.push_back(Group{i, 0, keys[i].kernel, 0, 1, 0.0});
+        if (groups.empty() || groups.back().kernel != keys[i].kernel || groups.back().cls != keys[i].cls) {
+            groups.push_back(Group{i, 0, keys[i].kernel, keys[i].cls, 0, 1, 0.0});
         }
         Group &g = groups.back();
         ++g.count;
@@ -679,6 +705,7 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
         err = "item upload";
         return PBN_EDEVICE;
     }
+    if ((rc = ws.after_copy(ws.ev_items, ws.items_in_flight, stream, err))) return rc;
     ProfileMark mark;
     if (profiling()) {
         for (const StepItem &it : items) {
@@ -820,22 +847,31 @@ MachineParams make_params(const pbn_sim *sim, const pbn_opts *opts, double r, do
 // Transitions of one slice: about tick_us of the step kernel for this network,
 // from a model of the per-transition latency of one 64-chain block (the
 // per-node work divided over the block's waves), in multiples of 32.
-uint64_t slice_len(const pbn_sim *sim, double tick_us)
+uint64_t slice_len(const pbn_sim *sim, double tick_us, bool latency)
 {
     StepItem probe{};
-    choose_kernel(sim->net, probe);
+    choose_kernel(sim->net, probe, latency);
     const double n = sim->net.n;
-    const double lat_us = probe.kernel ? 1.0 + 0.35 * n / probe.kernel : 1.0 + 1.0 * n;
+    // fitted to single-block timings: about 2.5 us plus 0.17 us per node and
+    // wave (0.25 us with 16 waves, whose barriers cost more)
+    const double per = probe.kernel == 16 ? 0.25 : 0.17;
+    const double lat_us = probe.kernel ? 2.5 + per * n / probe.kernel : 1.0 + 1.0 * n;
     const double q = std::floor(tick_us / lat_us / 32.0) * 32.0;
     return (uint64_t)std::max(32.0, q);
 }
 
 int round_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, RoundCtx &ctx, std::string &err,
-                bool allow_fork, double tick_us)
+                bool allow_fork, double tick_us, int latency)
 {
     ctx.owners.clear();
     ctx.kinds.clear();
     ctx.pending = false;
+    if (latency < 0) {
+        uint64_t groups = 0;
+        for (SimRun *run : runs)
+            if (!run->finished()) groups += (run->sim->omega + 63) / 64;
+        latency = groups <= kLatencyGroups;
+    }
     // 1. extensions for runs with no request ready at their current length
     std::vector<StepItem> items;
     for (SimRun *run : runs) {
@@ -852,8 +888,8 @@ int round_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, 
             if (target > sim->max_len) { err = "request beyond the bit-stream capacity"; return PBN_ELIMIT; }
             if (sim->t_done + (target - sim->len) >= (1ull << 32)) { err = "transition index limit"; return PBN_ELIMIT; }
             uint64_t ext = target - sim->len;
-            if (tick_us > 0.0) ext = std::min(ext, slice_len(sim, tick_us));
-            sim_extend_items(sim, 0, ext, 1, items);
+            if (tick_us > 0.0) ext = std::min(ext, slice_len(sim, tick_us, latency != 0));
+            sim_extend_items(sim, 0, ext, 1, items, latency != 0);
         }
     }
     int rc = launch_items(items, ws, stream, err, allow_fork);
@@ -881,11 +917,24 @@ int round_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, 
             qs.push_back(q);
         }
     }
-    if (qs.empty()) return PBN_OK;
+    if (qs.empty() && items.empty()) return PBN_OK;
+    if (qs.empty()) {
+        // extension only: the round still completes on an event, since the
+        // next round rewrites the pinned item table this one copies from
+        if (!ctx.done && hipEventCreateWithFlags(&ctx.done, hipEventDisableTiming) != hipSuccess) {
+            err = "round event";
+            return PBN_EDEVICE;
+        }
+        if (hipEventRecord(ctx.done, stream) != hipSuccess) { err = "round event"; return PBN_EDEVICE; }
+        ctx.pending = true;
+        return PBN_OK;
+    }
+    if ((rc = ws.before_write(ws.ev_queries, ws.queries_in_flight, err))) return rc;
     if ((rc = ws.ensure(0, qs.size(), bsum_total, err))) return rc;
     std::memcpy(ws.h_queries, qs.data(), qs.size() * sizeof(Query));
     if (hipMemcpyAsync(ws.d_queries, ws.h_queries, qs.size() * sizeof(Query), hipMemcpyHostToDevice, stream) !=
         hipSuccess) { err = "query upload"; return PBN_EDEVICE; }
+    if ((rc = ws.after_copy(ws.ev_queries, ws.queries_in_flight, stream, err))) return rc;
     if ((rc = launch_reduce(ws.d_queries, (uint32_t)qs.size(), ws.d_win, ws.d_bsum, stream, err))) return rc;
     if (hipMemcpyAsync(ws.h_win, ws.d_win, qs.size() * sizeof(WindowResult), hipMemcpyDeviceToHost, stream) !=
         hipSuccess) { err = "result download"; return PBN_EDEVICE; }
@@ -940,8 +989,8 @@ int run_to_completion(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t st
 
 // Lanes: one stream each (three, the hardware queues left beside the caller's),
 // every lane with its own asynchronous round loop.  Networks go to lanes by
-// step-kernel class (16 waves, 8 waves, the rest), so one launch serves one
-// class; an empty lane takes half of the busiest one.  Rounds are time-sliced:
+// step-kernel class (8 waves, 4 waves, the rest, for throughput), so one
+// launch serves one class; an empty lane takes half of the busiest one.  Rounds are time-sliced:
 // an extension advances at most about kTickUs of kernel time per round, so a
 // network that needs a long extension never holds back the decisions of the
 // others in its lane, and every round returns the results of the networks
@@ -1000,8 +1049,8 @@ int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
                      [](const SimRun *a, const SimRun *b) { return a->sim->net.n < b->sim->net.n; });
     for (SimRun *r : order) {
         StepItem probe{};
-        choose_kernel(r->sim->net, probe);
-        const int k = probe.kernel == 16 ? 0 : probe.kernel == 8 ? 1 : 2;
+        choose_kernel(r->sim->net, probe, false);
+        const int k = probe.kernel == 8 ? 0 : probe.kernel == 4 ? 1 : 2;
         P.lane[k]->runs.push_back(r);
     }
     auto work = [](const Lane &L) {
@@ -1027,12 +1076,17 @@ int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
     for (int k = 0; k < nl; ++k) (void)hipStreamWaitEvent(P.lane[k]->stream, start, 0);
     for (;;) {
         bool any_pending = false, all_done = true;
+        // latency mode once the unfinished work fits on the chip at once
+        uint64_t groups = 0;
+        for (SimRun *r : runs)
+            if (!r->finished()) groups += (r->sim->omega + 63) / 64;
+        const int latency = groups <= kLatencyGroups;
         for (int k = 0; k < nl; ++k) {
             Lane &L = *P.lane[k];
             if (L.ctx.pending) { any_pending = true; all_done = false; continue; }
             if (L.finished()) continue;
             all_done = false;
-            if ((rc = round_begin(L.runs, L.ws, L.stream, L.ctx, err, false, kTickUs))) break;
+            if ((rc = round_begin(L.runs, L.ws, L.stream, L.ctx, err, false, kTickUs, latency))) break;
             if (L.ctx.pending) any_pending = true;
         }
         if (rc || all_done) break;

@@ -26,7 +26,14 @@ struct Workspace {
     DevSim *d_stage = nullptr, *h_stage = nullptr;
     DevSim **d_dst = nullptr, **h_dst = nullptr;
     size_t cap_items = 0, cap_q = 0, cap_bsum = 0, cap_stage = 0;
+    // the last copies out of h_items / h_queries: the host waits for them
+    // before rewriting those pinned tables
+    hipEvent_t ev_items = nullptr, ev_queries = nullptr;
+    bool items_in_flight = false, queries_in_flight = false;
     int ensure(size_t items, size_t queries, size_t bsum, std::string &err);
+    // wait for the previous copy out of a pinned table, record the next one
+    int before_write(hipEvent_t &ev, bool &in_flight, std::string &err);
+    int after_copy(hipEvent_t &ev, bool &in_flight, hipStream_t stream, std::string &err);
     int ensure_stage(size_t count, std::string &err);
     void release();
     ~Workspace() { release(); }
@@ -105,8 +112,12 @@ int sim_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops, hipStream
 int sims_reset_batch(pbn_sim *const *sims, uint32_t count, const pbn_pattern *props, const uint32_t *nprops,
                      const uint32_t *prop_off, Workspace &ws, hipStream_t stream, std::string &err);
 // Append the step items that extend sim by `steps` recorded positions.
+// latency: pick the kernel shape for the shortest transition (the chip is not
+// full) rather than for throughput.
 void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin,
-                      std::vector<StepItem> &items);
+                      std::vector<StepItem> &items, bool latency);
+// Unfinished 64-chain groups up to which the scheduler picks latency shapes.
+constexpr uint64_t kLatencyGroups = 256;
 
 // A simulation together with the machines of its state sets.
 struct SimRun {
@@ -128,9 +139,10 @@ struct RoundCtx {
     hipEvent_t done = nullptr;
     bool pending = false;
 };
-// tick_us > 0 limits each extension to a slice of about that much kernel time.
+// tick_us > 0 limits each extension to a slice of about that much kernel time;
+// latency 1/0 forces the kernel shapes, -1 decides from the runs' chain groups.
 int round_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, RoundCtx &ctx, std::string &err,
-                bool allow_fork = true, double tick_us = 0.0);
+                bool allow_fork = true, double tick_us = 0.0, int latency = -1);
 void round_end(Workspace &ws, RoundCtx &ctx);
 int run_round(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err);
 // Many simulations: lanes by step-kernel class, each with its own stream and
@@ -152,7 +164,8 @@ void profile_set(bool on);
 void profile_clear();
 
 // Kernel selection for a step item (see pbn_driver.cpp) and its override.
-void choose_kernel(const Net &net, StepItem &it);
+void choose_kernel(const Net &net, StepItem &it, bool latency);
+uint32_t waves_for(uint32_t n, bool latency);
 void set_kernel_mode(int mode, uint32_t waves);
 
 // Launch step items for several sims (sorted by cost) on stream.

@@ -29,7 +29,8 @@ struct Net {
     std::vector<uint16_t> par;
     // Bit-sliced schedule (networks with k <= 6):
     //   nd_meta[n]   l(i) | (offset of node i's selection masks) << 8
-    //   nd_tb[n]     top bytes of T_1..T_3 (l <= 4), byte j = T_{j+1} >> 24
+    //   nd_tb[n]     top bytes of T_1..T_3, byte j = T_{j+1} >> 24 (j < min(l-1, 3)),
+    //                byte 3 = min(l, 255)
     //   blk_sel[nb]  largest predictor count l of the 16-node block b
     //   predictor slots sorted by k, F_pad = 64 * ceil(F/64):
     //   fs_node      node of the slot (kNoNode for padding)
@@ -123,6 +124,10 @@ int launch_step(const StepItem *d_items, uint32_t nitems, uint32_t max_W, void *
 int launch_step_bs(const StepItem *d_items, uint32_t nitems, uint32_t G, size_t lds, void *stream,
                    std::string &err);
 size_t bs_lds_bytes(uint32_t n, uint32_t msel_total, uint32_t G);
+// Waves of the bit-sliced kernel one CU holds at its register use.
+uint32_t bs_waves_per_cu();
+// Dynamic-LDS limit of a kernel raised to 160 KB (once per device).
+int allow_full_lds(const void *fn, std::string &err);
 int launch_reduce(const Query *d_queries, uint32_t nq, WindowResult *d_win, int32_t *d_bsum,
                   void *stream, std::string &err);
 

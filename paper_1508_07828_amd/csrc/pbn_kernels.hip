@@ -11,6 +11,10 @@
 // host from the exact aggregates.
 #include "pbn_device.h"
 
+#include <mutex>
+#include <set>
+#include <utility>
+
 namespace pbn {
 
 // Any byte of x strictly below m (1 <= m <= 128): classic SWAR test.
@@ -369,6 +373,26 @@ int launch_setup(const DevSim *d_staging, DevSim *const *d_dst, uint32_t count, 
     return check(hipGetLastError(), "k_setup launch", err);
 }
 
+// Raise a kernel's dynamic-LDS limit to the full 160 KB once per device and
+// kernel.  Setting the attribute can wait for running launches of the same
+// kernel, so it must not sit on the launch path.
+int allow_full_lds(const void *fn, std::string &err)
+{
+    static std::mutex mu;
+    static std::set<std::pair<const void *, int>> done;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        err = "hipGetDevice";
+        return PBN_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.count({fn, dev})) return PBN_OK;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return check(e, "LDS attribute", err);
+    done.insert({fn, dev});
+    return PBN_OK;
+}
+
 int launch_step(const StepItem *d_items, uint32_t nitems, uint32_t max_W, void *stream, std::string &err)
 {
     if (nitems == 0) return PBN_OK;
@@ -379,8 +403,8 @@ int launch_step(const StepItem *d_items, uint32_t nitems, uint32_t max_W, void *
         return PBN_ELIMIT;
     }
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_step, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return check(e, "k_step LDS attribute", err);
+        int rc = allow_full_lds((const void *)k_step, err);
+        if (rc) return rc;
     }
     hipLaunchKernelGGL(k_step, dim3(nitems), dim3(64), lds, (hipStream_t)stream, d_items, S);
     return check(hipGetLastError(), "k_step launch", err);

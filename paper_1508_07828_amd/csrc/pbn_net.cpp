@@ -250,7 +250,7 @@ void build_bitsliced_schedule(Net &net)
         net.nd_meta[i] = l | (net.msel_total << 8);
         uint32_t tb = 0;
         for (uint32_t j = 0; j + 1 < l && j < 3; ++j) tb |= (net.fn_thr[a + j] >> 24) << (8 * j);
-        net.nd_tb[i] = tb;
+        net.nd_tb[i] = tb | (std::min<uint32_t>(l, 255) << 24);
         net.blk_sel[i / 16] = std::max(net.blk_sel[i / 16], l);
         net.msel_total += l - 1;
     }

@@ -23,6 +23,8 @@
 // are never stored.
 #include "pbn_device.h"
 
+#include <algorithm>
+
 namespace pbn {
 
 // v_writelane: lane `lane` of `old` takes the wave-uniform value `src`.
@@ -66,18 +68,26 @@ __device__ __forceinline__ uint64_t bsel(uint64_t m, uint64_t a, uint64_t b)
     return (m & a) | (~m & b);          // a where m is set, else b
 }
 
+// Bit e of w as an all-zeros or all-ones word (one signed bit-field extract).
+__device__ __forceinline__ uint32_t bit_mask(uint32_t w, int e)
+{
+    return (uint32_t)(((int32_t)(w << (31 - e))) >> 31);
+}
+
 template <int K>
 __device__ __forceinline__ uint64_t mux_tree(uint32_t lo, uint32_t hi, const uint64_t *x)
 {
     constexpr int L = 1 << K;
     uint64_t r[L / 2];
+    const uint32_t x0l = (uint32_t)x[0], x0h = (uint32_t)(x[0] >> 32);
 #pragma unroll
     for (int m = 0; m < L / 2; ++m) {
         const int e0 = 2 * m, e1 = 2 * m + 1;
         const uint32_t w0 = e0 < 32 ? lo : hi, w1 = e1 < 32 ? lo : hi;
-        const uint64_t A = 0ull - (uint64_t)((w0 >> (e0 & 31)) & 1u);
-        const uint64_t B = 0ull - (uint64_t)((w1 >> (e1 & 31)) & 1u);
-        r[m] = bsel(x[0], B, A);
+        // leaves: table bits e0 / e1 broadcast to whole words, selected by x0
+        const uint32_t A = bit_mask(w0, e0 & 31), B = bit_mask(w1, e1 & 31);
+        const uint32_t rl = (x0l & B) | (~x0l & A), rh = (x0h & B) | (~x0h & A);
+        r[m] = ((uint64_t)rh << 32) | rl;
     }
 #pragma unroll
     for (int lev = 1; lev < K; ++lev) {
@@ -206,7 +216,9 @@ __global__ void __launch_bounds__(1024) k_step_bs(const StepItem *__restrict__ i
     const BsView v = load_bs_view(it.sim);
     const uint32_t n = v.n, W = v.W, omega = v.omega;
     const uint32_t G = blockDim.x >> 6;
-    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t lane = threadIdx.x & 63u;
+    // wave index as a scalar: block and slot loops branch on the scalar unit
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t chain0 = it.chain0;
     const uint32_t c = chain0 + lane;
     const bool active = lane < it.nchains;
@@ -249,6 +261,25 @@ __global__ void __launch_bounds__(1024) k_step_bs(const StepItem *__restrict__ i
 
     const uint32_t p_thr = v.p_thr, thr8 = p_thr >> 24, thr8x4 = thr8 * 0x01010101u;
     const uint32_t nblk = v.nblk, F_pad = v.F_pad;
+    // Small networks: at most one node block and one slot group per wave, whose
+    // metadata then stay in registers for the whole launch.
+    const bool res_a = nblk <= G, res_c = F_pad <= 64 * G;
+    uint32_t ra_lmax = 0, ra_meta = 0, ra_tb = 0;
+    if (res_a && wave < nblk) {
+        ra_lmax = v.blk_sel[wave];
+        if (ra_lmax >= 2 && lane < min(16u, n - 16 * wave)) {
+            ra_meta = v.nd_info[2 * (16 * wave + lane)];
+            ra_tb = v.nd_info[2 * (16 * wave + lane) + 1];
+        }
+    }
+    uint32_t rc_K = 1;
+    u32x4 rc0 = {0u, 0u, 0u, 0u}, rc1 = {0u, 0u, 0u, 0u};
+    if (res_c && 64 * wave < F_pad) {
+        rc_K = v.fg_K[wave];
+        const PBN_CAS u32x4 *rec = (const PBN_CAS u32x4 *)(v.fs_rec + 8 * (size_t)(64 * wave + lane));
+        rc0 = rec[0];
+        rc1 = rec[1];
+    }
     const uint32_t total = it.nburn + it.nrec * it.thin;
     uint32_t since = 0;
     for (uint32_t s = 0; s < total; ++s) {
@@ -265,10 +296,10 @@ __global__ void __launch_bounds__(1024) k_step_bs(const StepItem *__restrict__ i
             }
             if (last) break;
             const uint32_t i0 = 16 * b, ib = min(16u, n - i0);
-            const uint32_t lmax = v.blk_sel[b];
+            const uint32_t lmax = res_a ? ra_lmax : v.blk_sel[b];
             // node metadata of the block, one node per lane, fetched ahead of the draws
-            uint32_t my_meta = 0, my_tb = 0;
-            if (lmax >= 2 && lane < ib) {
+            uint32_t my_meta = ra_meta, my_tb = ra_tb;
+            if (!res_a && lmax >= 2 && lane < ib) {
                 my_meta = v.nd_info[2 * (i0 + lane)];
                 my_tb = v.nd_info[2 * (i0 + lane) + 1];
             }
@@ -300,9 +331,10 @@ __global__ void __launch_bounds__(1024) k_step_bs(const StepItem *__restrict__ i
 #pragma unroll
                 for (uint32_t k = 0; k < 16; ++k) {
                     if (k < ib) {
-                        const uint32_t l = __builtin_amdgcn_readlane(my_meta, k) & 0xFFu;
+                        // top bytes of T_1..T_3 and (byte 3) the predictor count
+                        const uint32_t tbs = __builtin_amdgcn_readlane(my_tb, k);
+                        const uint32_t l = tbs >> 24;
                         if (l >= 2) {
-                            const uint32_t tbs = __builtin_amdgcn_readlane(my_tb, k);
                             const uint32_t byte = (ws[k >> 2] >> (8 * (k & 3))) & 0xFFu;
                             sel_threshold(byte, tbs & 0xFFu, k, 0, a0l, a0h, flo, fhi);
                             if (l >= 3) sel_threshold(byte, (tbs >> 8) & 0xFFu, k, 1, a1l, a1h, flo, fhi);
@@ -354,9 +386,14 @@ __global__ void __launch_bounds__(1024) k_step_bs(const StepItem *__restrict__ i
         const uint64_t nP = ~P;
         for (uint32_t s0 = 64 * wave; s0 < F_pad; s0 += 64 * G) {
             const uint32_t slot = s0 + lane;
-            const uint32_t K = v.fg_K[s0 >> 6];
-            const PBN_CAS u32x4 *rec = (const PBN_CAS u32x4 *)(v.fs_rec + 8 * (size_t)slot);
-            const u32x4 r0 = rec[0], r1 = rec[1];
+            uint32_t K = rc_K;
+            u32x4 r0 = rc0, r1 = rc1;
+            if (!res_c) {
+                K = v.fg_K[s0 >> 6];
+                const PBN_CAS u32x4 *rec = (const PBN_CAS u32x4 *)(v.fs_rec + 8 * (size_t)slot);
+                r0 = rec[0];
+                r1 = rec[1];
+            }
             const uint32_t node = r0.x, tlo = r0.y, thi = r0.z, mlo = r0.w, mhi = r1.x;
             const uint32_t p01 = r1.y, p23 = r1.z, p45 = r1.w;
             uint64_t x[6];
@@ -435,6 +472,20 @@ static int check_bs(hipError_t e, const char *what, std::string &err)
     return PBN_EDEVICE;
 }
 
+uint32_t bs_waves_per_cu()
+{
+    static uint32_t cached = 0;
+    if (cached) return cached;
+    hipFuncAttributes a{};
+    uint32_t per_simd = 4;
+    if (hipFuncGetAttributes(&a, (const void *)k_step_bs) == hipSuccess && a.numRegs > 0) {
+        const uint32_t regs = (uint32_t)((a.numRegs + 7) / 8 * 8);
+        per_simd = std::min<uint32_t>(8, std::max<uint32_t>(1, 512 / regs));
+    }
+    cached = 4 * per_simd;
+    return cached;
+}
+
 size_t bs_lds_bytes(uint32_t n, uint32_t msel_total, uint32_t G)
 {
     return (size_t)8 * (2 * (size_t)n + msel_total + G) + (size_t)4 * 3 * kQCap * G;
@@ -452,9 +503,8 @@ int launch_step_bs(const StepItem *d_items, uint32_t nitems, uint32_t G, size_t 
         return PBN_ELIMIT;
     }
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_step_bs, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
-        if (e != hipSuccess) return check_bs(e, "k_step_bs LDS attribute", err);
+        int rc = allow_full_lds((const void *)k_step_bs, err);
+        if (rc) return rc;
     }
     hipLaunchKernelGGL(k_step_bs, dim3(nitems), dim3(64 * G), lds, (hipStream_t)stream, d_items);
     return check_bs(hipGetLastError(), "k_step_bs launch", err);

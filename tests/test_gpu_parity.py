@@ -6,6 +6,7 @@ integer decision of the procedures (psi, n, N, M, kappa, batches, chain
 length, status).  Floating point (R, the estimates, the Skart CI): within
 1e-12 relative, the tolerance stated for this path.
 """
+import dataclasses
 import sys
 
 import numpy as np
@@ -227,10 +228,10 @@ def test_batched_equals_oracle():
         assert_same_result(g[0], want[0], j.name)
 
 
-def test_batched_buckets_equal_oracle():
-    # enough networks for the asynchronous per-bucket rounds (16 or more)
+def test_batched_lanes_equal_oracle():
+    # many small networks: every lane's rounds, lanes rebalanced
     jobs = sorted(ps.batched(), key=lambda j: j.net.n * j.chains)[:24]
-    say("bucketed batched estimate of {} networks".format(len(jobs)))
+    say("laned batched estimate of {} networks".format(len(jobs)))
     nets = [pkg.Network(ps.to_text(j.net)) for j in jobs]
     sims = [pkg.Simulation(nt, j.chains, j.seed, max_props=1, max_len=CAP) for nt, j in zip(nets, jobs)]
     got = pkg.batch_estimate(sims, [j.patterns for j in jobs], [j.r for j in jobs],
@@ -243,6 +244,22 @@ def test_batched_buckets_equal_oracle():
                                [j.confidence for j in jobs], psrf_max=1.1)
     for a, b in zip(got, again):
         assert_same_result(b[0], a[0], "rerun")
+
+
+def test_sliced_rounds_equal_oracle():
+    # the largest networks take several time slices per extension (16-wave
+    # lane), beside small ones in the other lanes
+    big = sorted(ps.batched(), key=lambda j: -j.net.n)[:3]
+    small = sorted(ps.batched(), key=lambda j: j.net.n)[:3]
+    jobs = [dataclasses.replace(j, chains=96) for j in big] + small
+    say("sliced rounds: n = {}".format([j.net.n for j in jobs]))
+    nets = [pkg.Network(ps.to_text(j.net)) for j in jobs]
+    sims = [pkg.Simulation(nt, j.chains, j.seed, max_props=1, max_len=CAP) for nt, j in zip(nets, jobs)]
+    got = pkg.batch_estimate(sims, [j.patterns for j in jobs], [j.r for j in jobs],
+                             [j.confidence for j in jobs], psrf_max=1.1)
+    for j, g in zip(jobs, got):
+        want = drivers.solve(ps.to_text(j.net), j.chains, j.seed, j.patterns, j.r, j.confidence, 1.1, cap=CAP)
+        assert_same_result(g[0], want[0], j.name)
 
 
 def test_server_isolation():
