@@ -160,7 +160,14 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--waves", type=int, default=0, help="bit-sliced waves per block (0 = by n)")
+    ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter scale)")
+    ap.add_argument("--traffic-from", nargs=5, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE", "OUT"),
+                    help="turn rocprofv3 FETCH_SIZE/WRITE_SIZE runs into bytes per k_step_bs launch")
     args = ap.parse_args()
+    if args.traffic_from:
+        return traffic_from(*args.traffic_from)
+    if args.copy_probe:
+        return copy_probe()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs every simulation on a single MI355X "
               "(chains shard by id across GPUs by design, but no multi-GPU path is built)", file=sys.stderr)
@@ -213,12 +220,15 @@ def main() -> int:
     achieved = ops_per_launch / avg_launch_s
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32_OPS / 1e12, "unit": "Tops/s",
                 "frac": achieved / PEAK_INT32_OPS, "traffic": None,
-                "kernel": "k_step", "launches": int(prof["launches"]),
+                "kernel": "k_step_bs", "launches": int(prof["launches"]),
                 "avg_launch_ms": avg_launch_s * 1e3,
+                "alg_ops_per_launch": ops_per_launch,
                 "kernel_node_updates_per_s": prof["node_updates"] / (prof["kernel_ms"] / 1e3),
                 "philox_evals_per_s": prof["philox_evals"] / (prof["kernel_ms"] / 1e3),
-                "kernel_share_of_step": prof["kernel_ms"] / 1e3 / total_t}
-    tr = os.path.join(ROOT, "profiles", "k_step_traffic.json")
+                # launches of the three lanes overlap: the chip-wide rate over the timed region
+                "aggregate_tops": prof["alg_ops"] / total_t / 1e12,
+                "aggregate_frac": prof["alg_ops"] / total_t / PEAK_INT32_OPS}
+    tr = os.path.join(ROOT, "profiles", "k_step_bs_traffic.json")
     if os.path.exists(tr):
         info = json.load(open(tr))
         if info.get("kernel_source_sha") == kernel_sha():
@@ -272,8 +282,54 @@ def main() -> int:
 
 def kernel_sha() -> str:
     import hashlib
-    src = os.path.join(ROOT, "paper_1508_07828_amd", "csrc", "pbn_kernels.hip")
+    src = os.path.join(ROOT, "paper_1508_07828_amd", "csrc", "pbn_step_bs.hip")
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def copy_probe(mib: int = 1024, reps: int = 4) -> int:
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": mib << 20, "launches": reps}))
+    return 0
+
+
+def _counter_sum(csv_dir: str, kernel: str, counter: str):
+    import csv
+    import glob
+    total, n = 0.0, 0
+    for f in glob.glob(os.path.join(csv_dir, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if kernel in r["Kernel_Name"] and r["Counter_Name"] == counter:
+                total += float(r["Counter_Value"])
+                n += 1
+    return total, n
+
+
+def traffic_from(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy_write_dir: str, out: str) -> int:
+    """HBM bytes per k_step_bs launch from FETCH_SIZE / WRITE_SIZE runs (KiB per
+    dispatch), each scaled so that the plain copy reads and writes its size."""
+    f_k, n_kf = _counter_sum(fetch_dir, "k_step_bs", "FETCH_SIZE")
+    w_k, n_kw = _counter_sum(write_dir, "k_step_bs", "WRITE_SIZE")
+    f_c, n_cf = _counter_sum(copy_fetch_dir, "", "FETCH_SIZE")
+    w_c, n_cw = _counter_sum(copy_write_dir, "", "WRITE_SIZE")
+    copy_bytes = float(1024 << 20)
+    f_scale = copy_bytes / (f_c / n_cf * 1024.0)
+    w_scale = copy_bytes / (w_c / n_cw * 1024.0)
+    fetch = f_k / n_kf * 1024.0 * f_scale
+    write = w_k / n_kw * 1024.0 * w_scale
+    info = {"kernel": "k_step_bs", "kernel_source_sha": kernel_sha(), "dispatches": n_kf,
+            "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+            "bytes_per_launch": fetch + write, "fetch_scale": f_scale, "write_scale": w_scale}
+    with open(out, "w") as fh:
+        json.dump(info, fh, indent=1)
+    print(json.dumps(info))
+    return 0
 
 
 if __name__ == "__main__":

@@ -60,12 +60,13 @@ CASES = {
     "ragged_k7_p05": lambda: (_ragged_net(), 100, [((0, 1), (5, 0)), ((36, 1),)]),
     "ragged_k6_p05": lambda: (_ragged_net(37, 0.05, 6, 6), 100, [((0, 1), (5, 0)), ((36, 1),), ((2, 0),)]),
     "high_p": lambda: (_ragged_net(20, 0.6, 9, 4), 70, [((3, 1),)]),
+    "ragged_l6_k5": lambda: (ps.small_network(11, 45, l_max=6, k_max=5, p=0.02), 90, [((1, 1), (44, 0))]),
     "one_node": lambda: (ps.small_network(2, 1, l_max=2, k_max=1, p=0.3), 65, [((0, 1),)]),
     "n300_l4": lambda: (ps.random_network(np.random.default_rng(4), 300, (1, 4), (1, 6), 0.004), 130,
                         [((7, 1), (299, 0))]),
 }
 
-# (mode, waves): the lane-per-chain kernel and the bit-sliced kernel with 1, 2, 4 waves per block
+# (mode, waves): the lane-per-chain kernel and the bit-sliced kernel with 1 to 16 waves per block
 KERNELS = [("lane", 0), ("bitsliced", 1), ("bitsliced", 2), ("bitsliced", 4), ("bitsliced", 8),
            ("bitsliced", 16)]
 
