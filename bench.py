@@ -68,6 +68,7 @@ def run_serving(pkg, torch, seconds, rate, arena_bytes, serial_budget_s=20.0):
     srv = pkg.Server(arena_bytes)
     t0 = time.perf_counter()
     nxt, ids, finish = 0, {}, {}
+    pkg.profile_enable(True)
     pkg.profile_reset()
     rounds = 0
     while len(finish) < len(jobs):
@@ -93,6 +94,7 @@ def run_serving(pkg, torch, seconds, rate, arena_bytes, serial_budget_s=20.0):
             time.sleep(max(0.0, jobs[nxt].arrival - (time.perf_counter() - t0)))
     wall = time.perf_counter() - t0
     prof = pkg.profile_read()
+    pkg.profile_enable(False)
     lat = np.array([finish[i] - jobs[i].arrival for i in range(len(jobs))])
     results = [srv.poll(ids[i]) for i in range(len(jobs))]
     _, peak_mem = srv.memory()

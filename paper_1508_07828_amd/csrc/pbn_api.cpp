@@ -473,7 +473,9 @@ int pbn_server_step(pbn_server *srv, uint32_t *active, uint32_t *waiting, uint32
     std::vector<pbn::SimRun *> runs;
     for (ServeReq *rq : srv->active) runs.push_back(&rq->run);
     if (!runs.empty()) {
-        int rc = pbn::run_round(runs, srv->ws, srv->stream, err);
+        // time-sliced: a request that needs a long extension does not hold the
+        // others (or the next admissions) for its whole length
+        int rc = pbn::run_round(runs, srv->ws, srv->stream, err, pbn::kTickUs);
         if (rc) return fail(rc, err);
     }
     // retire finished requests and free their memory for the next admission

@@ -671,9 +671,8 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
     if (items.empty()) return PBN_OK;
     int rc = ws.before_write(ws.ev_items, ws.items_in_flight, err);
     if (rc) return rc;
-    if ((rc = ws.ensure(items.size(), 0, 0, err))) return rc;
-    // groups of equal (kernel, LDS class); inside a group the longest items
-    // first, since the hardware dispatches blocks roughly in order
+    // groups of equal (kernel, residency class); inside a group the longest
+    // items first, since the hardware dispatches blocks roughly in order
     struct Key { uint32_t kernel, cls; double cost; size_t idx; };
     std::vector<Key> keys(items.size());
     for (size_t i = 0; i < items.size(); ++i) {
@@ -688,39 +687,96 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
     });
     struct Group { size_t first, count; uint32_t kernel, cls, lds, maxW; double cost; };
     std::vector<Group> groups;
-    for (size_t i = 0; i < keys.size(); ++i) {
-        const StepItem &it = items[keys[i].idx];
-        ws.h_items[i] = it;
-        if (groups.empty() || groups.back().kernel != keys[i].kernel || groups.back().cls != keys[i].cls) {
-            groups.push_back(Group{i, 0, keys[i].kernel, keys[i].cls, 0, 1, 0.0});
+    std::vector<StepItem> laid;
+    laid.reserve(items.size() + 64);
+    for (size_t a = 0; a < keys.size();) {
+        size_t b = a;
+        while (b < keys.size() && keys[b].kernel == keys[a].kernel && keys[b].cls == keys[a].cls) ++b;
+        Group g{laid.size(), 0, keys[a].kernel, keys[a].cls, 0, 1, 0.0};
+        for (size_t i = a; i < b; ++i) {
+            const StepItem &it = items[keys[i].idx];
+            g.lds = std::max(g.lds, it.lds);
+            g.maxW = std::max(g.maxW, (it.nodes + 31) / 32);
+            g.cost += keys[i].cost * it.nchains;
         }
-        Group &g = groups.back();
-        ++g.count;
-        g.lds = std::max(g.lds, it.lds);
-        g.maxW = std::max(g.maxW, (it.nodes + 31) / 32);
-        g.cost += keys[i].cost * it.nchains;
+        if (g.kernel != 0 && b - a >= 2 * kXcds) {
+            // XCD-aware placement: block i of a launch runs on XCD i mod 8, so
+            // all blocks of one network go to one XCD (its records then live in
+            // one L2), networks spread over the XCDs by cost; short lists are
+            // padded with empty items, which exit at once
+            std::vector<std::vector<size_t>> per_sim;
+            std::vector<double> sim_cost;
+            std::vector<const DevSim *> sim_of;
+            for (size_t i = a; i < b; ++i) {
+                const DevSim *sp = items[keys[i].idx].sim;
+                size_t s_idx = 0;
+                while (s_idx < sim_of.size() && sim_of[s_idx] != sp) ++s_idx;
+                if (s_idx == sim_of.size()) {
+                    sim_of.push_back(sp);
+                    per_sim.emplace_back();
+                    sim_cost.push_back(0.0);
+                }
+                per_sim[s_idx].push_back(keys[i].idx);
+                sim_cost[s_idx] += keys[i].cost * items[keys[i].idx].nchains;
+            }
+            std::vector<size_t> sord(per_sim.size());
+            for (size_t i = 0; i < sord.size(); ++i) sord[i] = i;
+            std::stable_sort(sord.begin(), sord.end(), [&](size_t x, size_t y) { return sim_cost[x] > sim_cost[y]; });
+            std::vector<std::vector<size_t>> xl(kXcds);
+            std::vector<double> load(kXcds, 0.0);
+            for (size_t si : sord) {
+                const size_t x = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+                xl[x].insert(xl[x].end(), per_sim[si].begin(), per_sim[si].end());
+                load[x] += sim_cost[si];
+            }
+            size_t rows = 0;
+            for (auto &l : xl) {
+                std::stable_sort(l.begin(), l.end(), [&](size_t x, size_t y) {
+                    return (double)(items[x].nburn + (uint64_t)items[x].nrec * items[x].thin) * items[x].nodes >
+                           (double)(items[y].nburn + (uint64_t)items[y].nrec * items[y].thin) * items[y].nodes;
+                });
+                rows = std::max(rows, l.size());
+            }
+            StepItem empty = items[keys[a].idx];
+            empty.nchains = 0;
+            empty.nburn = empty.nrec = 0;
+            for (size_t r = 0; r < rows; ++r)
+                for (size_t x = 0; x < kXcds; ++x) laid.push_back(r < xl[x].size() ? items[xl[x][r]] : empty);
+        } else {
+            for (size_t i = a; i < b; ++i) laid.push_back(items[keys[i].idx]);
+        }
+        g.count = laid.size() - g.first;
+        groups.push_back(g);
+        a = b;
     }
-    if (hipMemcpyAsync(ws.d_items, ws.h_items, items.size() * sizeof(StepItem), hipMemcpyHostToDevice,
+    if ((rc = ws.ensure(laid.size(), 0, 0, err))) return rc;
+    std::memcpy(ws.h_items, laid.data(), laid.size() * sizeof(StepItem));
+    if (hipMemcpyAsync(ws.d_items, ws.h_items, laid.size() * sizeof(StepItem), hipMemcpyHostToDevice,
                        stream) != hipSuccess) {
         err = "item upload";
         return PBN_EDEVICE;
     }
     if ((rc = ws.after_copy(ws.ev_items, ws.items_in_flight, stream, err))) return rc;
-    ProfileMark mark;
-    if (profiling()) {
-        for (const StepItem &it : items) {
-            const double cs = (double)(it.nburn + (uint64_t)it.nrec * it.thin) * it.nchains;
-            mark.chain_steps += cs;
-            mark.node_updates += cs * it.nodes;
-            mark.ops += cs * it.ops_per_step;
-            mark.philox += cs * it.philox_per_step;
-        }
-        profile_begin(mark, stream);
-    }
+    // one profiling mark per kernel dispatch, on the stream it runs on
+    const bool prof_on = profiling();
     auto launch_group = [&](const Group &g, hipStream_t s) -> int {
         const StepItem *d = ws.d_items + g.first;
-        if (g.kernel == 0) return launch_step(d, (uint32_t)g.count, g.maxW, s, err);
-        return launch_step_bs(d, (uint32_t)g.count, g.kernel, g.lds, s, err);
+        ProfileMark mark;
+        if (prof_on) {
+            for (size_t i = g.first; i < g.first + g.count; ++i) {
+                const StepItem &it = ws.h_items[i];
+                const double cs = (double)(it.nburn + (uint64_t)it.nrec * it.thin) * it.nchains;
+                mark.chain_steps += cs;
+                mark.node_updates += cs * it.nodes;
+                mark.ops += cs * it.ops_per_step;
+                mark.philox += cs * it.philox_per_step;
+            }
+            profile_begin(mark, s);
+        }
+        const int r = g.kernel == 0 ? launch_step(d, (uint32_t)g.count, g.maxW, s, err)
+                                    : launch_step_bs(d, (uint32_t)g.count, g.kernel, g.lds, s, err);
+        if (prof_on) profile_end(mark, s);
+        return r;
     };
     if (groups.size() == 1 || !allow_fork) {
         for (size_t g = 0; g < groups.size() && !rc; ++g) rc = launch_group(groups[g], stream);
@@ -742,7 +798,6 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
             }
         }
     }
-    if (profiling()) profile_end(mark, stream);
     return rc;
 }
 
@@ -847,16 +902,22 @@ MachineParams make_params(const pbn_sim *sim, const pbn_opts *opts, double r, do
 // Transitions of one slice: about tick_us of the step kernel for this network,
 // from a model of the per-transition latency of one 64-chain block (the
 // per-node work divided over the block's waves), in multiples of 32.
-uint64_t slice_len(const pbn_sim *sim, double tick_us, bool latency)
+// Per-transition latency of one 64-chain block of this network, fitted to
+// single-block timings: about 2.5 us plus 0.17 us per node and wave (0.25 us
+// with 16 waves, whose barriers cost more); about 1 us per node for the
+// lane-per-chain kernel.
+double step_latency_us(const Net &net, bool latency)
 {
     StepItem probe{};
-    choose_kernel(sim->net, probe, latency);
-    const double n = sim->net.n;
-    // fitted to single-block timings: about 2.5 us plus 0.17 us per node and
-    // wave (0.25 us with 16 waves, whose barriers cost more)
+    choose_kernel(net, probe, latency);
+    const double n = net.n;
     const double per = probe.kernel == 16 ? 0.25 : 0.17;
-    const double lat_us = probe.kernel ? 2.5 + per * n / probe.kernel : 1.0 + 1.0 * n;
-    const double q = std::floor(tick_us / lat_us / 32.0) * 32.0;
+    return probe.kernel ? 2.5 + per * n / probe.kernel : 1.0 + 1.0 * n;
+}
+
+uint64_t slice_len(const pbn_sim *sim, double tick_us, bool latency)
+{
+    const double q = std::floor(tick_us / step_latency_us(sim->net, latency) / 32.0) * 32.0;
     return (uint64_t)std::max(32.0, q);
 }
 
@@ -962,10 +1023,10 @@ void round_end(Workspace &ws, RoundCtx &ctx)
     ctx.pending = false;
 }
 
-int run_round(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err)
+int run_round(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err, double tick_us)
 {
     RoundCtx ctx;
-    int rc = round_begin(runs, ws, stream, ctx, err);
+    int rc = round_begin(runs, ws, stream, ctx, err, true, tick_us);
     if (!rc && ctx.pending) {
         hipError_t e = hipEventSynchronize(ctx.done);
         if (e != hipSuccess) { err = std::string("round sync: ") + hipGetErrorString(e); rc = PBN_EDEVICE; }
@@ -987,16 +1048,20 @@ int run_to_completion(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t st
     }
 }
 
-// Lanes: one stream each (three, the hardware queues left beside the caller's),
-// every lane with its own asynchronous round loop.  Networks go to lanes by
-// step-kernel class (8 waves, 4 waves, the rest, for throughput), so one
-// launch serves one class; an empty lane takes half of the busiest one.  Rounds are time-sliced:
-// an extension advances at most about kTickUs of kernel time per round, so a
-// network that needs a long extension never holds back the decisions of the
-// others in its lane, and every round returns the results of the networks
-// whose extension completed in it.
+// Lanes: one stream each, every lane with its own asynchronous round loop.
+//   - express lane (the caller's stream): the few networks whose first round
+//     alone is a large share of the whole batch's expected time (the longest
+//     serial paths), unsliced, so their decisions and continuations overlap
+//     the bulk instead of following it;
+//   - three class lanes (own streams: the hardware queues left beside the
+//     caller's): the rest by step-kernel class (8 waves, 4 waves, the others,
+//     for throughput), so one launch serves one class; an empty lane takes
+//     half of the busiest one.  Their rounds are time-sliced: an extension
+//     advances at most about kTickUs of kernel time per round, so a network
+//     that needs a long extension never holds back the decisions of the
+//     others in its lane, and every round returns the results of the networks
+//     whose extension completed in it.
 namespace {
-constexpr double kTickUs = 5000.0;
 struct Lane {
     std::vector<SimRun *> runs;
     hipStream_t stream = nullptr;
@@ -1013,6 +1078,7 @@ struct LanePool {
     static constexpr int kN = 3;
     hipEvent_t ev[kN] = {};
     std::vector<std::unique_ptr<Lane>> lane;
+    Lane express;                     // runs on the caller's stream
     bool ready = false;
     int init(std::string &err)
     {
@@ -1044,9 +1110,40 @@ int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
     if (rc) return rc;
     const int nl = LanePool::kN;
     for (int k = 0; k < nl; ++k) P.lane[k]->runs.clear();
+    P.express.runs.clear();
+    P.express.stream = stream;
     std::vector<SimRun *> order(runs);
     std::stable_sort(order.begin(), order.end(),
                      [](const SimRun *a, const SimRun *b) { return a->sim->net.n < b->sim->net.n; });
+    // express: first-round serial time above a quarter of the batch's expected
+    // time at about 8e11 node-updates/s, at most 8 networks, only with a bulk
+    // of at least 8 others beside them
+    {
+        std::vector<std::pair<double, SimRun *>> crit;
+        double bulk_us = 0.0;
+        for (SimRun *r : order) {
+            const uint64_t first = r->machines.empty() ? 0 : r->machines[0].request().need_len;
+            bulk_us += (double)r->sim->net.n * r->sim->omega * (double)first / 8e5;
+        }
+        for (SimRun *r : order) {
+            const uint64_t first = r->machines.empty() ? 0 : r->machines[0].request().need_len;
+            const double serial = (double)first * step_latency_us(r->sim->net, false);
+            if (serial > 0.25 * bulk_us) crit.push_back({serial, r});
+        }
+        std::stable_sort(crit.begin(), crit.end(),
+                         [](const std::pair<double, SimRun *> &a, const std::pair<double, SimRun *> &b) {
+                             return a.first > b.first;
+                         });
+        if (crit.size() > 8) crit.resize(8);
+        if (order.size() >= crit.size() + 8) {
+            for (auto &c : crit) P.express.runs.push_back(c.second);
+            std::vector<SimRun *> rest;
+            for (SimRun *r : order)
+                if (std::find(P.express.runs.begin(), P.express.runs.end(), r) == P.express.runs.end())
+                    rest.push_back(r);
+            order.swap(rest);
+        }
+    }
     for (SimRun *r : order) {
         StepItem probe{};
         choose_kernel(r->sim->net, probe, false);
@@ -1081,12 +1178,15 @@ int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
         for (SimRun *r : runs)
             if (!r->finished()) groups += (r->sim->omega + 63) / 64;
         const int latency = groups <= kLatencyGroups;
-        for (int k = 0; k < nl; ++k) {
-            Lane &L = *P.lane[k];
+        for (int k = 0; k <= nl; ++k) {
+            Lane &L = k < nl ? *P.lane[k] : P.express;
             if (L.ctx.pending) { any_pending = true; all_done = false; continue; }
             if (L.finished()) continue;
             all_done = false;
-            if ((rc = round_begin(L.runs, L.ws, L.stream, L.ctx, err, false, kTickUs, latency))) break;
+            // the express lane always takes latency shapes and whole extensions
+            const double tick = k < nl ? kTickUs : 0.0;
+            const int lat = k < nl ? latency : 1;
+            if ((rc = round_begin(L.runs, L.ws, L.stream, L.ctx, err, false, tick, lat))) break;
             if (L.ctx.pending) any_pending = true;
         }
         if (rc || all_done) break;
@@ -1094,8 +1194,8 @@ int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
         // wait for the first lane whose round completes
         bool progressed = false;
         while (!progressed) {
-            for (int k = 0; k < nl; ++k) {
-                Lane &L = *P.lane[k];
+            for (int k = 0; k <= nl; ++k) {
+                Lane &L = k < nl ? *P.lane[k] : P.express;
                 if (!L.ctx.pending) continue;
                 hipError_t e = hipEventQuery(L.ctx.done);
                 if (e == hipSuccess) {
@@ -1113,14 +1213,16 @@ int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
         if (rc) break;
     }
     // drain and join back into the caller's stream
-    for (int k = 0; k < nl; ++k) {
-        Lane &L = *P.lane[k];
+    for (int k = 0; k <= nl; ++k) {
+        Lane &L = k < nl ? *P.lane[k] : P.express;
         if (L.ctx.pending) {
             (void)hipEventSynchronize(L.ctx.done);
             L.ctx.pending = false;
         }
-        (void)hipEventRecord(P.ev[k], L.stream);
-        (void)hipStreamWaitEvent(stream, P.ev[k], 0);
+        if (k < nl) {
+            (void)hipEventRecord(P.ev[k], L.stream);
+            (void)hipStreamWaitEvent(stream, P.ev[k], 0);
+        }
         L.runs.clear();
     }
     (void)hipEventDestroy(start);

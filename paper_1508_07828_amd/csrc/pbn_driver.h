@@ -118,6 +118,10 @@ void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t t
                       std::vector<StepItem> &items, bool latency);
 // Unfinished 64-chain groups up to which the scheduler picks latency shapes.
 constexpr uint64_t kLatencyGroups = 256;
+// Kernel time per extension slice of a time-sliced round (microseconds).
+constexpr double kTickUs = 5000.0;
+// XCDs of the chip: block i of a launch runs on XCD i mod kXcds.
+constexpr size_t kXcds = 8;
 
 // A simulation together with the machines of its state sets.
 struct SimRun {
@@ -144,7 +148,9 @@ struct RoundCtx {
 int round_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, RoundCtx &ctx, std::string &err,
                 bool allow_fork = true, double tick_us = 0.0, int latency = -1);
 void round_end(Workspace &ws, RoundCtx &ctx);
-int run_round(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err);
+// One synchronous round; tick_us > 0 time-slices its extensions.
+int run_round(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err,
+              double tick_us = 0.0);
 // Many simulations: lanes by step-kernel class, each with its own stream and
 // asynchronous, time-sliced round loop (run_to_completion for one simulation).
 int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err);

@@ -213,6 +213,7 @@ extern __shared__ uint64_t lds_bs[];
 __global__ void __launch_bounds__(1024) k_step_bs(const StepItem *__restrict__ items)
 {
     const StepItem it = load_item(items, blockIdx.x);
+    if (it.nchains == 0) return;         // padding of an XCD-aware launch
     const BsView v = load_bs_view(it.sim);
     const uint32_t n = v.n, W = v.W, omega = v.omega;
     const uint32_t G = blockDim.x >> 6;
