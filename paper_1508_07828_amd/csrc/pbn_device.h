@@ -114,6 +114,8 @@ __device__ __forceinline__ StepItem load_item(const StepItem *items, uint32_t b)
     it.philox_per_step = 0.0f;
     it.kernel = p->kernel;
     it.lds = p->lds;
+    it.small = 0;
+    it.pad_ = 0;
     return it;
 }
 

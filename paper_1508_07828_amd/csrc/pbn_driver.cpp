@@ -615,12 +615,14 @@ void choose_kernel(const Net &net, StepItem &it, bool latency)
 {
     it.kernel = 0;
     it.lds = 0;
+    it.small = 0;
     if (g_kernel_mode == 1 || !net.bitsliced) return;
     uint32_t G = g_waves_override ? g_waves_override : waves_for(net.n, latency);
     const size_t lds = bs_lds_bytes(net.n, net.msel_total, G);
     if (lds > 160 * 1024) return;
     it.kernel = G;
     it.lds = (uint32_t)lds;
+    it.small = net.nblk <= G && net.F_pad <= 64 * G;
 }
 
 namespace {
@@ -652,15 +654,6 @@ StreamPool &stream_pool()
     return p;
 }
 
-// Launch class of a bit-sliced item: blocks per CU that its waves (at the
-// kernel's register use) and its LDS allow.  Items of one class share a launch
-// sized for the group's largest LDS without losing residency.
-uint32_t bs_class(uint32_t G, uint32_t lds)
-{
-    const uint32_t by_waves = std::max<uint32_t>(1, bs_waves_per_cu() / G);
-    const uint32_t by_lds = std::max<uint32_t>(1, (160u << 10) / std::max<uint32_t>(lds, 1));
-    return std::min(by_waves, by_lds);
-}
 
 
 }  // namespace
@@ -671,13 +664,16 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
     if (items.empty()) return PBN_OK;
     int rc = ws.before_write(ws.ev_items, ws.items_in_flight, err);
     if (rc) return rc;
-    // groups of equal (kernel, residency class); inside a group the longest
+    // groups of equal kernel form; inside a group the longest
     // items first, since the hardware dispatches blocks roughly in order
     struct Key { uint32_t kernel, cls; double cost; size_t idx; };
     std::vector<Key> keys(items.size());
     for (size_t i = 0; i < items.size(); ++i) {
         const StepItem &it = items[i];
-        keys[i] = Key{it.kernel, it.kernel ? bs_class(it.kernel, it.lds) : 0u,
+        // one launch per kernel form: separate launches of one lane run one
+        // after the other, and each one's tail costs more than the residency a
+        // smaller LDS size would gain
+        keys[i] = Key{it.kernel, it.kernel ? (it.small << 16) : 0u,
                       (double)(it.nburn + (uint64_t)it.nrec * it.thin) * (double)it.nodes, i};
     }
     std::stable_sort(keys.begin(), keys.end(), [](const Key &a, const Key &b) {
@@ -722,12 +718,24 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
             std::vector<size_t> sord(per_sim.size());
             for (size_t i = 0; i < sord.size(); ++i) sord[i] = i;
             std::stable_sort(sord.begin(), sord.end(), [&](size_t x, size_t y) { return sim_cost[x] > sim_cost[y]; });
+            // a network stays on one XCD while that XCD is under its share of
+            // the group's cost; a network larger than a share spills its
+            // remaining blocks onto the least loaded XCDs
             std::vector<std::vector<size_t>> xl(kXcds);
             std::vector<double> load(kXcds, 0.0);
+            double total = 0.0;
+            for (double c : sim_cost) total += c;
+            const double share = total / (double)kXcds;
             for (size_t si : sord) {
-                const size_t x = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
-                xl[x].insert(xl[x].end(), per_sim[si].begin(), per_sim[si].end());
-                load[x] += sim_cost[si];
+                size_t x = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+                for (size_t idx : per_sim[si]) {
+                    const double c = (double)(items[idx].nburn + (uint64_t)items[idx].nrec * items[idx].thin) *
+                                     items[idx].nodes * items[idx].nchains;
+                    if (load[x] > 0.0 && load[x] + c > share * 1.0001)
+                        x = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+                    xl[x].push_back(idx);
+                    load[x] += c;
+                }
             }
             size_t rows = 0;
             for (auto &l : xl) {
@@ -774,7 +782,7 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
             profile_begin(mark, s);
         }
         const int r = g.kernel == 0 ? launch_step(d, (uint32_t)g.count, g.maxW, s, err)
-                                    : launch_step_bs(d, (uint32_t)g.count, g.kernel, g.lds, s, err);
+                                    : launch_step_bs(d, (uint32_t)g.count, g.kernel, (g.cls >> 16) != 0, g.lds, s, err);
         if (prof_on) profile_end(mark, s);
         return r;
     };

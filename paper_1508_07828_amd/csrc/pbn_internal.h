@@ -96,6 +96,8 @@ struct StepItem {
     float ops_per_step, philox_per_step;   // host-side accounting only
     uint32_t kernel;             // host-side: 0 = lane-per-chain, else waves per block (bit-sliced)
     uint32_t lds;                // host-side: LDS bytes the bit-sliced kernel needs
+    uint32_t small;              // host-side: bit-sliced with per-wave metadata in registers
+    uint32_t pad_;
 };
 
 enum QueryKind : uint32_t { kQueryWindow = 0, kQueryBatch = 1 };
@@ -121,11 +123,10 @@ int launch_setup(const DevSim *d_staging, DevSim *const *d_dst, uint32_t count, 
 int launch_step(const StepItem *d_items, uint32_t nitems, uint32_t max_W, void *stream,
                 std::string &err);
 // Bit-sliced trajectory kernel: G waves per 64-chain block, lds bytes of LDS.
-int launch_step_bs(const StepItem *d_items, uint32_t nitems, uint32_t G, size_t lds, void *stream,
+// small: every wave owns at most one 16-node block and one 64-slot group.
+int launch_step_bs(const StepItem *d_items, uint32_t nitems, uint32_t G, bool small, size_t lds, void *stream,
                    std::string &err);
 size_t bs_lds_bytes(uint32_t n, uint32_t msel_total, uint32_t G);
-// Waves of the bit-sliced kernel one CU holds at its register use.
-uint32_t bs_waves_per_cu();
 // Dynamic-LDS limit of a kernel raised to 160 KB (once per device).
 int allow_full_lds(const void *fn, std::string &err);
 int launch_reduce(const Query *d_queries, uint32_t nq, WindowResult *d_win, int32_t *d_bsum,

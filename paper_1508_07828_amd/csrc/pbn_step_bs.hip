@@ -18,7 +18,8 @@
 //   D  record the state-set indicators; clear S (the next step's gamma);
 //      swap S and Gm
 // LDS (u64 words): S[n], Gm[n], M[msel_total], Pw[G], then per wave a queue of
-// kQCap entries (three u32 arrays: header, flags low, flags high).
+// kQCap entries (three u32 arrays: header, flags low, flags high), then the
+// indicator words under construction (u32, [state set][lane]).
 // Lanes beyond the item's chain count run along on their own bit positions and
 // are never stored.
 #include "pbn_device.h"
@@ -74,27 +75,38 @@ __device__ __forceinline__ uint32_t bit_mask(uint32_t w, int e)
     return (uint32_t)(((int32_t)(w << (31 - e))) >> 31);
 }
 
+// Multiplexer tree, evaluated depth first so that at most one partial result
+// per level is live: node (LEV, BASE) selects between the subtrees of table
+// indices BASE.. and BASE + 2^LEV.. with parent mask x[LEV]; level 0 picks
+// table bit BASE or BASE + 1 with x[0].
+template <int LEV, int BASE>
+struct Mux {
+    static __device__ __forceinline__ uint64_t eval(uint32_t lo, uint32_t hi, const uint64_t *x)
+    {
+        const uint64_t a = Mux<LEV - 1, BASE>::eval(lo, hi, x);
+        const uint64_t b = Mux<LEV - 1, BASE + (1 << LEV)>::eval(lo, hi, x);
+        return bsel(x[LEV], b, a);
+    }
+};
+
+template <int BASE>
+struct Mux<0, BASE> {
+    static __device__ __forceinline__ uint64_t eval(uint32_t lo, uint32_t hi, const uint64_t *x)
+    {
+        constexpr int e0 = BASE, e1 = BASE + 1;
+        const uint32_t w0 = e0 < 32 ? lo : hi, w1 = e1 < 32 ? lo : hi;
+        // table bits e0 / e1 broadcast to whole words, selected by x0
+        const uint32_t A = bit_mask(w0, e0 & 31), B = bit_mask(w1, e1 & 31);
+        const uint32_t x0l = (uint32_t)x[0], x0h = (uint32_t)(x[0] >> 32);
+        const uint32_t rl = (x0l & B) | (~x0l & A), rh = (x0h & B) | (~x0h & A);
+        return ((uint64_t)rh << 32) | rl;
+    }
+};
+
 template <int K>
 __device__ __forceinline__ uint64_t mux_tree(uint32_t lo, uint32_t hi, const uint64_t *x)
 {
-    constexpr int L = 1 << K;
-    uint64_t r[L / 2];
-    const uint32_t x0l = (uint32_t)x[0], x0h = (uint32_t)(x[0] >> 32);
-#pragma unroll
-    for (int m = 0; m < L / 2; ++m) {
-        const int e0 = 2 * m, e1 = 2 * m + 1;
-        const uint32_t w0 = e0 < 32 ? lo : hi, w1 = e1 < 32 ? lo : hi;
-        // leaves: table bits e0 / e1 broadcast to whole words, selected by x0
-        const uint32_t A = bit_mask(w0, e0 & 31), B = bit_mask(w1, e1 & 31);
-        const uint32_t rl = (x0l & B) | (~x0l & A), rh = (x0h & B) | (~x0h & A);
-        r[m] = ((uint64_t)rh << 32) | rl;
-    }
-#pragma unroll
-    for (int lev = 1; lev < K; ++lev) {
-#pragma unroll
-        for (int m = 0; m < (L >> (lev + 1)); ++m) r[m] = bsel(x[lev], r[2 * m + 1], r[2 * m]);
-    }
-    return r[0];
+    return Mux<K - 1, 0>::eval(lo, hi, x);
 }
 
 __device__ __forceinline__ uint64_t eval_slot(uint32_t K, uint32_t lo, uint32_t hi, const uint64_t *x)
@@ -210,7 +222,11 @@ __device__ __forceinline__ void sel_threshold(uint32_t byte, uint32_t tb, uint32
 
 extern __shared__ uint64_t lds_bs[];
 
-__global__ void __launch_bounds__(1024) k_step_bs(const StepItem *__restrict__ items)
+// SMALL: every wave owns at most one 16-node block and one 64-slot group (the
+// host launches it only then), whose metadata stay in registers; the general
+// form reloads them per transition and spends no registers on them.
+template <bool SMALL>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) k_step_bs(const StepItem *__restrict__ items)
 {
     const StepItem it = load_item(items, blockIdx.x);
     if (it.nchains == 0) return;         // padding of an XCD-aware launch
@@ -246,16 +262,20 @@ __global__ void __launch_bounds__(1024) k_step_bs(const StepItem *__restrict__ i
     for (uint32_t i = threadIdx.x; i < v.msel_total; i += 64 * G) M[i] = 0ull;
     if (threadIdx.x < G) Pw[threadIdx.x] = 0ull;
 
-    uint32_t acc[kMaxProps];
+    // indicator words under construction, one per state set and chain, in LDS
+    // (wave 0 alone records)
+    uint32_t *acc = (uint32_t *)(Pw + G) + G * 3 * kQCap + lane;
     uint64_t pos = it.pos0;
     const uint32_t nprops = v.nprops;
-#pragma unroll
-    for (uint32_t q = 0; q < kMaxProps; ++q) {
-        acc[q] = 0;
-        if (wave == 0 && active && q < nprops && it.nrec > 0 && (pos & 31)) {
-            gu32 bits = (gu32)v.d->bits;
-            const uint32_t old = bits[((size_t)q * words_cap + (pos >> 5)) * omega + c];
-            acc[q] = old & ((1u << (pos & 31)) - 1u);
+    if (wave == 0) {
+        for (uint32_t q = 0; q < nprops; ++q) {
+            uint32_t a = 0;
+            if (active && it.nrec > 0 && (pos & 31)) {
+                gu32 bits = (gu32)v.d->bits;
+                const uint32_t old = bits[((size_t)q * words_cap + (pos >> 5)) * omega + c];
+                a = old & ((1u << (pos & 31)) - 1u);
+            }
+            acc[64 * q] = a;
         }
     }
     __syncthreads();
@@ -264,7 +284,9 @@ __global__ void __launch_bounds__(1024) k_step_bs(const StepItem *__restrict__ i
     const uint32_t nblk = v.nblk, F_pad = v.F_pad;
     // Small networks: at most one node block and one slot group per wave, whose
     // metadata then stay in registers for the whole launch.
-    const bool res_a = nblk <= G, res_c = F_pad <= 64 * G;
+    // (the small form keeps them register-resident; the flags stay run-time so
+    // the compiler does not trade registers for the single-iteration loops)
+    const bool res_a = SMALL && nblk <= G, res_c = SMALL && F_pad <= 64 * G;
     uint32_t ra_lmax = 0, ra_meta = 0, ra_tb = 0;
     if (res_a && wave < nblk) {
         ra_lmax = v.blk_sel[wave];
@@ -420,25 +442,18 @@ __global__ void __launch_bounds__(1024) k_step_bs(const StepItem *__restrict__ i
             since = 0;
             if (wave == 0) {
                 const uint32_t bpos = (uint32_t)(pos & 31);
-#pragma unroll
-                for (uint32_t q = 0; q < kMaxProps; ++q) {
-                    if (q < nprops) {
-                        uint64_t xm = ~0ull;
-                        for (uint32_t m = v.d->pn_off[q]; m < v.d->pn_off[q + 1]; ++m) {
-                            const uint64_t g = Gm[v.d->pn_node[m]];
-                            xm &= v.d->pn_val[m] ? g : ~g;
-                        }
-                        acc[q] |= (uint32_t)((xm >> lane) & 1ull) << bpos;
+                for (uint32_t q = 0; q < nprops; ++q) {
+                    uint64_t xm = ~0ull;
+                    for (uint32_t m = v.d->pn_off[q]; m < v.d->pn_off[q + 1]; ++m) {
+                        const uint64_t g = Gm[v.d->pn_node[m]];
+                        xm &= v.d->pn_val[m] ? g : ~g;
                     }
-                }
-                if (bpos == 31 && active) {
-                    gu32 bits = (gu32)v.d->bits;
-#pragma unroll
-                    for (uint32_t q = 0; q < kMaxProps; ++q) {
-                        if (q < nprops) {
-                            bits[((size_t)q * words_cap + (pos >> 5)) * omega + c] = acc[q];
-                            acc[q] = 0;
-                        }
+                    const uint32_t a = acc[64 * q] | ((uint32_t)((xm >> lane) & 1ull) << bpos);
+                    if (bpos == 31) {
+                        if (active) ((gu32)v.d->bits)[((size_t)q * words_cap + (pos >> 5)) * omega + c] = a;
+                        acc[64 * q] = 0;
+                    } else {
+                        acc[64 * q] = a;
                     }
                 }
             }
@@ -452,9 +467,7 @@ __global__ void __launch_bounds__(1024) k_step_bs(const StepItem *__restrict__ i
 
     if (wave == 0 && active && it.nrec > 0 && (pos & 31)) {
         gu32 bits = (gu32)v.d->bits;
-#pragma unroll
-        for (uint32_t q = 0; q < kMaxProps; ++q)
-            if (q < nprops) bits[((size_t)q * words_cap + (pos >> 5)) * omega + c] = acc[q];
+        for (uint32_t q = 0; q < nprops; ++q) bits[((size_t)q * words_cap + (pos >> 5)) * omega + c] = acc[64 * q];
     }
     // transpose back
     gu32 state = (gu32)v.d->state;
@@ -473,26 +486,13 @@ static int check_bs(hipError_t e, const char *what, std::string &err)
     return PBN_EDEVICE;
 }
 
-uint32_t bs_waves_per_cu()
-{
-    static uint32_t cached = 0;
-    if (cached) return cached;
-    hipFuncAttributes a{};
-    uint32_t per_simd = 4;
-    if (hipFuncGetAttributes(&a, (const void *)k_step_bs) == hipSuccess && a.numRegs > 0) {
-        const uint32_t regs = (uint32_t)((a.numRegs + 7) / 8 * 8);
-        per_simd = std::min<uint32_t>(8, std::max<uint32_t>(1, 512 / regs));
-    }
-    cached = 4 * per_simd;
-    return cached;
-}
-
 size_t bs_lds_bytes(uint32_t n, uint32_t msel_total, uint32_t G)
 {
-    return (size_t)8 * (2 * (size_t)n + msel_total + G) + (size_t)4 * 3 * kQCap * G;
+    return (size_t)8 * (2 * (size_t)n + msel_total + G) + (size_t)4 * 3 * kQCap * G + (size_t)4 * 64 * kMaxProps;
 }
 
-int launch_step_bs(const StepItem *d_items, uint32_t nitems, uint32_t G, size_t lds, void *stream, std::string &err)
+int launch_step_bs(const StepItem *d_items, uint32_t nitems, uint32_t G, bool small, size_t lds, void *stream,
+                   std::string &err)
 {
     if (nitems == 0) return PBN_OK;
     if (G != 1 && G != 2 && G != 4 && G != 8 && G != 16) {
@@ -503,11 +503,15 @@ int launch_step_bs(const StepItem *d_items, uint32_t nitems, uint32_t G, size_t 
         err = "bit-sliced state exceeds LDS";
         return PBN_ELIMIT;
     }
+    const void *fn = small ? (const void *)k_step_bs<true> : (const void *)k_step_bs<false>;
     if (lds > 64 * 1024) {
-        int rc = allow_full_lds((const void *)k_step_bs, err);
+        int rc = allow_full_lds(fn, err);
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(k_step_bs, dim3(nitems), dim3(64 * G), lds, (hipStream_t)stream, d_items);
+    if (small)
+        hipLaunchKernelGGL(k_step_bs<true>, dim3(nitems), dim3(64 * G), lds, (hipStream_t)stream, d_items);
+    else
+        hipLaunchKernelGGL(k_step_bs<false>, dim3(nitems), dim3(64 * G), lds, (hipStream_t)stream, d_items);
     return check_bs(hipGetLastError(), "k_step_bs launch", err);
 }
 
