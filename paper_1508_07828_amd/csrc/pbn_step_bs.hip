@@ -134,15 +134,6 @@ __device__ __forceinline__ uint32_t bytes_eq(uint32_t x, uint32_t m4)
     return ~(((y & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | y | 0x7F7F7F7Fu);
 }
 
-// The four byte flags of bytes_eq as bits 0..3.
-__device__ __forceinline__ uint32_t gather4(uint32_t z)
-{
-    uint32_t b = (z >> 7) & 0x01010101u;   // bits 0, 8, 16, 24
-    b |= b >> 7;                            // + bits 1 (byte 1) and 17 (byte 3)
-    b |= b >> 14;                           // + bits 2 (byte 2) and 3 (byte 3)
-    return b & 0xFu;
-}
-
 // Set bit `pos` (compile-time after unrolling) of the 64-bit flag pair.
 __device__ __forceinline__ void set_flag(bool on, uint32_t pos, uint32_t &lo, uint32_t &hi)
 {
@@ -151,7 +142,7 @@ __device__ __forceinline__ void set_flag(bool on, uint32_t pos, uint32_t &lo, ui
 }
 
 // Queue entry: header kind (1 bit) | lane (6) << 1 | block << 7, flags lo/hi.
-//   kind 0: perturbation ties, flag k = node 16 b + k
+//   kind 0: perturbation ties, flag 8 bb + q = node 16 b + 4 q + bb
 //   kind 1: selection ties, flag 3 k + j = threshold j (< 3) of node 16 b + k
 __device__ __forceinline__ void push(bool mine, uint32_t hdr, uint32_t flo, uint32_t fhi, uint32_t *Q,
                                      uint32_t &qlen)
@@ -186,7 +177,7 @@ __device__ __forceinline__ void resolve(const BsView &v, uint32_t t, uint32_t ch
         while (f) {
             const uint32_t x = (uint32_t)__builtin_ctzll(f);
             f &= f - 1;
-            const uint32_t k = kind ? x / 3 : x, j = kind ? x - 3 * k : 0u;
+            const uint32_t k = kind ? x / 3 : 4 * (x & 7u) + (x >> 3), j = kind ? x - 3 * k : 0u;
             const uint32_t i = 16 * b + k;
             if ((i >> 2) != rq) {
                 rq = i >> 2;
@@ -328,10 +319,17 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             }
             uint32_t wp[4];
             philox4(t, c, b, kTagPert, v.key, wp);
-            uint32_t tie = 0;
-#pragma unroll
-            for (uint32_t q = 0; q < 4; ++q) tie |= gather4(bytes_eq(wp[q], thr8x4)) << (4 * q);
-            if (ib < 16) tie &= (1u << ib) - 1u;
+            // tie flags: bit 8 bb + q <-> node 4 q + bb (byte bb of word q)
+            uint32_t tie = (bytes_eq(wp[0], thr8x4) >> 7) | (bytes_eq(wp[1], thr8x4) >> 6) |
+                           (bytes_eq(wp[2], thr8x4) >> 5) | (bytes_eq(wp[3], thr8x4) >> 4);
+            if (ib < 16) {
+                uint32_t valid = 0;
+                for (uint32_t bb = 0; bb < 4; ++bb) {
+                    const uint32_t cnt = ib > bb ? (ib - bb + 3) >> 2 : 0u;   // words q with 4 q + bb < ib
+                    valid |= ((1u << cnt) - 1u) << (8 * bb);
+                }
+                tie &= valid;
+            }
             if (thr8 > 0) {
                 // bytes below the primary threshold flip at once
 #pragma unroll
