@@ -590,7 +590,7 @@ void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t t
 // Kernel choice per item: the bit-sliced kernel when every predictor has
 // k <= 6 and its LDS fits, else the lane-per-chain kernel.  The waves per
 // 64-chain block follow measured per-transition cost on the device: for
-// throughput (many blocks per CU) 2 waves below 40 nodes, 4 up to 300, 8
+// throughput (many blocks per CU) 2 waves below 40 nodes, 4 up to 600, 8
 // beyond; for latency (the chip holds every block of the work at once) 2, 8
 // or 16 waves, which shortens each transition's critical path.  kernel_mode
 // forces one kernel or wave count (testing and tuning).
@@ -608,7 +608,7 @@ void set_kernel_mode(int mode, uint32_t waves)
 uint32_t waves_for(uint32_t n, bool latency)
 {
     if (latency) return n < 40 ? 2 : n < 150 ? 8 : 16;
-    return n < 40 ? 2 : n < 300 ? 4 : 8;
+    return n < 40 ? 2 : n < 600 ? 4 : 8;
 }
 
 void choose_kernel(const Net &net, StepItem &it, bool latency)

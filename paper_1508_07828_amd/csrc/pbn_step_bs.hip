@@ -2,23 +2,29 @@
 //
 // One block of G waves (G = blockDim.x / 64, 1..16) advances 64 chains.  State
 // is bit-sliced in LDS: S[i] holds node i of all 64 chains (bit = lane =
-// chain).  Per transition:
-//   A  lane = chain: the waves share the 16-node blocks.  Each lane draws its
-//      chain's perturbation and selection bytes for the block (one Philox
-//      evaluation each).  Selection masks m_j = [u < T_j] come from one ballot
-//      per (node, threshold) and are written whole into M.  Perturbations are
-//      rare: bytes below the primary threshold flip at once (only when
-//      p >= 2^-8), bytes equal to it are ties.  Ties of either kind are
-//      queued per lane and block as bit flags and resolved with the 24-bit
-//      refinement words, 64 queue entries per pass
-//   B  lane = node: Gm[i] := P & (S[i] ^ gamma_i), P = perturbed chains
+// chain).  Wave w owns the 16-node blocks b = w, w + G, ...  Per transition:
+//   A  lane = chain, own blocks: each lane draws its chain's perturbation and
+//      selection bytes for the block (one Philox evaluation each).  Selection
+//      masks m_j = [u < T_j] come from one ballot per (node, threshold) and are
+//      written whole into M.  Perturbations are rare: bytes below the primary
+//      threshold flip at once (only when p >= 2^-8), bytes equal to it are
+//      ties.  Ties of either kind are queued per lane and block as bit flags
+//      and resolved with the 24-bit refinement words, 64 queue entries per
+//      pass.  Flips go into Gm[i] (the next state, zero so far), the chains
+//      with any flip into this wave's word of P.
+//   -- barrier (P complete, every M written)
 //   C  lane = predictor slot (sorted by parent count): K-input multiplexer
 //      tree over the parents' masks, restricted to the chains that selected
-//      this predictor and were not perturbed, OR-ed into Gm[node]
-//   D  record the state-set indicators; clear S (the next step's gamma);
-//      swap S and Gm
-// LDS (u64 words): S[n], Gm[n], M[msel_total], Pw[G], then per wave a queue of
-// kQCap entries (three u32 arrays: header, flags low, flags high), then the
+//      this predictor and were not perturbed, OR-ed into Gm[node]; wave 0 also
+//      records the state-set indicators of the state reached by the previous
+//      transition
+//   -- barrier (every slot done)
+//   D  own nodes: Gm[i] ^= P & S[i] (perturbed chains: S XOR gamma, the
+//      others keep the functions' values), S[i] := 0 (the next transition's
+//      Gm); swap S and Gm.  The next A touches only the same wave's nodes, so
+//      no barrier follows D; P is double-buffered by transition parity.
+// LDS (u64 words): S[n], Gm[n], M[msel_total], Pw[2][G], then per wave a queue
+// of kQCap entries (three u32 arrays: header, flags low, flags high), then the
 // indicator words under construction (u32, [state set][lane]).
 // Lanes beyond the item's chain count run along on their own bit positions and
 // are never stored.
@@ -234,7 +240,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     uint64_t *Gm = lds_bs + n;
     uint64_t *M = lds_bs + 2 * n;
     uint64_t *Pw = M + v.msel_total;
-    uint32_t *Q = (uint32_t *)(Pw + G) + wave * 3 * kQCap;
+    uint32_t *Q = (uint32_t *)(Pw + 2 * G) + wave * 3 * kQCap;
     const uint64_t words_cap = v.d->words_cap;
 
     // transpose the chains' packed words into node masks
@@ -251,11 +257,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     }
     for (uint32_t i = threadIdx.x; i < n; i += 64 * G) Gm[i] = 0ull;
     for (uint32_t i = threadIdx.x; i < v.msel_total; i += 64 * G) M[i] = 0ull;
-    if (threadIdx.x < G) Pw[threadIdx.x] = 0ull;
+    if (threadIdx.x < 2 * G) Pw[threadIdx.x] = 0ull;
 
     // indicator words under construction, one per state set and chain, in LDS
     // (wave 0 alone records)
-    uint32_t *acc = (uint32_t *)(Pw + G) + G * 3 * kQCap + lane;
+    uint32_t *acc = (uint32_t *)(Pw + 2 * G) + G * 3 * kQCap + lane;
     uint64_t pos = it.pos0;
     const uint32_t nprops = v.nprops;
     if (wave == 0) {
@@ -296,16 +302,37 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     }
     const uint32_t total = it.nburn + it.nrec * it.thin;
     uint32_t since = 0;
+    bool pending = false;             // the state in S awaits recording
+    // the indicators of the current state S, at position pos (wave 0)
+    auto record = [&]() {
+        const uint32_t bpos = (uint32_t)(pos & 31);
+        for (uint32_t q = 0; q < nprops; ++q) {
+            uint64_t xm = ~0ull;
+            for (uint32_t m = v.d->pn_off[q]; m < v.d->pn_off[q + 1]; ++m) {
+                const uint64_t g = S[v.d->pn_node[m]];
+                xm &= v.d->pn_val[m] ? g : ~g;
+            }
+            const uint32_t a = acc[64 * q] | ((uint32_t)((xm >> lane) & 1ull) << bpos);
+            if (bpos == 31) {
+                if (active) ((gu32)v.d->bits)[((size_t)q * words_cap + (pos >> 5)) * omega + c] = a;
+                acc[64 * q] = 0;
+            } else {
+                acc[64 * q] = a;
+            }
+        }
+    };
     for (uint32_t s = 0; s < total; ++s) {
         const uint32_t t = it.t0 + s;
+        uint64_t *Pt = Pw + (s & 1) * G;  // this transition's perturbed-chain words
         // ---- A: draws, lane = chain
         uint64_t P_acc = 0;
         uint32_t qlen = 0;
+        if (lane == 0) Pt[wave] = 0ull;   // last read two transitions ago
         for (uint32_t b = wave;; b += G) {
             const bool last = b >= nblk;
             // a block queues at most 128 entries: resolve before the queue could overflow
             if (qlen != 0 && (last || qlen + 128 > kQCap)) {
-                resolve(v, t, chain0, Q, qlen, Gm, M, &Pw[wave], lane);
+                resolve(v, t, chain0, Q, qlen, Gm, M, &Pt[wave], lane);
                 qlen = 0;
             }
             if (last) break;
@@ -394,16 +421,17 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
                 }
             }
         }
-        if (P_acc && lane == 0) lds_or(&Pw[wave], P_acc);
-        __syncthreads();
-
-        // ---- B: S' := P & (S ^ gamma), lane = node
-        uint64_t P = 0;
-        for (uint32_t w = 0; w < G; ++w) P |= Pw[w];
-        for (uint32_t i = threadIdx.x; i < n; i += 64 * G) Gm[i] = P & (S[i] ^ Gm[i]);
+        if (P_acc && lane == 0) lds_or(&Pt[wave], P_acc);
         __syncthreads();
 
         // ---- C: predictor slots, lane = slot
+        if (pending && wave == 0) {
+            record();
+            ++pos;
+        }
+        pending = false;
+        uint64_t P = 0;
+        for (uint32_t w = 0; w < G; ++w) P |= Pt[w];
         const uint64_t nP = ~P;
         for (uint32_t s0 = 64 * wave; s0 < F_pad; s0 += 64 * G) {
             const uint32_t slot = s0 + lane;
@@ -434,33 +462,26 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
         }
         __syncthreads();
 
-        // ---- D: record, clear, swap (Pw was last read before C's barrier;
-        // every selection mask is rewritten whole in the next A)
+        // ---- D: own nodes, lane = (block, node); blocks w + G m, four per pass
+        for (uint32_t m0 = 0;; m0 += 4) {
+            const uint32_t b0 = wave + G * m0;
+            if (b0 >= nblk) break;
+            const uint32_t b = wave + G * (m0 + (lane >> 4)), i = 16 * b + (lane & 15u);
+            if (b < nblk && i < n) {
+                Gm[i] ^= P & S[i];
+                S[i] = 0ull;
+            }
+        }
         if (s >= it.nburn && ++since == it.thin) {
             since = 0;
-            if (wave == 0) {
-                const uint32_t bpos = (uint32_t)(pos & 31);
-                for (uint32_t q = 0; q < nprops; ++q) {
-                    uint64_t xm = ~0ull;
-                    for (uint32_t m = v.d->pn_off[q]; m < v.d->pn_off[q + 1]; ++m) {
-                        const uint64_t g = Gm[v.d->pn_node[m]];
-                        xm &= v.d->pn_val[m] ? g : ~g;
-                    }
-                    const uint32_t a = acc[64 * q] | ((uint32_t)((xm >> lane) & 1ull) << bpos);
-                    if (bpos == 31) {
-                        if (active) ((gu32)v.d->bits)[((size_t)q * words_cap + (pos >> 5)) * omega + c] = a;
-                        acc[64 * q] = 0;
-                    } else {
-                        acc[64 * q] = a;
-                    }
-                }
-            }
-            ++pos;
+            pending = true;
         }
-        for (uint32_t i = threadIdx.x; i < n; i += 64 * G) S[i] = 0ull;
-        if (threadIdx.x < G) Pw[threadIdx.x] = 0ull;
         uint64_t *tmp = S; S = Gm; Gm = tmp;
-        __syncthreads();
+    }
+    __syncthreads();
+    if (pending && wave == 0) {
+        record();
+        ++pos;
     }
 
     if (wave == 0 && active && it.nrec > 0 && (pos & 31)) {
@@ -486,7 +507,7 @@ static int check_bs(hipError_t e, const char *what, std::string &err)
 
 size_t bs_lds_bytes(uint32_t n, uint32_t msel_total, uint32_t G)
 {
-    return (size_t)8 * (2 * (size_t)n + msel_total + G) + (size_t)4 * 3 * kQCap * G + (size_t)4 * 64 * kMaxProps;
+    return (size_t)8 * (2 * (size_t)n + msel_total + 2 * G) + (size_t)4 * 3 * kQCap * G + (size_t)4 * 64 * kMaxProps;
 }
 
 int launch_step_bs(const StepItem *d_items, uint32_t nitems, uint32_t G, bool small, size_t lds, void *stream,
