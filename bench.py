@@ -129,6 +129,68 @@ def run_serving(pkg, torch, seconds, rate, arena_bytes, serial_budget_s=20.0):
     )
 
 
+def single_workload(pkg, torch, name: str, steps: int, warmup: int, cpu_s: float, no_cpu: bool) -> dict:
+    """One network of a plain configuration (tiny, medium or large), solved end
+    to end by estimate_prob per step; every step restarts the same chains."""
+    job = getattr(ps, name)()
+    net = pkg.Network(ps.to_text(job.net))
+    sim = pkg.Simulation(net, job.chains, job.seed, max_props=len(job.patterns), max_len=MAX_LEN)
+    kw = dict(method=job.method, psrf_max=job.psrf_max)
+    for w in range(warmup):
+        log("warmup {}".format(w))
+        sim.estimate(job.patterns, job.r, job.confidence, **kw)
+    torch.cuda.synchronize()
+    pkg.profile_enable(True)
+    pkg.profile_reset()
+    times, nus, res = [], [], None
+    for k in range(steps):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        res = sim.estimate(job.patterns, job.r, job.confidence, **kw)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - a)
+        nus.append(float(sim.position()[1]) * job.chains * job.net.n)
+        log("step {}: {:.3f} s, {:.3e} node-updates".format(k, times[-1], nus[-1]))
+    prof = pkg.profile_read()
+    pkg.profile_enable(False)
+    total_t = sum(times)
+    line = {
+        "metric": METRIC, "value": sum(nus) / total_t, "unit": "node-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": total_t / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "{}: one random PBN, n={}, {} chains, {} state set(s), {} r={} s={}, psrf {}".format(
+            name, job.net.n, job.chains, len(job.patterns), job.method, job.r, job.confidence, job.psrf_max),
+            "chain_len": int(sim.position()[0]), "transitions": int(sim.position()[1])},
+        "roofline": roofline_of(prof, total_t),
+        "results": [{k: r[k] for k in ("prob", "ci_lo", "ci_hi", "psi", "n", "N", "M", "kappa", "batches")} for r in res],
+        "cpu_baseline": None if no_cpu else cpu_baseline([job], cpu_s),
+    }
+    return line
+
+
+def roofline_of(prof: dict, total_t: float) -> dict:
+    launches = max(1, prof["launches"])
+    avg_launch_s = prof["kernel_ms"] / launches / 1e3
+    ops_per_launch = prof["alg_ops"] / launches
+    achieved = ops_per_launch / max(avg_launch_s, 1e-12)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32_OPS / 1e12, "unit": "Tops/s",
+                "frac": achieved / PEAK_INT32_OPS, "traffic": None,
+                "kernel": "k_step_bs", "launches": int(prof["launches"]),
+                "avg_launch_ms": avg_launch_s * 1e3,
+                "alg_ops_per_launch": ops_per_launch,
+                "kernel_node_updates_per_s": prof["node_updates"] / max(prof["kernel_ms"] / 1e3, 1e-12),
+                "philox_evals_per_s": prof["philox_evals"] / max(prof["kernel_ms"] / 1e3, 1e-12),
+                # launches of the lanes overlap: the chip-wide rate over the timed region
+                "aggregate_tops": prof["alg_ops"] / total_t / 1e12,
+                "aggregate_frac": prof["alg_ops"] / total_t / PEAK_INT32_OPS}
+    tr = os.path.join(ROOT, "profiles", "k_step_bs_traffic.json")
+    if os.path.exists(tr):
+        info = json.load(open(tr))
+        if info.get("kernel_source_sha") == kernel_sha():
+            roofline["traffic"] = info.get("bytes_per_launch")
+    return roofline
+
+
 def cpu_baseline(jobs, budget_s: float):
     import oracle
     threads = min(os.cpu_count() or 1, 16)
@@ -162,6 +224,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--waves", type=int, default=0, help="bit-sliced waves per block (0 = by n)")
+    ap.add_argument("--workload", default="batched", choices=["batched", "tiny", "medium", "large"],
+                    help="batched (default, the headline) or one plain configuration")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter scale)")
     ap.add_argument("--traffic-from", nargs=5, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE", "OUT"),
                     help="turn rocprofv3 FETCH_SIZE/WRITE_SIZE runs into bytes per k_step_bs launch")
@@ -183,6 +247,10 @@ def main() -> int:
     pkg.lib()
     if args.waves:
         pkg.set_kernel("bitsliced", args.waves)
+    if args.workload != "batched":
+        print(json.dumps(single_workload(pkg, torch, args.workload, args.steps, args.warmup, args.cpu_seconds,
+                                         args.no_cpu)))
+        return 0
 
     jobs = ps.batched(args.count)
     log("setting up {} networks".format(len(jobs)))
@@ -216,25 +284,7 @@ def main() -> int:
     value = sum(nus) / total_t
     nconv = sum(r[0]["status"] != 0 for r in res)
 
-    launches = max(1, prof["launches"])
-    avg_launch_s = prof["kernel_ms"] / launches / 1e3
-    ops_per_launch = prof["alg_ops"] / launches
-    achieved = ops_per_launch / avg_launch_s
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32_OPS / 1e12, "unit": "Tops/s",
-                "frac": achieved / PEAK_INT32_OPS, "traffic": None,
-                "kernel": "k_step_bs", "launches": int(prof["launches"]),
-                "avg_launch_ms": avg_launch_s * 1e3,
-                "alg_ops_per_launch": ops_per_launch,
-                "kernel_node_updates_per_s": prof["node_updates"] / (prof["kernel_ms"] / 1e3),
-                "philox_evals_per_s": prof["philox_evals"] / (prof["kernel_ms"] / 1e3),
-                # launches of the three lanes overlap: the chip-wide rate over the timed region
-                "aggregate_tops": prof["alg_ops"] / total_t / 1e12,
-                "aggregate_frac": prof["alg_ops"] / total_t / PEAK_INT32_OPS}
-    tr = os.path.join(ROOT, "profiles", "k_step_bs_traffic.json")
-    if os.path.exists(tr):
-        info = json.load(open(tr))
-        if info.get("kernel_source_sha") == kernel_sha():
-            roofline["traffic"] = info.get("bytes_per_launch")
+    roofline = roofline_of(prof, total_t)
 
     plain = None
     if not args.no_plain:
