@@ -224,6 +224,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--waves", type=int, default=0, help="bit-sliced waves per block (0 = by n)")
+    ap.add_argument("--tune", action="store_true",
+                    help="measure the kernel shapes per network size first (untimed) and use them")
     ap.add_argument("--workload", default="batched", choices=["batched", "tiny", "medium", "large"],
                     help="batched (default, the headline) or one plain configuration")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter scale)")
@@ -247,6 +249,13 @@ def main() -> int:
     pkg.lib()
     if args.waves:
         pkg.set_kernel("bitsliced", args.waves)
+    tune = None
+    if args.tune:
+        log("autotune")
+        tune = pkg.autotune()
+        for r in tune:
+            log("  n={n}: throughput {waves_throughput} waves ({node_updates_per_s:.3e}/s), "
+                "latency {waves_latency} waves ({transition_us:.2f} us)".format(**r))
     if args.workload != "batched":
         print(json.dumps(single_workload(pkg, torch, args.workload, args.steps, args.warmup, args.cpu_seconds,
                                          args.no_cpu)))
@@ -327,6 +336,7 @@ def main() -> int:
         "batched_vs_plain": (value / plain["value"]) if plain else None,
         "serving": serving,
         "cpu_baseline": cpu,
+        "autotune": tune,
     }
     print(json.dumps(line))
     return 0

@@ -249,6 +249,34 @@ int pbn_set_kernel(int mode, uint32_t waves);
 int pbn_profile_read(pbn_profile *out);
 int pbn_profile_reset(void);
 
+/* ---------------------------------------------------------------- autotuning */
+
+/* One row of the kernel-shape table: for networks of about n nodes, the waves
+ * per 64-chain block of the bit-sliced kernel that gave the highest node-update
+ * rate with the chip full of blocks (throughput) and the shortest transition
+ * of one block alone (latency), with the measured figures. */
+typedef struct {
+    uint32_t n;
+    uint32_t waves_throughput;
+    uint32_t waves_latency;
+    uint32_t reserved;
+    double node_updates_per_s;   /* at waves_throughput, 131072 chains        */
+    double transition_us;        /* at waves_latency, 64 chains               */
+} pbn_tune_row;
+
+/* Measures the bit-sliced kernel's shapes (1, 2, 4, 8, 16 waves per block) on
+ * synthetic networks of 24..3072 nodes drawn like the paper's random networks
+ * (Sec. 5.1: 1-3 predictors per node, 1-5 parents, p = 1e-3), with short
+ * event-timed launches on hip_stream (under a second of GPU time), and uses
+ * the result for every later launch in this process instead of the built-in
+ * rule.  Results of the method do not depend on the shapes.  Fills
+ * rows[0 .. min(cap, *count)) and sets *count to the number of rows (8).
+ * The library allocates and frees its own device memory for the runs.
+ * Errors: PBN_ENOMEM, PBN_EDEVICE (message in pbn_last_error). */
+int pbn_autotune(void *hip_stream, pbn_tune_row *rows, uint32_t cap, uint32_t *count);
+/* Back to the built-in shape rule. */
+int pbn_autotune_reset(void);
+
 /* ---------------------------------------------------------------- misc */
 
 /* Phi^{-1}(p) (AS 241) and the Student-t quantile used by the statistics. */

@@ -28,6 +28,7 @@ EXPORTS = (
     "pbn_batch_run", "pbn_batch_estimate", "pbn_server_create", "pbn_server_free", "pbn_server_submit",
     "pbn_server_step", "pbn_server_poll", "pbn_server_memory", "pbn_normal_quantile", "pbn_t_quantile",
     "pbn_last_error", "pbn_profile_enable", "pbn_profile_read", "pbn_profile_reset", "pbn_set_kernel",
+    "pbn_autotune", "pbn_autotune_reset",
 )
 
 
@@ -125,6 +126,8 @@ def lib():
         "pbn_profile_read": (i32, [ctypes.POINTER(Profile)]),
         "pbn_profile_reset": (i32, []),
         "pbn_set_kernel": (i32, [i32, u32]),
+        "pbn_autotune": (i32, [vp, ctypes.POINTER(TuneRow), u32, ctypes.POINTER(u32)]),
+        "pbn_autotune_reset": (i32, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -150,6 +153,25 @@ def t_quantile(p: float, nu: float) -> float:
 def set_kernel(mode: str = "auto", waves: int = 0) -> None:
     """Trajectory-kernel choice: "auto", "lane" (lane per chain) or "bitsliced"."""
     _check(lib().pbn_set_kernel({"auto": 0, "lane": 1, "bitsliced": 2}[mode], waves))
+
+
+class TuneRow(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("waves_throughput", ctypes.c_uint32),
+                ("waves_latency", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("node_updates_per_s", ctypes.c_double), ("transition_us", ctypes.c_double)]
+
+
+def autotune(stream=None) -> List[Dict]:
+    """Measure the bit-sliced kernel's shapes per network size and use them from now on."""
+    rows = (TuneRow * 16)()
+    count = ctypes.c_uint32()
+    _check(lib().pbn_autotune(_stream_handle(stream), rows, 16, ctypes.byref(count)))
+    return [{f: getattr(rows[i], f) for f, _ in TuneRow._fields_ if f != "reserved"} for i in range(count.value)]
+
+
+def autotune_reset() -> None:
+    """Back to the built-in shape rule."""
+    _check(lib().pbn_autotune_reset())
 
 
 def profile_enable(on: bool = True) -> None:

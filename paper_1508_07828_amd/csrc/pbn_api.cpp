@@ -515,6 +515,19 @@ int pbn_set_kernel(int mode, uint32_t waves)
     return PBN_OK;
 }
 
+int pbn_autotune(void *hip_stream, pbn_tune_row *rows, uint32_t cap, uint32_t *count)
+{
+    std::string err;
+    int rc = pbn::autotune((hipStream_t)hip_stream, rows, cap, count, err);
+    return rc ? fail(rc, err) : PBN_OK;
+}
+
+int pbn_autotune_reset(void)
+{
+    pbn::autotune_reset();
+    return PBN_OK;
+}
+
 int pbn_profile_enable(int on)
 {
     pbn::profile_set(on != 0);

@@ -607,8 +607,10 @@ void set_kernel_mode(int mode, uint32_t waves)
 
 uint32_t waves_for(uint32_t n, bool latency)
 {
+    uint32_t G = 0;
+    if (tuned_waves(n, latency, &G)) return G;
     if (latency) return n < 40 ? 2 : n < 150 ? 8 : 16;
-    return n < 40 ? 2 : n < 600 ? 4 : 8;
+    return n < 40 ? 2 : n < 900 ? 4 : 8;
 }
 
 void choose_kernel(const Net &net, StepItem &it, bool latency)
@@ -618,7 +620,12 @@ void choose_kernel(const Net &net, StepItem &it, bool latency)
     it.small = 0;
     if (g_kernel_mode == 1 || !net.bitsliced) return;
     uint32_t G = g_waves_override ? g_waves_override : waves_for(net.n, latency);
-    const size_t lds = bs_lds_bytes(net.n, net.msel_total, G);
+    size_t lds = bs_lds_bytes(net.n, net.msel_total, G);
+    // a shape whose LDS does not fit falls back to fewer waves
+    while (lds > 160 * 1024 && G > 1 && !g_waves_override) {
+        G /= 2;
+        lds = bs_lds_bytes(net.n, net.msel_total, G);
+    }
     if (lds > 160 * 1024) return;
     it.kernel = G;
     it.lds = (uint32_t)lds;

@@ -171,6 +171,10 @@ void profile_clear();
 
 // Kernel selection for a step item (see pbn_driver.cpp) and its override.
 void choose_kernel(const Net &net, StepItem &it, bool latency);
+// Autotuner (pbn_tune.cpp): measured shapes per size bucket, if measured.
+bool tuned_waves(uint32_t n, bool latency, uint32_t *G);
+int autotune(hipStream_t stream, pbn_tune_row *rows, uint32_t cap, uint32_t *count, std::string &err);
+void autotune_reset();
 uint32_t waves_for(uint32_t n, bool latency);
 void set_kernel_mode(int mode, uint32_t waves);
 

@@ -263,6 +263,32 @@ def test_sliced_rounds_equal_oracle():
         assert_same_result(g[0], want[0], j.name)
 
 
+def test_autotune_keeps_results():
+    # the measured kernel shapes change launches, never results
+    jobs = sorted(ps.batched(), key=lambda j: j.net.n * j.chains)[:6] + sorted(ps.batched(), key=lambda j: -j.net.n)[:2]
+    jobs = [dataclasses.replace(j, chains=min(j.chains, 128)) for j in jobs]
+    nets = [pkg.Network(ps.to_text(j.net)) for j in jobs]
+
+    def solve():
+        sims = [pkg.Simulation(nt, j.chains, j.seed, max_props=1, max_len=CAP) for nt, j in zip(nets, jobs)]
+        return pkg.batch_estimate(sims, [j.patterns for j in jobs], [j.r for j in jobs],
+                                  [j.confidence for j in jobs], psrf_max=1.1)
+
+    before = solve()
+    say("autotune")
+    rows = pkg.autotune()
+    try:
+        assert len(rows) == 8
+        for r in rows:
+            assert r["waves_throughput"] in (1, 2, 4, 8, 16) and r["waves_latency"] in (1, 2, 4, 8, 16)
+            assert r["node_updates_per_s"] > 0 and r["transition_us"] > 0
+        after = solve()
+    finally:
+        pkg.autotune_reset()
+    for a, b, j in zip(after, before, jobs):
+        assert_same_result(a[0], b[0], j.name)
+
+
 def test_server_isolation():
     jobs = sorted(ps.serving(limit=40), key=lambda j: j.net.n)[:8]
     say("server with {} requests".format(len(jobs)))
