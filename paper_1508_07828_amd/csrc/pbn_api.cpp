@@ -147,7 +147,7 @@ int run_chains(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin)
         return fail(PBN_ELIMIT, "transition index limit (2^32)");
     if (burn_in + steps * (uint64_t)thin >= (1ull << 32)) return fail(PBN_ELIMIT, "too many transitions");
     std::vector<pbn::StepItem> items;
-    pbn::sim_extend_items(sim, burn_in, steps, thin, items, (sim->omega + 63) / 64 <= pbn::kLatencyGroups);
+    pbn::sim_extend_items(sim, burn_in, steps, thin, items, pbn::latency_waves(sim) <= pbn::kLatencyWaves);
     std::string err;
     int rc = pbn::launch_items(items, sim->ws, sim->stream, err);
     return rc ? fail(rc, err) : PBN_OK;
@@ -268,10 +268,10 @@ int pbn_batch_run(pbn_sim *const *sims, uint32_t count, const uint64_t *steps, v
         if (s->len + steps[i] > s->words_cap * 32 - 32) return fail(PBN_ELIMIT, "bit-stream capacity exceeded");
         if (s->t_done + steps[i] >= (1ull << 32)) return fail(PBN_ELIMIT, "transition index limit (2^32)");
     }
-    uint64_t groups = 0;
+    uint64_t waves = 0;
     for (uint32_t i = 0; i < count; ++i)
-        if (steps[i]) groups += (sims[i]->omega + 63) / 64;
-    const bool latency = groups <= pbn::kLatencyGroups;
+        if (steps[i]) waves += pbn::latency_waves(sims[i]);
+    const bool latency = waves <= pbn::kLatencyWaves;
     for (uint32_t i = 0; i < count; ++i)
         if (steps[i]) pbn::sim_extend_items(sims[i], 0, steps[i], 1, items, latency);
     static thread_local pbn::Workspace ws;

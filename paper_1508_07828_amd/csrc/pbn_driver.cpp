@@ -605,6 +605,13 @@ void set_kernel_mode(int mode, uint32_t waves)
     g_waves_override = waves;
 }
 
+uint64_t latency_waves(const pbn_sim *sim)
+{
+    StepItem probe{};
+    choose_kernel(sim->net, probe, true);
+    return (uint64_t)((sim->omega + 63) / 64) * (probe.kernel ? probe.kernel : 1);
+}
+
 uint32_t waves_for(uint32_t n, bool latency)
 {
     uint32_t G = 0;
@@ -943,10 +950,10 @@ int round_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, 
     ctx.kinds.clear();
     ctx.pending = false;
     if (latency < 0) {
-        uint64_t groups = 0;
+        uint64_t waves = 0;
         for (SimRun *run : runs)
-            if (!run->finished()) groups += (run->sim->omega + 63) / 64;
-        latency = groups <= kLatencyGroups;
+            if (!run->finished()) waves += latency_waves(run->sim);
+        latency = waves <= kLatencyWaves;
     }
     // 1. extensions for runs with no request ready at their current length
     std::vector<StepItem> items;
@@ -1189,10 +1196,10 @@ int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
     for (;;) {
         bool any_pending = false, all_done = true;
         // latency mode once the unfinished work fits on the chip at once
-        uint64_t groups = 0;
+        uint64_t waves = 0;
         for (SimRun *r : runs)
-            if (!r->finished()) groups += (r->sim->omega + 63) / 64;
-        const int latency = groups <= kLatencyGroups;
+            if (!r->finished()) waves += latency_waves(r->sim);
+        const int latency = waves <= kLatencyWaves;
         for (int k = 0; k <= nl; ++k) {
             Lane &L = k < nl ? *P.lane[k] : P.express;
             if (L.ctx.pending) { any_pending = true; all_done = false; continue; }

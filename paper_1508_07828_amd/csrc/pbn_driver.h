@@ -116,8 +116,12 @@ int sims_reset_batch(pbn_sim *const *sims, uint32_t count, const pbn_pattern *pr
 // full) rather than for throughput.
 void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin,
                       std::vector<StepItem> &items, bool latency);
-// Unfinished 64-chain groups up to which the scheduler picks latency shapes.
-constexpr uint64_t kLatencyGroups = 256;
+// Latency shapes are picked while every 64-chain block of the unfinished work,
+// in its latency shape, fits on the chip at once (waves of 256 CUs at six
+// waves per SIMD).
+constexpr uint64_t kLatencyWaves = 256 * 24;
+// Waves that the blocks of sim need in latency shapes.
+uint64_t latency_waves(const pbn_sim *sim);
 // Kernel time per extension slice of a time-sliced round (microseconds).
 constexpr double kTickUs = 5000.0;
 // XCDs of the chip: block i of a launch runs on XCD i mod kXcds.
