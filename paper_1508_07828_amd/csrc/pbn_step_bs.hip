@@ -140,16 +140,12 @@ __device__ __forceinline__ uint32_t bytes_eq(uint32_t x, uint32_t m4)
     return ~(((y & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | y | 0x7F7F7F7Fu);
 }
 
-// Set bit `pos` (compile-time after unrolling) of the 64-bit flag pair.
-__device__ __forceinline__ void set_flag(bool on, uint32_t pos, uint32_t &lo, uint32_t &hi)
-{
-    if (pos < 32) lo |= on ? (1u << pos) : 0u;
-    else hi |= on ? (1u << (pos - 32)) : 0u;
-}
-
-// Queue entry: header kind (1 bit) | lane (6) << 1 | block << 7, flags lo/hi.
-//   kind 0: perturbation ties, flag 8 bb + q = node 16 b + 4 q + bb
-//   kind 1: selection ties, flag 3 k + j = threshold j (< 3) of node 16 b + k
+// Queue entry: header and a 64-bit flag word (lo, hi).
+//   kind 0, perturbation ties of chain lane: header 0 | lane << 1 | block << 7,
+//     flag 8 bb + q = node 16 b + 4 q + bb
+//   kind 1, selection ties of node k (of block b) in chains 16 g .. 16 g + 15:
+//     header 1 | k << 1 | g << 5 | block << 7, flag 16 j + x = threshold j of
+//     chain 16 g + x
 __device__ __forceinline__ void push(bool mine, uint32_t hdr, uint32_t flo, uint32_t fhi, uint32_t *Q,
                                      uint32_t &qlen)
 {
@@ -174,47 +170,51 @@ __device__ __forceinline__ void resolve(const BsView &v, uint32_t t, uint32_t ch
     const uint32_t pthr24 = v.p_thr & 0xFFFFFFu;
     for (uint32_t e = lane; e < qlen; e += 64) {
         const uint32_t hdr = Q[e];
-        const uint32_t kind = hdr & 1u, cl = (hdr >> 1) & 63u, b = hdr >> 7;
+        const uint32_t kind = hdr & 1u, b = hdr >> 7;
         uint64_t f = (uint64_t)Q[kQCap + e] | ((uint64_t)Q[2 * kQCap + e] << 32);
-        const uint64_t bit = 1ull << cl;
         const uint32_t tag = (kind ? kTagSel : kTagPert) + 1;
         uint32_t rq = 0xFFFFFFFFu, r[4] = {0u, 0u, 0u, 0u};
         bool flipped = false;
         while (f) {
             const uint32_t x = (uint32_t)__builtin_ctzll(f);
             f &= f - 1;
-            const uint32_t k = kind ? x / 3 : 4 * (x & 7u) + (x >> 3), j = kind ? x - 3 * k : 0u;
-            const uint32_t i = 16 * b + k;
-            if ((i >> 2) != rq) {
-                rq = i >> 2;
-                philox4(t, chain0 + cl, rq, tag, v.key, r);
+            uint32_t cl, i, j;
+            if (kind == 0) {
+                cl = (hdr >> 1) & 63u;
+                i = 16 * b + 4 * (x & 7u) + (x >> 3);
+                j = 0;
+            } else {
+                cl = 16 * ((hdr >> 5) & 3u) + (x & 15u);
+                i = 16 * b + ((hdr >> 1) & 15u);
+                j = x >> 4;
+            }
+            const uint32_t key = (cl << 24) | (i >> 2);
+            if (key != rq) {
+                rq = key;
+                philox4(t, chain0 + cl, i >> 2, tag, v.key, r);
             }
             const uint32_t r24 = pick4(r, i & 3u) & 0xFFFFFFu;
             if (kind == 0) {
                 if (r24 < pthr24) {
-                    lds_or(&Gm[i], bit);
+                    lds_or(&Gm[i], 1ull << cl);
                     flipped = true;
                 }
             } else {
                 const uint32_t T = v.fn_thr[v.nd_first[i] + j];
-                if (r24 < (T & 0xFFFFFFu)) lds_or(&M[(v.nd_info[2 * i] >> 8) + j], bit);
+                if (r24 < (T & 0xFFFFFFu)) lds_or(&M[(v.nd_info[2 * i] >> 8) + j], 1ull << cl);
             }
         }
-        if (flipped) lds_or(Pw_mine, bit);
+        if (flipped) lds_or(Pw_mine, 1ull << ((hdr >> 1) & 63u));
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-// Selection threshold j (< 3) of node k: the mask of chains whose byte lies
-// below the threshold's top byte goes to lane k of (al, ah); equal bytes are
-// ties (flag 3 k + j).
-__device__ __forceinline__ void sel_threshold(uint32_t byte, uint32_t tb, uint32_t k, uint32_t j, uint32_t &al,
-                                              uint32_t &ah, uint32_t &flo, uint32_t &fhi)
+// Sixteen byte-compare flags (bit 7 of each byte of w[m]; byte bb of w[m]
+// belongs to chain m + 4 bb) packed as bit m + 4 bb.
+__device__ __forceinline__ uint32_t pack16(const uint32_t w[4])
 {
-    const uint64_t lt = __ballot(byte < tb);
-    al = amdgcn_writelane((uint32_t)lt, k, al);
-    ah = amdgcn_writelane((uint32_t)(lt >> 32), k, ah);
-    set_flag(byte == tb, 3 * k + j, flo, fhi);
+    const uint32_t y = (w[0] >> 7) | (w[1] >> 6) | (w[2] >> 5) | (w[3] >> 4);
+    return (y & 0xFu) | ((y >> 4) & 0xF0u) | ((y >> 8) & 0xF00u) | ((y >> 12) & 0xF000u);
 }
 
 extern __shared__ uint64_t lds_bs[];
@@ -241,6 +241,12 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     uint64_t *M = lds_bs + 2 * n;
     uint64_t *Pw = M + v.msel_total;
     uint32_t *Q = (uint32_t *)(Pw + 2 * G) + wave * 3 * kQCap;
+    // this wave's 256 words for the selection-byte transpose
+    uint32_t *TB = (uint32_t *)(Pw + 2 * G) + G * 3 * kQCap + 64 * kMaxProps + wave * 256;
+    // selection lanes: node kk of the block, chain group g; byte kk & 3 of a
+    // word pair is picked by sel_pair
+    const uint32_t kk = lane & 15u, g = lane >> 4;
+    const uint32_t sel_pair = (kk & 3u) | ((4u + (kk & 3u)) << 8) | 0x0C0C0000u;
     const uint64_t words_cap = v.d->words_cap;
 
     // transpose the chains' packed words into node masks
@@ -287,9 +293,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     uint32_t ra_lmax = 0, ra_meta = 0, ra_tb = 0;
     if (res_a && wave < nblk) {
         ra_lmax = v.blk_sel[wave];
-        if (ra_lmax >= 2 && lane < min(16u, n - 16 * wave)) {
-            ra_meta = v.nd_info[2 * (16 * wave + lane)];
-            ra_tb = v.nd_info[2 * (16 * wave + lane) + 1];
+        if (ra_lmax >= 2 && kk < min(16u, n - 16 * wave)) {
+            ra_meta = v.nd_info[2 * (16 * wave + kk)];
+            ra_tb = v.nd_info[2 * (16 * wave + kk) + 1];
         }
     }
     uint32_t rc_K = 1;
@@ -309,8 +315,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
         for (uint32_t q = 0; q < nprops; ++q) {
             uint64_t xm = ~0ull;
             for (uint32_t m = v.d->pn_off[q]; m < v.d->pn_off[q + 1]; ++m) {
-                const uint64_t g = S[v.d->pn_node[m]];
-                xm &= v.d->pn_val[m] ? g : ~g;
+                const uint64_t sv = S[v.d->pn_node[m]];
+                xm &= v.d->pn_val[m] ? sv : ~sv;
             }
             const uint32_t a = acc[64 * q] | ((uint32_t)((xm >> lane) & 1ull) << bpos);
             if (bpos == 31) {
@@ -340,9 +346,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             const uint32_t lmax = res_a ? ra_lmax : v.blk_sel[b];
             // node metadata of the block, one node per lane, fetched ahead of the draws
             uint32_t my_meta = ra_meta, my_tb = ra_tb;
-            if (!res_a && lmax >= 2 && lane < ib) {
-                my_meta = v.nd_info[2 * (i0 + lane)];
-                my_tb = v.nd_info[2 * (i0 + lane) + 1];
+            if (!res_a && lmax >= 2 && kk < ib) {
+                my_meta = v.nd_info[2 * (i0 + kk)];
+                my_tb = v.nd_info[2 * (i0 + kk) + 1];
             }
             uint32_t wp[4];
             philox4(t, c, b, kTagPert, v.key, wp);
@@ -375,28 +381,55 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             if (lmax >= 2) {
                 uint32_t ws[4];
                 philox4(t, c, b, kTagSel, v.key, ws);
-                uint32_t a0l = 0, a0h = 0, a1l = 0, a1h = 0, a2l = 0, a2h = 0, flo = 0, fhi = 0;
+                // transpose through this wave's LDS words: lane = (node kk, chain
+                // group g) gathers byte kk of chains 16 g .. 16 g + 15, word m
+                // holding chains m, m + 4, m + 8, m + 12 of the group
 #pragma unroll
-                for (uint32_t k = 0; k < 16; ++k) {
-                    if (k < ib) {
-                        // top bytes of T_1..T_3 and (byte 3) the predictor count
-                        const uint32_t tbs = __builtin_amdgcn_readlane(my_tb, k);
-                        const uint32_t l = tbs >> 24;
-                        if (l >= 2) {
-                            const uint32_t byte = (ws[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-                            sel_threshold(byte, tbs & 0xFFu, k, 0, a0l, a0h, flo, fhi);
-                            if (l >= 3) sel_threshold(byte, (tbs >> 8) & 0xFFu, k, 1, a1l, a1h, flo, fhi);
-                            if (l >= 4) sel_threshold(byte, (tbs >> 16) & 0xFFu, k, 2, a2l, a2h, flo, fhi);
+                for (uint32_t q = 0; q < 4; ++q) TB[64 * q + lane] = ws[q];
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                uint32_t R[16];
+                {
+                    const uint32_t *src = TB + 64 * (kk >> 2) + 16 * g;
+#pragma unroll
+                    for (uint32_t i = 0; i < 16; ++i) R[i] = src[i];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                uint32_t W[4];
+#pragma unroll
+                for (uint32_t m = 0; m < 4; ++m) {
+                    const uint32_t p1 = __builtin_amdgcn_perm(R[m + 4], R[m], sel_pair);
+                    const uint32_t p2 = __builtin_amdgcn_perm(R[m + 12], R[m + 8], sel_pair);
+                    W[m] = __builtin_amdgcn_perm(p2, p1, 0x05040100u);
+                }
+                // thresholds j of node kk: masks [u < T_j] written per 16-chain
+                // group, equal top bytes queued as ties
+                const uint32_t lk = my_tb >> 24;
+                const bool vk = kk < ib;
+                uint32_t f01 = 0, f2 = 0;
+#pragma unroll
+                for (uint32_t j = 0; j < 3; ++j) {
+                    if (j + 2 <= lmax) {
+                        const bool valid = vk && j + 2 <= lk;
+                        const uint32_t y4 = ((my_tb >> (8 * j)) & 0xFFu) * 0x01010101u;
+                        const uint32_t y7 = y4 & 0x7F7F7F7Fu;
+                        uint32_t lt[4], eq[4];
+#pragma unroll
+                        for (uint32_t m = 0; m < 4; ++m) {
+                            const uint32_t x = W[m];
+                            const uint32_t d = (x | 0x80808080u) - y7;      // bit 7: low 7 bits of x >= those of y
+                            lt[m] = ((~x & y4) | (~(x ^ y4) & ~d)) & 0x80808080u;
+                            const uint32_t z = x ^ y4;
+                            eq[m] = ~(((z & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | z | 0x7F7F7F7Fu);
+                        }
+                        const uint32_t cl = pack16(lt), ce = pack16(eq);
+                        if (valid) {
+                            ((uint16_t *)(M + (my_meta >> 8) + j))[g] = (uint16_t)cl;
+                            if (j < 2) f01 |= ce << (16 * j);
+                            else f2 = ce;
                         }
                     }
                 }
-                if (lane < ib) {
-                    const uint32_t l = my_meta & 0xFFu, moff = my_meta >> 8;
-                    if (l >= 2) M[moff] = ((uint64_t)a0h << 32) | a0l;
-                    if (l >= 3) M[moff + 1] = ((uint64_t)a1h << 32) | a1l;
-                    if (l >= 4) M[moff + 2] = ((uint64_t)a2h << 32) | a2l;
-                }
-                push((flo | fhi) != 0, 1u | (lane << 1) | (b << 7), flo, fhi, Q, qlen);
+                push((f01 | f2) != 0, 1u | (kk << 1) | (g << 5) | (b << 7), f01, f2, Q, qlen);
                 if (lmax >= 5) {
                     // thresholds 4.. of nodes with more than four predictors,
                     // straight from fn_thr with their ties refined in place
@@ -507,7 +540,8 @@ static int check_bs(hipError_t e, const char *what, std::string &err)
 
 size_t bs_lds_bytes(uint32_t n, uint32_t msel_total, uint32_t G)
 {
-    return (size_t)8 * (2 * (size_t)n + msel_total + 2 * G) + (size_t)4 * 3 * kQCap * G + (size_t)4 * 64 * kMaxProps;
+    return (size_t)8 * (2 * (size_t)n + msel_total + 2 * G) + (size_t)4 * 3 * kQCap * G + (size_t)4 * 64 * kMaxProps +
+           (size_t)4 * 256 * G;
 }
 
 int launch_step_bs(const StepItem *d_items, uint32_t nitems, uint32_t G, bool small, size_t lds, void *stream,
