@@ -1205,10 +1205,9 @@ int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
             if (L.ctx.pending) { any_pending = true; all_done = false; continue; }
             if (L.finished()) continue;
             all_done = false;
-            // the express lane always takes latency shapes and whole extensions
+            // the express lane takes whole extensions
             const double tick = k < nl ? kTickUs : 0.0;
-            const int lat = k < nl ? latency : 1;
-            if ((rc = round_begin(L.runs, L.ws, L.stream, L.ctx, err, false, tick, lat))) break;
+            if ((rc = round_begin(L.runs, L.ws, L.stream, L.ctx, err, false, tick, latency))) break;
             if (L.ctx.pending) any_pending = true;
         }
         if (rc || all_done) break;
