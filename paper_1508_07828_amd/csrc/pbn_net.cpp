@@ -194,8 +194,9 @@ int parse_and_compile(const char *text, size_t len, Net &net, std::string &err)
     place(net.off_par, 2 * net.par.size());
     // interleaved records for the bit-sliced kernel: per node (meta, top bytes),
     // per predictor slot (node, table lo, table hi, mask below, mask up to,
-    // parents 0|1, 2|3, 4|5 as u16 pairs)
-    std::vector<uint32_t> nd_info(2 * (size_t)net.nd_meta.size()), fs_rec(8 * (size_t)net.F_pad);
+    // parents 0|1, 2|3, 4|5 as u16 pairs); node records padded with zeros to
+    // whole 16-node blocks, so a block's 32 words load without bounds checks
+    std::vector<uint32_t> nd_info(32 * (size_t)((net.nd_meta.size() + 15) / 16)), fs_rec(8 * (size_t)net.F_pad);
     for (size_t i = 0; i < net.nd_meta.size(); ++i) {
         nd_info[2 * i] = net.nd_meta[i];
         nd_info[2 * i + 1] = net.nd_tb[i];

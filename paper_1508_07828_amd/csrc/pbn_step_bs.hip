@@ -38,6 +38,7 @@ namespace pbn {
 __device__ uint32_t amdgcn_writelane(uint32_t src, uint32_t lane, uint32_t old) __asm("llvm.amdgcn.writelane.i32");
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
 
 // What the bit-sliced kernel reads, with as few live pointers as possible.
 struct BsView {
@@ -143,9 +144,8 @@ __device__ __forceinline__ uint32_t bytes_eq(uint32_t x, uint32_t m4)
 // Queue entry: header and a 64-bit flag word (lo, hi).
 //   kind 0, perturbation ties of chain lane: header 0 | lane << 1 | block << 7,
 //     flag 8 bb + q = node 16 b + 4 q + bb
-//   kind 1, selection ties of node k (of block b) in chains 16 g .. 16 g + 15:
-//     header 1 | k << 1 | g << 5 | block << 7, flag 16 j + x = threshold j of
-//     chain 16 g + x
+//   kind 1, selection ties of threshold j of node k (of block b):
+//     header 1 | k << 1 | j << 5 | block << 7, flag x = chain x
 __device__ __forceinline__ void push(bool mine, uint32_t hdr, uint32_t flo, uint32_t fhi, uint32_t *Q,
                                      uint32_t &qlen)
 {
@@ -184,9 +184,9 @@ __device__ __forceinline__ void resolve(const BsView &v, uint32_t t, uint32_t ch
                 i = 16 * b + 4 * (x & 7u) + (x >> 3);
                 j = 0;
             } else {
-                cl = 16 * ((hdr >> 5) & 3u) + (x & 15u);
+                cl = x;
                 i = 16 * b + ((hdr >> 1) & 15u);
-                j = x >> 4;
+                j = (hdr >> 5) & 3u;
             }
             const uint32_t key = (cl << 24) | (i >> 2);
             if (key != rq) {
@@ -207,14 +207,6 @@ __device__ __forceinline__ void resolve(const BsView &v, uint32_t t, uint32_t ch
         if (flipped) lds_or(Pw_mine, 1ull << ((hdr >> 1) & 63u));
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-}
-
-// Sixteen byte-compare flags (bit 7 of each byte of w[m]; byte bb of w[m]
-// belongs to chain m + 4 bb) packed as bit m + 4 bb.
-__device__ __forceinline__ uint32_t pack16(const uint32_t w[4])
-{
-    const uint32_t y = (w[0] >> 7) | (w[1] >> 6) | (w[2] >> 5) | (w[3] >> 4);
-    return (y & 0xFu) | ((y >> 4) & 0xF0u) | ((y >> 8) & 0xF00u) | ((y >> 12) & 0xF000u);
 }
 
 extern __shared__ uint64_t lds_bs[];
@@ -241,12 +233,6 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     uint64_t *M = lds_bs + 2 * n;
     uint64_t *Pw = M + v.msel_total;
     uint32_t *Q = (uint32_t *)(Pw + 2 * G) + wave * 3 * kQCap;
-    // this wave's 256 words for the selection-byte transpose
-    uint32_t *TB = (uint32_t *)(Pw + 2 * G) + G * 3 * kQCap + 64 * kMaxProps + wave * 256;
-    // selection lanes: node kk of the block, chain group g; byte kk & 3 of a
-    // word pair is picked by sel_pair
-    const uint32_t kk = lane & 15u, g = lane >> 4;
-    const uint32_t sel_pair = (kk & 3u) | ((4u + (kk & 3u)) << 8) | 0x0C0C0000u;
     const uint64_t words_cap = v.d->words_cap;
 
     // transpose the chains' packed words into node masks
@@ -290,13 +276,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     // (the small form keeps them register-resident; the flags stay run-time so
     // the compiler does not trade registers for the single-iteration loops)
     const bool res_a = SMALL && nblk <= G, res_c = SMALL && F_pad <= 64 * G;
-    uint32_t ra_lmax = 0, ra_meta = 0, ra_tb = 0;
+    uint32_t ra_lmax = 0, ra_meta = 0;
     if (res_a && wave < nblk) {
         ra_lmax = v.blk_sel[wave];
-        if (ra_lmax >= 2 && kk < min(16u, n - 16 * wave)) {
-            ra_meta = v.nd_info[2 * (16 * wave + kk)];
-            ra_tb = v.nd_info[2 * (16 * wave + kk) + 1];
-        }
+        if (ra_lmax >= 2 && lane < min(16u, n - 16 * wave)) ra_meta = v.nd_info[2 * (16 * wave + lane)];
     }
     uint32_t rc_K = 1;
     u32x4 rc0 = {0u, 0u, 0u, 0u}, rc1 = {0u, 0u, 0u, 0u};
@@ -345,11 +328,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             const uint32_t i0 = 16 * b, ib = min(16u, n - i0);
             const uint32_t lmax = res_a ? ra_lmax : v.blk_sel[b];
             // node metadata of the block, one node per lane, fetched ahead of the draws
-            uint32_t my_meta = ra_meta, my_tb = ra_tb;
-            if (!res_a && lmax >= 2 && kk < ib) {
-                my_meta = v.nd_info[2 * (i0 + kk)];
-                my_tb = v.nd_info[2 * (i0 + kk) + 1];
-            }
+            uint32_t my_meta = ra_meta;
+            if (!res_a && lmax >= 2 && lane < ib) my_meta = v.nd_info[2 * (i0 + lane)];
             uint32_t wp[4];
             philox4(t, c, b, kTagPert, v.key, wp);
             // tie flags: bit 8 bb + q <-> node 4 q + bb (byte bb of word q)
@@ -381,60 +361,62 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             if (lmax >= 2) {
                 uint32_t ws[4];
                 philox4(t, c, b, kTagSel, v.key, ws);
-                // transpose through this wave's LDS words: lane = (node kk, chain
-                // group g) gathers byte kk of chains 16 g .. 16 g + 15, word m
-                // holding chains m, m + 4, m + 8, m + 12 of the group
+                // one ballot per (node k, threshold j < 3) against the top byte of
+                // T_j (uniform, from scalar loads); lane k of a[j] gathers node k's
+                // mask, and each (node, threshold) with equal bytes is queued with
+                // its chain flags
+                const PBN_CAS uint32_t *info = v.nd_info + 32 * (size_t)b;
+                const PBN_CAS u32x8 *quads = (const PBN_CAS u32x8 *)info;
+                uint32_t al[3] = {0u, 0u, 0u}, ah[3] = {0u, 0u, 0u};
+                uint32_t eh = 0, el = 0, eu = 0, ne = 0;
+                // node records four at a time (one scalar load each), the next
+                // quad's load issued before the current quad's compares
+                u32x8 rq = quads[0], rn = rq;
 #pragma unroll
-                for (uint32_t q = 0; q < 4; ++q) TB[64 * q + lane] = ws[q];
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                uint32_t R[16];
-                {
-                    const uint32_t *src = TB + 64 * (kk >> 2) + 16 * g;
+                for (uint32_t k = 0; k < 16; ++k) {
+                    if ((k & 3u) == 0) {
+                        rq = rn;
+                        if (k < 12) rn = quads[(k >> 2) + 1];
+                    }
+                    const uint32_t tbs = rq[2 * (k & 3u) + 1];
+                    const uint32_t l = tbs >> 24;     // 0 for nodes past n
+                    if (l < 2) continue;
+                    const uint32_t byte = (ws[k >> 2] >> (8 * (k & 3))) & 0xFFu;
 #pragma unroll
-                    for (uint32_t i = 0; i < 16; ++i) R[i] = src[i];
-                }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                uint32_t W[4];
-#pragma unroll
-                for (uint32_t m = 0; m < 4; ++m) {
-                    const uint32_t p1 = __builtin_amdgcn_perm(R[m + 4], R[m], sel_pair);
-                    const uint32_t p2 = __builtin_amdgcn_perm(R[m + 12], R[m + 8], sel_pair);
-                    W[m] = __builtin_amdgcn_perm(p2, p1, 0x05040100u);
-                }
-                // thresholds j of node kk: masks [u < T_j] written per 16-chain
-                // group, equal top bytes queued as ties
-                const uint32_t lk = my_tb >> 24;
-                const bool vk = kk < ib;
-                uint32_t f01 = 0, f2 = 0;
-#pragma unroll
-                for (uint32_t j = 0; j < 3; ++j) {
-                    if (j + 2 <= lmax) {
-                        const bool valid = vk && j + 2 <= lk;
-                        const uint32_t y4 = ((my_tb >> (8 * j)) & 0xFFu) * 0x01010101u;
-                        const uint32_t y7 = y4 & 0x7F7F7F7Fu;
-                        uint32_t lt[4], eq[4];
-#pragma unroll
-                        for (uint32_t m = 0; m < 4; ++m) {
-                            const uint32_t x = W[m];
-                            const uint32_t d = (x | 0x80808080u) - y7;      // bit 7: low 7 bits of x >= those of y
-                            lt[m] = ((~x & y4) | (~(x ^ y4) & ~d)) & 0x80808080u;
-                            const uint32_t z = x ^ y4;
-                            eq[m] = ~(((z & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | z | 0x7F7F7F7Fu);
-                        }
-                        const uint32_t cl = pack16(lt), ce = pack16(eq);
-                        if (valid) {
-                            ((uint16_t *)(M + (my_meta >> 8) + j))[g] = (uint16_t)cl;
-                            if (j < 2) f01 |= ce << (16 * j);
-                            else f2 = ce;
+                    for (uint32_t j = 0; j < 3; ++j) {
+                        if (j + 2 > l) break;
+                        const uint32_t tb = (tbs >> (8 * j)) & 0xFFu;
+                        const uint64_t lt = __ballot(byte < tb);
+                        const uint64_t eq = __ballot(byte == tb);
+                        al[j] = amdgcn_writelane((uint32_t)lt, k, al[j]);
+                        ah[j] = amdgcn_writelane((uint32_t)(lt >> 32), k, ah[j]);
+                        if (eq) {
+                            eh = amdgcn_writelane(1u | (k << 1) | (j << 5) | (b << 7), ne, eh);
+                            el = amdgcn_writelane((uint32_t)eq, ne, el);
+                            eu = amdgcn_writelane((uint32_t)(eq >> 32), ne, eu);
+                            ++ne;
                         }
                     }
                 }
-                push((f01 | f2) != 0, 1u | (kk << 1) | (g << 5) | (b << 7), f01, f2, Q, qlen);
+                if (lane < ib) {
+                    const uint32_t l = my_meta & 0xFFu, moff = my_meta >> 8;
+#pragma unroll
+                    for (uint32_t j = 0; j < 3; ++j)
+                        if (j + 2 <= l) M[moff + j] = ((uint64_t)ah[j] << 32) | al[j];
+                }
+                if (ne) {
+                    if (lane < ne) {
+                        Q[qlen + lane] = eh;
+                        Q[kQCap + qlen + lane] = el;
+                        Q[2 * kQCap + qlen + lane] = eu;
+                    }
+                    qlen += ne;
+                }
                 if (lmax >= 5) {
                     // thresholds 4.. of nodes with more than four predictors,
                     // straight from fn_thr with their ties refined in place
                     for (uint32_t k = 0; k < ib; ++k) {
-                        const uint32_t meta = __builtin_amdgcn_readlane(my_meta, k);
+                        const uint32_t meta = info[2 * k];
                         const uint32_t l = meta & 0xFFu;
                         if (l < 5) continue;
                         const uint32_t i = i0 + k;
@@ -540,8 +522,7 @@ static int check_bs(hipError_t e, const char *what, std::string &err)
 
 size_t bs_lds_bytes(uint32_t n, uint32_t msel_total, uint32_t G)
 {
-    return (size_t)8 * (2 * (size_t)n + msel_total + 2 * G) + (size_t)4 * 3 * kQCap * G + (size_t)4 * 64 * kMaxProps +
-           (size_t)4 * 256 * G;
+    return (size_t)8 * (2 * (size_t)n + msel_total + 2 * G) + (size_t)4 * 3 * kQCap * G + (size_t)4 * 64 * kMaxProps;
 }
 
 int launch_step_bs(const StepItem *d_items, uint32_t nitems, uint32_t G, bool small, size_t lds, void *stream,
