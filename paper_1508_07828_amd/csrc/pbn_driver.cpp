@@ -1200,6 +1200,11 @@ int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
         for (SimRun *r : runs)
             if (!r->finished()) waves += latency_waves(r->sim);
         const int latency = waves <= kLatencyWaves;
+        // a small express remainder runs in its latency shape beside the bulk
+        uint64_t xwaves = 0;
+        for (SimRun *r : P.express.runs)
+            if (!r->finished()) xwaves += latency_waves(r->sim);
+        const int xlatency = latency || xwaves <= kExpressLatencyWaves;
         for (int k = 0; k <= nl; ++k) {
             Lane &L = k < nl ? *P.lane[k] : P.express;
             if (L.ctx.pending) { any_pending = true; all_done = false; continue; }
@@ -1207,7 +1212,7 @@ int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
             all_done = false;
             // the express lane takes whole extensions
             const double tick = k < nl ? kTickUs : 0.0;
-            if ((rc = round_begin(L.runs, L.ws, L.stream, L.ctx, err, false, tick, latency))) break;
+            if ((rc = round_begin(L.runs, L.ws, L.stream, L.ctx, err, false, tick, k < nl ? latency : xlatency))) break;
             if (L.ctx.pending) any_pending = true;
         }
         if (rc || all_done) break;

@@ -124,6 +124,9 @@ constexpr uint64_t kLatencyWaves = 256 * 24;
 uint64_t latency_waves(const pbn_sim *sim);
 // Kernel time per extension slice of a time-sliced round (microseconds).
 constexpr double kTickUs = 5000.0;
+// The express lane of a batch takes its latency shape once its unfinished work
+// is at most this many waves (a few CUs' worth beside the bulk).
+constexpr uint64_t kExpressLatencyWaves = 512;
 // XCDs of the chip: block i of a launch runs on XCD i mod kXcds.
 constexpr size_t kXcds = 8;
 
