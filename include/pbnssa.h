@@ -246,6 +246,19 @@ int pbn_profile_enable(int on);
  * the bit-sliced kernel (0 = chosen from n, else 1, 2, 4, 8 or 16).  Results do not
  * depend on the choice. */
 int pbn_set_kernel(int mode, uint32_t waves);
+/* Node-split form of the bit-sliced trajectory step (a latency-bound 64-chain
+ * group spread over several CUs: each block owns a contiguous range of nodes,
+ * and the blocks of a group exchange their nodes' next-state words through
+ * device memory once per transition, behind a bounded arrival counter).  It
+ * is used only by calls that own the device while they run: run_chains,
+ * pbn_batch_run, estimate_prob, a single-network pbn_batch_estimate and the
+ * server rounds.  parts: 0 = automatic (launches of at most 128 64-chain
+ * groups, up to 256 / groups parts of at least 8 node blocks, at most 16),
+ * 1 = never, P >= 2 = P parts for every bit-sliced group whose network has at
+ * least P 16-node blocks (fewer otherwise).  Results do not depend on the
+ * choice.  A group whose blocks cannot all be resident gives up after about a
+ * second and the call returns PBN_EDEVICE. */
+int pbn_set_split(uint32_t parts);
 int pbn_profile_read(pbn_profile *out);
 int pbn_profile_reset(void);
 

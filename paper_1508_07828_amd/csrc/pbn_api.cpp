@@ -149,7 +149,12 @@ int run_chains(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin)
     std::vector<pbn::StepItem> items;
     pbn::sim_extend_items(sim, burn_in, steps, thin, items, pbn::latency_waves(sim) <= pbn::kLatencyWaves);
     std::string err;
-    int rc = pbn::launch_items(items, sim->ws, sim->stream, err);
+    int rc = pbn::launch_items(items, sim->ws, sim->stream, err, true, true);
+    if (!rc && sim->ws.split_used) {
+        // a node-split launch is checked before the call returns
+        if (hipStreamSynchronize(sim->stream) != hipSuccess) return fail(PBN_EDEVICE, "stream synchronize");
+        rc = sim->ws.check_split(err);
+    }
     return rc ? fail(rc, err) : PBN_OK;
 }
 
@@ -276,9 +281,11 @@ int pbn_batch_run(pbn_sim *const *sims, uint32_t count, const uint64_t *steps, v
         if (steps[i]) pbn::sim_extend_items(sims[i], 0, steps[i], 1, items, latency);
     static thread_local pbn::Workspace ws;
     std::string err;
-    int rc = pbn::launch_items(items, ws, (hipStream_t)hip_stream, err);
+    int rc = pbn::launch_items(items, ws, (hipStream_t)hip_stream, err, true, true);
     if (rc) return fail(rc, err);
-    return sync((hipStream_t)hip_stream);
+    if ((rc = sync((hipStream_t)hip_stream))) return rc;
+    if ((rc = ws.check_split(err))) return fail(rc, err);
+    return PBN_OK;
 }
 
 int pbn_batch_estimate(pbn_sim *const *sims, uint32_t count, const pbn_pattern *props, const uint32_t *nprops,
@@ -512,6 +519,12 @@ int pbn_set_kernel(int mode, uint32_t waves)
     if (mode < 0 || mode > 2 || (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 16))
         return fail(PBN_EINVAL, "mode must be 0..2 and waves 0, 1, 2, 4, 8 or 16");
     pbn::set_kernel_mode(mode, waves);
+    return PBN_OK;
+}
+
+int pbn_set_split(uint32_t parts)
+{
+    pbn::set_split_mode(parts);
     return PBN_OK;
 }
 

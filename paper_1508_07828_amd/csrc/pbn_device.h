@@ -116,7 +116,8 @@ __device__ __forceinline__ StepItem load_item(const StepItem *items, uint32_t b)
     it.kernel = p->kernel;
     it.lds = p->lds;
     it.small = 0;
-    it.pad_ = 0;
+    it.part = p->part;
+    it.grp = p->grp;
     return it;
 }
 

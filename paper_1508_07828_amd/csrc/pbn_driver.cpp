@@ -109,8 +109,71 @@ int Workspace::ensure_stage(size_t count, std::string &err)
     return PBN_OK;
 }
 
+int Workspace::ensure_split(size_t groups, size_t xch_words, std::string &err)
+{
+    if (!d_err) {
+        if (hipMalloc((void **)&d_err, sizeof(uint32_t)) != hipSuccess ||
+            hipHostMalloc((void **)&h_err, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+            err = "workspace split flag";
+            return PBN_ENOMEM;
+        }
+        *h_err = 0;
+    }
+    if (groups > cap_grp) {
+        const size_t nc = std::max(groups, 2 * cap_grp);
+        if (d_grp) (void)hipFree(d_grp);
+        if (h_grp) (void)hipHostFree(h_grp);
+        if (d_ctr) (void)hipFree(d_ctr);
+        d_grp = h_grp = nullptr;
+        d_ctr = nullptr;
+        cap_grp = 0;
+        if (hipMalloc((void **)&d_grp, nc * sizeof(SplitGroup)) != hipSuccess ||
+            hipHostMalloc((void **)&h_grp, nc * sizeof(SplitGroup), hipHostMallocDefault) != hipSuccess ||
+            hipMalloc((void **)&d_ctr, nc * sizeof(uint32_t)) != hipSuccess) {
+            err = "workspace split groups";
+            return PBN_ENOMEM;
+        }
+        cap_grp = nc;
+    }
+    if (xch_words > cap_xch) {
+        const size_t nc = std::max(xch_words, 2 * cap_xch);
+        if (d_xch) (void)hipFree(d_xch);
+        d_xch = nullptr;
+        cap_xch = 0;
+        if (hipMalloc((void **)&d_xch, nc * sizeof(uint64_t)) != hipSuccess) {
+            err = "workspace split exchange";
+            return PBN_ENOMEM;
+        }
+        cap_xch = nc;
+    }
+    return PBN_OK;
+}
+
+int Workspace::check_split(std::string &err)
+{
+    if (!split_used) return PBN_OK;
+    split_used = false;
+    if (h_err && *h_err) {
+        *h_err = 0;
+        err = "node-split step: a block gave up waiting for its group (the launch did not fit on the device)";
+        return PBN_EDEVICE;
+    }
+    return PBN_OK;
+}
+
 void Workspace::release()
 {
+    if (d_grp) (void)hipFree(d_grp);
+    if (h_grp) (void)hipHostFree(h_grp);
+    if (d_ctr) (void)hipFree(d_ctr);
+    if (d_xch) (void)hipFree(d_xch);
+    if (d_err) (void)hipFree(d_err);
+    if (h_err) (void)hipHostFree(h_err);
+    d_grp = h_grp = nullptr;
+    d_xch = nullptr;
+    d_ctr = d_err = h_err = nullptr;
+    cap_grp = cap_xch = 0;
+    split_used = false;
     if (ev_items) (void)hipEventSynchronize(ev_items), (void)hipEventDestroy(ev_items);
     if (ev_queries) (void)hipEventSynchronize(ev_queries), (void)hipEventDestroy(ev_queries);
     ev_items = ev_queries = nullptr;
@@ -580,6 +643,7 @@ void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t t
         it.nodes = sim->net.n;
         it.ops_per_step = (float)sim->net.ops_per_step;
         it.philox_per_step = (float)sim->net.philox_per_step;
+        it.owner = sim;
         choose_kernel(sim->net, it, latency);
         items.push_back(it);
     }
@@ -604,6 +668,12 @@ void set_kernel_mode(int mode, uint32_t waves)
     g_kernel_mode = mode;
     g_waves_override = waves;
 }
+
+namespace {
+uint32_t g_split_mode = 0;
+}  // namespace
+
+void set_split_mode(uint32_t parts) { g_split_mode = parts; }
 
 uint64_t latency_waves(const pbn_sim *sim)
 {
@@ -670,14 +740,132 @@ StreamPool &stream_pool()
 
 
 
+// Node-split tables of sim for P parts, built and uploaded on first use.
+int split_table(pbn_sim *sim, uint32_t P, pbn_sim::SplitTab &out, std::string &err)
+{
+    for (const pbn_sim::SplitTab &t : sim->split_tabs)
+        if (t.P == P) {
+            out = t;
+            return PBN_OK;
+        }
+    const Net &net = sim->net;
+    std::vector<uint32_t> tab;
+    build_split_tables(net, P, tab);
+    pbn_sim::SplitTab t;
+    t.P = P;
+    t.groups = tab[2 * P + 1];
+    for (uint32_t r = 0; r < P; ++r) {
+        const uint32_t i_lo = 16 * tab[r], i_hi = std::min(net.n, 16 * tab[r + 1]);
+        const uint32_t m_lo = net.nd_meta[i_lo] >> 8, m_hi = i_hi < net.n ? net.nd_meta[i_hi] >> 8 : net.msel_total;
+        t.n_own = std::max(t.n_own, i_hi - i_lo);
+        t.m_own = std::max(t.m_own, m_hi - m_lo);
+    }
+    if (hipMalloc((void **)&t.d_tab, tab.size() * sizeof(uint32_t)) != hipSuccess) {
+        err = "node-split tables";
+        return PBN_ENOMEM;
+    }
+    if (hipMemcpy(t.d_tab, tab.data(), tab.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(t.d_tab);
+        err = "node-split table upload";
+        return PBN_EDEVICE;
+    }
+    sim->split_tabs.push_back(t);
+    out = t;
+    return PBN_OK;
+}
+
+// Spread latency-bound 64-chain groups over several CUs: automatic when the
+// launch has at most 128 blocks (each group then takes up to 256 / blocks
+// parts, at least 8 node blocks per part, at most 16 parts), or a forced part
+// count.  Every node-split group's parts are marked small = 2.
+int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, size_t &ngroups)
+{
+    ngroups = 0;
+    uint32_t P_auto = 0;
+    if (g_split_mode == 0) {
+        if (items.size() > 128) return PBN_OK;
+        P_auto = (uint32_t)std::min<size_t>(16, 256 / items.size());
+    }
+    struct Plan {
+        size_t idx;
+        uint32_t P, G, lds;
+        pbn_sim::SplitTab tab;
+    };
+    std::vector<Plan> plan;
+    size_t xwords = 0, extra = 0;
+    for (size_t i = 0; i < items.size(); ++i) {
+        const StepItem &it = items[i];
+        if (it.kernel == 0 || !it.owner || it.nchains == 0) continue;
+        pbn_sim *sim = (pbn_sim *)it.owner;
+        const uint32_t nblk = sim->net.nblk;
+        const uint32_t P = g_split_mode >= 2 ? std::min(g_split_mode, nblk) : std::min(P_auto, nblk / 8);
+        if (P < 2) continue;
+        const uint32_t per = (nblk + P - 1) / P;
+        uint32_t G = 16;
+        while (G > 1 && G > per) G /= 2;
+        if (g_waves_override) G = g_waves_override;
+        pbn_sim::SplitTab tab;
+        int rc = split_table(sim, P, tab, err);
+        if (rc) return rc;
+        size_t lds = split_lds_bytes(sim->net.n, tab.n_own, tab.m_own, G);
+        while (lds > 160 * 1024 && G > 1 && !g_waves_override) {
+            G /= 2;
+            lds = split_lds_bytes(sim->net.n, tab.n_own, tab.m_own, G);
+        }
+        if (lds > 160 * 1024) continue;
+        plan.push_back(Plan{i, P, G, (uint32_t)lds, tab});
+        xwords += 4 * (size_t)sim->net.n + 2 * (size_t)P;
+        extra += P - 1;
+    }
+    if (plan.empty()) return PBN_OK;
+    int rc = ws.ensure_split(plan.size(), xwords, err);
+    if (rc) return rc;
+    std::vector<StepItem> out;
+    out.reserve(items.size() + extra);
+    std::vector<int> which(items.size(), -1);
+    for (size_t q = 0; q < plan.size(); ++q) which[plan[q].idx] = (int)q;
+    size_t xoff = 0;
+    for (size_t i = 0; i < items.size(); ++i) {
+        if (which[i] < 0) {
+            out.push_back(items[i]);
+            continue;
+        }
+        const size_t q = (size_t)which[i];
+        const Plan &p = plan[q];
+        const pbn_sim *sim = (const pbn_sim *)items[i].owner;
+        SplitGroup &g = ws.h_grp[q];
+        g.tab = p.tab.d_tab;
+        g.xch = ws.d_xch + xoff;
+        g.ctr = ws.d_ctr + q;
+        g.err = ws.d_err;
+        g.nparts = p.P;
+        g.groups = p.tab.groups;
+        xoff += 4 * (size_t)sim->net.n + 2 * (size_t)p.P;
+        for (uint32_t r = 0; r < p.P; ++r) {
+            StepItem s = items[i];
+            s.part = r;
+            s.grp = ws.d_grp + q;
+            s.kernel = p.G;
+            s.lds = p.lds;
+            s.small = 2;
+            out.push_back(s);
+        }
+    }
+    items.swap(out);
+    ngroups = plan.size();
+    return PBN_OK;
+}
+
 }  // namespace
 
 int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream, std::string &err,
-                 bool allow_fork)
+                 bool allow_fork, bool allow_split)
 {
     if (items.empty()) return PBN_OK;
     int rc = ws.before_write(ws.ev_items, ws.items_in_flight, err);
     if (rc) return rc;
+    size_t nsplit = 0;
+    if (allow_split && g_split_mode != 1 && (rc = split_expand(items, ws, err, nsplit))) return rc;
     // groups of equal kernel form; inside a group the longest
     // items first, since the hardware dispatches blocks roughly in order
     struct Key { uint32_t kernel, cls; double cost; size_t idx; };
@@ -778,6 +966,15 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
         err = "item upload";
         return PBN_EDEVICE;
     }
+    if (nsplit) {
+        if (hipMemcpyAsync(ws.d_grp, ws.h_grp, nsplit * sizeof(SplitGroup), hipMemcpyHostToDevice, stream) !=
+                hipSuccess ||
+            hipMemsetAsync(ws.d_ctr, 0, nsplit * sizeof(uint32_t), stream) != hipSuccess ||
+            hipMemsetAsync(ws.d_err, 0, sizeof(uint32_t), stream) != hipSuccess) {
+            err = "node-split group upload";
+            return PBN_EDEVICE;
+        }
+    }
     if ((rc = ws.after_copy(ws.ev_items, ws.items_in_flight, stream, err))) return rc;
     // one profiling mark per kernel dispatch, on the stream it runs on
     const bool prof_on = profiling();
@@ -787,6 +984,7 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
         if (prof_on) {
             for (size_t i = g.first; i < g.first + g.count; ++i) {
                 const StepItem &it = ws.h_items[i];
+                if (it.small == 2 && it.part != 0) continue;     // a node-split group counts once
                 const double cs = (double)(it.nburn + (uint64_t)it.nrec * it.thin) * it.nchains;
                 mark.chain_steps += cs;
                 mark.node_updates += cs * it.nodes;
@@ -795,8 +993,9 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
             }
             profile_begin(mark, s);
         }
-        const int r = g.kernel == 0 ? launch_step(d, (uint32_t)g.count, g.maxW, s, err)
-                                    : launch_step_bs(d, (uint32_t)g.count, g.kernel, (g.cls >> 16) != 0, g.lds, s, err);
+        const int r = g.kernel == 0           ? launch_step(d, (uint32_t)g.count, g.maxW, s, err)
+                      : (g.cls >> 16) == 2 ? launch_step_split(d, (uint32_t)g.count, g.kernel, g.lds, s, err)
+                                           : launch_step_bs(d, (uint32_t)g.count, g.kernel, (g.cls >> 16) != 0, g.lds, s, err);
         if (prof_on) profile_end(mark, s);
         return r;
     };
@@ -819,6 +1018,13 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
                 return PBN_EDEVICE;
             }
         }
+    }
+    if (!rc && nsplit) {
+        if (hipMemcpyAsync(ws.h_err, ws.d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, stream) != hipSuccess) {
+            err = "node-split flag download";
+            return PBN_EDEVICE;
+        }
+        ws.split_used = true;
     }
     return rc;
 }
@@ -975,7 +1181,7 @@ int round_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, 
             sim_extend_items(sim, 0, ext, 1, items, latency != 0);
         }
     }
-    int rc = launch_items(items, ws, stream, err, allow_fork);
+    int rc = launch_items(items, ws, stream, err, allow_fork, allow_fork);
     if (rc) return rc;
     // 2. queries for every ready request
     std::vector<Query> qs;
@@ -1052,7 +1258,7 @@ int run_round(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
     if (!rc && ctx.pending) {
         hipError_t e = hipEventSynchronize(ctx.done);
         if (e != hipSuccess) { err = std::string("round sync: ") + hipGetErrorString(e); rc = PBN_EDEVICE; }
-        else round_end(ws, ctx);
+        else if (!(rc = ws.check_split(err))) round_end(ws, ctx);
     }
     if (ctx.done) (void)hipEventDestroy(ctx.done);
     return rc;
@@ -1256,3 +1462,10 @@ int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
 }
 
 }  // namespace pbn
+
+pbn_sim::~pbn_sim()
+{
+    if (!split_tabs.empty()) (void)hipDeviceSynchronize();
+    for (SplitTab &t : split_tabs)
+        if (t.d_tab) (void)hipFree(t.d_tab);
+}

@@ -35,6 +35,17 @@ struct Workspace {
     int before_write(hipEvent_t &ev, bool &in_flight, std::string &err);
     int after_copy(hipEvent_t &ev, bool &in_flight, hipStream_t stream, std::string &err);
     int ensure_stage(size_t count, std::string &err);
+    // node-split form: group descriptors (pinned staging, device), exchange
+    // area, arrival counters and the error word of the last launch
+    SplitGroup *d_grp = nullptr, *h_grp = nullptr;
+    uint64_t *d_xch = nullptr;
+    uint32_t *d_ctr = nullptr, *d_err = nullptr, *h_err = nullptr;
+    size_t cap_grp = 0, cap_xch = 0;
+    bool split_used = false;      // the last launch had node-split groups
+    int ensure_split(size_t groups, size_t xch_words, std::string &err);
+    // after the stream reached the last launch: PBN_EDEVICE if a node-split
+    // group gave up waiting
+    int check_split(std::string &err);
     void release();
     ~Workspace() { release(); }
 };
@@ -89,6 +100,7 @@ private:
 }  // namespace pbn
 
 struct pbn_sim {
+    ~pbn_sim();
     pbn::Net net;
     uint32_t omega = 0, max_props = 0, nprops = 0;
     uint64_t seed = 0, max_len = 0, words_cap = 0;
@@ -99,6 +111,12 @@ struct pbn_sim {
     pbn::DevSim *d_desc = nullptr;
     uint64_t len = 0, t_done = 0;
     pbn::Workspace ws;
+    // node-split tables uploaded so far, by part count
+    struct SplitTab {
+        uint32_t P = 0, groups = 0, n_own = 0, m_own = 0;
+        uint32_t *d_tab = nullptr;
+    };
+    std::vector<SplitTab> split_tabs;
 };
 
 namespace pbn {
@@ -184,9 +202,15 @@ int autotune(hipStream_t stream, pbn_tune_row *rows, uint32_t cap, uint32_t *cou
 void autotune_reset();
 uint32_t waves_for(uint32_t n, bool latency);
 void set_kernel_mode(int mode, uint32_t waves);
+// Node-split form: 0 = automatic, 1 = never, P >= 2 = P parts wherever the
+// network has P node blocks (launches that allow it).
+void set_split_mode(uint32_t parts);
 
-// Launch step items for several sims (sorted by cost) on stream.
+// Launch step items for several sims (sorted by cost) on stream.  allow_split:
+// the launch owns the device (nothing else runs beside it that could hold the
+// CUs its node-split groups wait for), so latency-bound 64-chain groups may
+// be spread over several CUs; ws.check_split then tells whether they finished.
 int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream, std::string &err,
-                 bool allow_fork = true);
+                 bool allow_fork = true, bool allow_split = false);
 
 }  // namespace pbn

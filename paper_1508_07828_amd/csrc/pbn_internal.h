@@ -85,6 +85,34 @@ struct DevSim {
     uint32_t F_pad, msel_total, nblk, pad0;
 };
 
+// Node-split form of the bit-sliced step: P blocks on P CUs share one 64-chain
+// group, block r owning a contiguous range of 16-node blocks and the predictor
+// slots of those nodes.  Each transition every block publishes, for its own
+// nodes, the perturbation flips and the function values, plus its chains'
+// perturbed flags, and reads everyone's after a counter barrier.
+//   tab: u32 [0, P]  first 16-node block of part r (tab[P] = nblk)
+//            [P + 1, 2P + 1]  first 64-slot group of part r (tab[2P + 1] = groups)
+//            at split_head(P): K of every slot group, then (16-byte aligned) the
+//            slot records, 8 words each, as in DevSim::fs_rec
+//   xch: u64 [2][2n] (perturbation flips, function values of node i at 2i,
+//        2i + 1) then [2][P] perturbed-chain words, by transition parity
+//   ctr: arrivals, one per part and transition, zero at launch
+//   err: set to 1 when a barrier wait times out (the launch then ends early)
+struct SplitGroup {
+    const uint32_t *tab;
+    uint64_t *xch;
+    uint32_t *ctr;
+    uint32_t *err;
+    uint32_t nparts, groups;
+};
+// Polls of a block's counter wait before it gives up (each poll reads the
+// counter from memory and sleeps, together well over 100 ns).
+constexpr uint32_t kSplitSpins = 1u << 20;
+constexpr uint32_t split_head(uint32_t P) { return 2 * (P + 1); }
+constexpr uint32_t split_rec_off(uint32_t P, uint32_t groups) { return (split_head(P) + groups + 3) / 4 * 4; }
+// The node-split tables of net for P parts (layout of SplitGroup::tab).
+void build_split_tables(const Net &net, uint32_t P, std::vector<uint32_t> &tab);
+
 // One unit of step-kernel work: chains [chain0, chain0+nchains) of one sim.
 struct StepItem {
     const DevSim *sim;
@@ -97,7 +125,9 @@ struct StepItem {
     uint32_t kernel;             // host-side: 0 = lane-per-chain, else waves per block (bit-sliced)
     uint32_t lds;                // host-side: LDS bytes the bit-sliced kernel needs
     uint32_t small;              // host-side: bit-sliced with per-wave metadata in registers
-    uint32_t pad_;
+    uint32_t part;               // node-split form: this block's part
+    const SplitGroup *grp;       // node-split form: the group (null otherwise)
+    void *owner;                 // host-side: the simulation the item advances
 };
 
 enum QueryKind : uint32_t { kQueryWindow = 0, kQueryBatch = 1 };
@@ -127,6 +157,10 @@ int launch_step(const StepItem *d_items, uint32_t nitems, uint32_t max_W, void *
 int launch_step_bs(const StepItem *d_items, uint32_t nitems, uint32_t G, bool small, size_t lds, void *stream,
                    std::string &err);
 size_t bs_lds_bytes(uint32_t n, uint32_t msel_total, uint32_t G);
+// Node-split form: LDS of one block owning n_own nodes and m_own selection masks.
+size_t split_lds_bytes(uint32_t n, uint32_t n_own, uint32_t m_own, uint32_t G);
+int launch_step_split(const StepItem *d_items, uint32_t nitems, uint32_t G, size_t lds, void *stream,
+                      std::string &err);
 // Dynamic-LDS limit of a kernel raised to 160 KB (once per device).
 int allow_full_lds(const void *fn, std::string &err);
 int launch_reduce(const Query *d_queries, uint32_t nq, WindowResult *d_win, int32_t *d_bsum,

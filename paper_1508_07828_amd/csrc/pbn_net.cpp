@@ -301,3 +301,74 @@ void build_bitsliced_schedule(Net &net)
 }
 
 }  // namespace pbn
+
+namespace pbn {
+
+// Node-split tables: 16-node blocks in P contiguous parts of near-equal size;
+// each part's predictor slots (its nodes' functions) sorted by parent count
+// and padded to whole 64-slot groups, with records as in the one-block
+// schedule (the selection-mask indices stay global).
+void build_split_tables(const Net &net, uint32_t P, std::vector<uint32_t> &tab)
+{
+    std::vector<uint32_t> blk(P + 1), grp(P + 1, 0);
+    for (uint32_t r = 0; r <= P; ++r) blk[r] = (uint32_t)(((uint64_t)net.nblk * r) / P);
+    std::vector<std::vector<uint32_t>> order(P);
+    for (uint32_t r = 0; r < P; ++r) {
+        const uint32_t i_lo = 16 * blk[r], i_hi = std::min(net.n, 16 * blk[r + 1]);
+        for (uint32_t i = i_lo; i < i_hi; ++i)
+            for (uint32_t f = net.nd_first[i]; f < net.nd_first[i + 1]; ++f) order[r].push_back(f);
+        std::stable_sort(order[r].begin(), order[r].end(),
+                         [&](uint32_t x, uint32_t y) { return (net.fn_desc[x] & 31u) < (net.fn_desc[y] & 31u); });
+        grp[r + 1] = grp[r] + (uint32_t)((order[r].size() + 63) / 64);
+    }
+    const uint32_t groups = grp[P];
+    const uint32_t rec0 = split_rec_off(P, groups);
+    tab.assign((size_t)rec0 + (size_t)groups * 64 * 8, 0);
+    for (uint32_t r = 0; r <= P; ++r) {
+        tab[r] = blk[r];
+        tab[P + 1 + r] = grp[r];
+    }
+    std::vector<uint32_t> fn_node(net.F), fn_j(net.F);
+    for (uint32_t i = 0; i < net.n; ++i)
+        for (uint32_t f = net.nd_first[i]; f < net.nd_first[i + 1]; ++f) {
+            fn_node[f] = i;
+            fn_j[f] = f - net.nd_first[i];
+        }
+    for (uint32_t r = 0; r < P; ++r) {
+        const std::vector<uint32_t> &ord = order[r];
+        for (uint32_t g = grp[r]; g < grp[r + 1]; ++g) {
+            const size_t s0 = (size_t)(g - grp[r]) * 64, s1 = std::min(ord.size(), s0 + 64);
+            uint32_t K = 1;
+            for (size_t s = s0; s < s1; ++s) K = std::max(K, net.fn_desc[ord[s]] & 31u);
+            tab[split_head(P) + g] = K;
+            for (uint32_t m = 0; m < 64; ++m) {
+                uint32_t *rec = &tab[rec0 + ((size_t)g * 64 + m) * 8];
+                if (s0 + m >= s1) {
+                    rec[0] = kNoNode;
+                    rec[3] = kNoMask;
+                    rec[4] = kNoMask;
+                    continue;
+                }
+                const uint32_t f = ord[s0 + m], k = net.fn_desc[f] & 31u, po = net.fn_desc[f] >> 5;
+                const uint32_t i = fn_node[f], j = fn_j[f], l = net.nd_first[i + 1] - net.nd_first[i];
+                const uint32_t moff = net.nd_meta[i] >> 8;
+                const uint64_t tt = (k <= 5) ? (uint64_t)net.fn_tt[f]
+                                             : ((uint64_t)net.tt_ext[net.fn_tt[f]] | ((uint64_t)net.tt_ext[net.fn_tt[f] + 1] << 32));
+                uint64_t rep = 0;
+                const uint32_t span = 1u << K, per = 1u << k;
+                for (uint32_t e = 0; e < span && e < 64; ++e) rep |= ((tt >> (e % per)) & 1ull) << e;
+                if (K <= 5) rep &= 0xFFFFFFFFull;
+                uint16_t par[kBsMaxK] = {0, 0, 0, 0, 0, 0};
+                for (uint32_t q = 0; q < k; ++q) par[q] = net.par[po + q];
+                rec[0] = i;
+                rec[1] = (uint32_t)rep;
+                rec[2] = (uint32_t)(rep >> 32);
+                rec[3] = j == 0 ? kNoMask : moff + j - 1;
+                rec[4] = j + 1 == l ? kNoMask : moff + j;
+                for (uint32_t q = 0; q < 3; ++q) rec[5 + q] = (uint32_t)par[2 * q] | ((uint32_t)par[2 * q + 1] << 16);
+            }
+        }
+    }
+}
+
+}  // namespace pbn

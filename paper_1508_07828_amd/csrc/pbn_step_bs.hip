@@ -164,7 +164,8 @@ __device__ __forceinline__ void push(bool mine, uint32_t hdr, uint32_t flo, uint
 
 // Resolve queued ties with the refinement words (stream tag + 1), lane = entry.
 __device__ __forceinline__ void resolve(const BsView &v, uint32_t t, uint32_t chain0, const uint32_t *Q,
-                                        uint32_t qlen, uint64_t *Gm, uint64_t *M, uint64_t *Pw_mine, uint32_t lane)
+                                        uint32_t qlen, uint64_t *Gm, uint32_t i_lo, uint64_t *M, uint32_t m_lo,
+                                        uint64_t *Pw_mine, uint32_t lane)
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     const uint32_t pthr24 = v.p_thr & 0xFFFFFFu;
@@ -196,17 +197,137 @@ __device__ __forceinline__ void resolve(const BsView &v, uint32_t t, uint32_t ch
             const uint32_t r24 = pick4(r, i & 3u) & 0xFFFFFFu;
             if (kind == 0) {
                 if (r24 < pthr24) {
-                    lds_or(&Gm[i], 1ull << cl);
+                    lds_or(&Gm[i - i_lo], 1ull << cl);
                     flipped = true;
                 }
             } else {
                 const uint32_t T = v.fn_thr[v.nd_first[i] + j];
-                if (r24 < (T & 0xFFFFFFu)) lds_or(&M[(v.nd_info[2 * i] >> 8) + j], 1ull << cl);
+                if (r24 < (T & 0xFFFFFFu)) lds_or(&M[(v.nd_info[2 * i] >> 8) + j - m_lo], 1ull << cl);
             }
         }
         if (flipped) lds_or(Pw_mine, 1ull << ((hdr >> 1) & 63u));
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// A-phase work of one 16-node block b, lane = chain: the perturbation draws
+// (flips into Gm, chains with a flip into P_acc, ties queued) and, when some
+// node of the block has two or more predictors (lmax >= 2), the selection
+// draws (masks into M, ties queued).  Gm is indexed from node i_lo, M from
+// mask m_lo.
+__device__ __forceinline__ void draw_block(const BsView &v, uint32_t t, uint32_t c, uint32_t lane, uint32_t b,
+                                           uint32_t lmax, uint32_t thr8, uint32_t thr8x4, uint64_t *Gm,
+                                           uint32_t i_lo, uint64_t *M, uint32_t m_lo, uint32_t *Q, uint32_t &qlen,
+                                           uint64_t &P_acc)
+{
+    const uint32_t n = v.n, i0 = 16 * b, ib = min(16u, n - i0);
+    uint32_t wp[4];
+    philox4(t, c, b, kTagPert, v.key, wp);
+    // tie flags: bit 8 bb + q <-> node 4 q + bb (byte bb of word q)
+    uint32_t tie = (bytes_eq(wp[0], thr8x4) >> 7) | (bytes_eq(wp[1], thr8x4) >> 6) |
+                   (bytes_eq(wp[2], thr8x4) >> 5) | (bytes_eq(wp[3], thr8x4) >> 4);
+    if (ib < 16) {
+        uint32_t valid = 0;
+        for (uint32_t bb = 0; bb < 4; ++bb) {
+            const uint32_t cnt = ib > bb ? (ib - bb + 3) >> 2 : 0u;   // words q with 4 q + bb < ib
+            valid |= ((1u << cnt) - 1u) << (8 * bb);
+        }
+        tie &= valid;
+    }
+    if (thr8 > 0) {
+        // bytes below the primary threshold flip at once
+#pragma unroll
+        for (uint32_t k = 0; k < 16; ++k) {
+            if (k < ib) {
+                const uint32_t byte = (wp[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+                const uint64_t d1 = __ballot(byte < thr8);
+                if (d1) {
+                    if (lane == 0) lds_or(&Gm[i0 + k - i_lo], d1);
+                    P_acc |= d1;
+                }
+            }
+        }
+    }
+    push(tie != 0, (lane << 1) | (b << 7), tie, 0u, Q, qlen);
+    if (lmax >= 2) {
+        uint32_t ws[4];
+        philox4(t, c, b, kTagSel, v.key, ws);
+        // one ballot per (node k, threshold j < 3) against the top byte of
+        // T_j (uniform, from scalar loads); lane k of a[j] gathers node k's
+        // mask, and each (node, threshold) with equal bytes is queued with
+        // its chain flags
+        const PBN_CAS uint32_t *info = v.nd_info + 32 * (size_t)b;
+        const PBN_CAS u32x8 *quads = (const PBN_CAS u32x8 *)info;
+        uint32_t al[3] = {0u, 0u, 0u}, ah[3] = {0u, 0u, 0u};
+        uint32_t eh = 0, el = 0, eu = 0, ne = 0;
+        uint32_t mv = 0;                  // lane k: node k's record (l | mask offset << 8)
+        // node records four at a time (one scalar load each), the next
+        // quad's load issued before the current quad's compares
+        u32x8 rq = quads[0], rn = rq;
+#pragma unroll
+        for (uint32_t k = 0; k < 16; ++k) {
+            if ((k & 3u) == 0) {
+                rq = rn;
+                if (k < 12) rn = quads[(k >> 2) + 1];
+            }
+            const uint32_t tbs = rq[2 * (k & 3u) + 1];
+            const uint32_t l = tbs >> 24;     // 0 for nodes past n
+            if (l < 2) continue;
+            mv = amdgcn_writelane(rq[2 * (k & 3u)], k, mv);
+            const uint32_t byte = (ws[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+#pragma unroll
+            for (uint32_t j = 0; j < 3; ++j) {
+                if (j + 2 > l) break;
+                const uint32_t tb = (tbs >> (8 * j)) & 0xFFu;
+                const uint64_t lt = __ballot(byte < tb);
+                const uint64_t eq = __ballot(byte == tb);
+                al[j] = amdgcn_writelane((uint32_t)lt, k, al[j]);
+                ah[j] = amdgcn_writelane((uint32_t)(lt >> 32), k, ah[j]);
+                if (eq) {
+                    eh = amdgcn_writelane(1u | (k << 1) | (j << 5) | (b << 7), ne, eh);
+                    el = amdgcn_writelane((uint32_t)eq, ne, el);
+                    eu = amdgcn_writelane((uint32_t)(eq >> 32), ne, eu);
+                    ++ne;
+                }
+            }
+        }
+        {
+            const uint32_t l = mv & 0xFFu, moff = mv >> 8;
+#pragma unroll
+            for (uint32_t j = 0; j < 3; ++j)
+                if (j + 2 <= l) M[moff + j - m_lo] = ((uint64_t)ah[j] << 32) | al[j];
+        }
+        if (ne) {
+            if (lane < ne) {
+                Q[qlen + lane] = eh;
+                Q[kQCap + qlen + lane] = el;
+                Q[2 * kQCap + qlen + lane] = eu;
+            }
+            qlen += ne;
+        }
+        if (lmax >= 5) {
+            // thresholds 4.. of nodes with more than four predictors,
+            // straight from fn_thr with their ties refined in place
+            for (uint32_t k = 0; k < ib; ++k) {
+                const uint32_t meta = info[2 * k];
+                const uint32_t l = meta & 0xFFu;
+                if (l < 5) continue;
+                const uint32_t i = i0 + k;
+                const uint32_t byte = (pick4(ws, k >> 2) >> (8 * (k & 3))) & 0xFFu;
+                for (uint32_t j = 3; j + 1 < l; ++j) {
+                    const uint32_t T = v.fn_thr[v.nd_first[i] + j];
+                    const uint32_t tb = T >> 24;
+                    bool below = byte < tb;
+                    const bool eq = byte == tb;
+                    if (__ballot(eq)) {
+                        if (eq) below = refine24(v.key, t, c, i, kTagSel) < (T & 0xFFFFFFu);
+                    }
+                    const uint64_t lt = __ballot(below);
+                    if (lane == 0) M[(meta >> 8) + j - m_lo] = lt;
+                }
+            }
+        }
+    }
 }
 
 extern __shared__ uint64_t lds_bs[];
@@ -276,11 +397,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     // (the small form keeps them register-resident; the flags stay run-time so
     // the compiler does not trade registers for the single-iteration loops)
     const bool res_a = SMALL && nblk <= G, res_c = SMALL && F_pad <= 64 * G;
-    uint32_t ra_lmax = 0, ra_meta = 0;
-    if (res_a && wave < nblk) {
-        ra_lmax = v.blk_sel[wave];
-        if (ra_lmax >= 2 && lane < min(16u, n - 16 * wave)) ra_meta = v.nd_info[2 * (16 * wave + lane)];
-    }
+    uint32_t ra_lmax = 0;
+    if (res_a && wave < nblk) ra_lmax = v.blk_sel[wave];
     uint32_t rc_K = 1;
     u32x4 rc0 = {0u, 0u, 0u, 0u}, rc1 = {0u, 0u, 0u, 0u};
     if (res_c && 64 * wave < F_pad) {
@@ -321,120 +439,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             const bool last = b >= nblk;
             // a block queues at most 128 entries: resolve before the queue could overflow
             if (qlen != 0 && (last || qlen + 128 > kQCap)) {
-                resolve(v, t, chain0, Q, qlen, Gm, M, &Pt[wave], lane);
+                resolve(v, t, chain0, Q, qlen, Gm, 0u, M, 0u, &Pt[wave], lane);
                 qlen = 0;
             }
             if (last) break;
-            const uint32_t i0 = 16 * b, ib = min(16u, n - i0);
-            const uint32_t lmax = res_a ? ra_lmax : v.blk_sel[b];
-            // node metadata of the block, one node per lane, fetched ahead of the draws
-            uint32_t my_meta = ra_meta;
-            if (!res_a && lmax >= 2 && lane < ib) my_meta = v.nd_info[2 * (i0 + lane)];
-            uint32_t wp[4];
-            philox4(t, c, b, kTagPert, v.key, wp);
-            // tie flags: bit 8 bb + q <-> node 4 q + bb (byte bb of word q)
-            uint32_t tie = (bytes_eq(wp[0], thr8x4) >> 7) | (bytes_eq(wp[1], thr8x4) >> 6) |
-                           (bytes_eq(wp[2], thr8x4) >> 5) | (bytes_eq(wp[3], thr8x4) >> 4);
-            if (ib < 16) {
-                uint32_t valid = 0;
-                for (uint32_t bb = 0; bb < 4; ++bb) {
-                    const uint32_t cnt = ib > bb ? (ib - bb + 3) >> 2 : 0u;   // words q with 4 q + bb < ib
-                    valid |= ((1u << cnt) - 1u) << (8 * bb);
-                }
-                tie &= valid;
-            }
-            if (thr8 > 0) {
-                // bytes below the primary threshold flip at once
-#pragma unroll
-                for (uint32_t k = 0; k < 16; ++k) {
-                    if (k < ib) {
-                        const uint32_t byte = (wp[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-                        const uint64_t d1 = __ballot(byte < thr8);
-                        if (d1) {
-                            if (lane == 0) lds_or(&Gm[i0 + k], d1);
-                            P_acc |= d1;
-                        }
-                    }
-                }
-            }
-            push(tie != 0, (lane << 1) | (b << 7), tie, 0u, Q, qlen);
-            if (lmax >= 2) {
-                uint32_t ws[4];
-                philox4(t, c, b, kTagSel, v.key, ws);
-                // one ballot per (node k, threshold j < 3) against the top byte of
-                // T_j (uniform, from scalar loads); lane k of a[j] gathers node k's
-                // mask, and each (node, threshold) with equal bytes is queued with
-                // its chain flags
-                const PBN_CAS uint32_t *info = v.nd_info + 32 * (size_t)b;
-                const PBN_CAS u32x8 *quads = (const PBN_CAS u32x8 *)info;
-                uint32_t al[3] = {0u, 0u, 0u}, ah[3] = {0u, 0u, 0u};
-                uint32_t eh = 0, el = 0, eu = 0, ne = 0;
-                // node records four at a time (one scalar load each), the next
-                // quad's load issued before the current quad's compares
-                u32x8 rq = quads[0], rn = rq;
-#pragma unroll
-                for (uint32_t k = 0; k < 16; ++k) {
-                    if ((k & 3u) == 0) {
-                        rq = rn;
-                        if (k < 12) rn = quads[(k >> 2) + 1];
-                    }
-                    const uint32_t tbs = rq[2 * (k & 3u) + 1];
-                    const uint32_t l = tbs >> 24;     // 0 for nodes past n
-                    if (l < 2) continue;
-                    const uint32_t byte = (ws[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-#pragma unroll
-                    for (uint32_t j = 0; j < 3; ++j) {
-                        if (j + 2 > l) break;
-                        const uint32_t tb = (tbs >> (8 * j)) & 0xFFu;
-                        const uint64_t lt = __ballot(byte < tb);
-                        const uint64_t eq = __ballot(byte == tb);
-                        al[j] = amdgcn_writelane((uint32_t)lt, k, al[j]);
-                        ah[j] = amdgcn_writelane((uint32_t)(lt >> 32), k, ah[j]);
-                        if (eq) {
-                            eh = amdgcn_writelane(1u | (k << 1) | (j << 5) | (b << 7), ne, eh);
-                            el = amdgcn_writelane((uint32_t)eq, ne, el);
-                            eu = amdgcn_writelane((uint32_t)(eq >> 32), ne, eu);
-                            ++ne;
-                        }
-                    }
-                }
-                if (lane < ib) {
-                    const uint32_t l = my_meta & 0xFFu, moff = my_meta >> 8;
-#pragma unroll
-                    for (uint32_t j = 0; j < 3; ++j)
-                        if (j + 2 <= l) M[moff + j] = ((uint64_t)ah[j] << 32) | al[j];
-                }
-                if (ne) {
-                    if (lane < ne) {
-                        Q[qlen + lane] = eh;
-                        Q[kQCap + qlen + lane] = el;
-                        Q[2 * kQCap + qlen + lane] = eu;
-                    }
-                    qlen += ne;
-                }
-                if (lmax >= 5) {
-                    // thresholds 4.. of nodes with more than four predictors,
-                    // straight from fn_thr with their ties refined in place
-                    for (uint32_t k = 0; k < ib; ++k) {
-                        const uint32_t meta = info[2 * k];
-                        const uint32_t l = meta & 0xFFu;
-                        if (l < 5) continue;
-                        const uint32_t i = i0 + k;
-                        const uint32_t byte = (pick4(ws, k >> 2) >> (8 * (k & 3))) & 0xFFu;
-                        for (uint32_t j = 3; j + 1 < l; ++j) {
-                            const uint32_t T = v.fn_thr[v.nd_first[i] + j];
-                            const uint32_t tb = T >> 24;
-                            bool below = byte < tb;
-                            const bool eq = byte == tb;
-                            if (__ballot(eq)) {
-                                if (eq) below = refine24(v.key, t, c, i, kTagSel) < (T & 0xFFFFFFu);
-                            }
-                            const uint64_t lt = __ballot(below);
-                            if (lane == 0) M[(meta >> 8) + j] = lt;
-                        }
-                    }
-                }
-            }
+            draw_block(v, t, c, lane, b, res_a ? ra_lmax : v.blk_sel[b], thr8, thr8x4, Gm, 0u, M, 0u, Q, qlen, P_acc);
         }
         if (P_acc && lane == 0) lds_or(&Pt[wave], P_acc);
         __syncthreads();
@@ -513,6 +522,225 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     }
 }
 
+// Node-split form.  P blocks (on P CUs) share one 64-chain group: block r of
+// the group owns the 16-node blocks [tab[r], tab[r + 1]) and the predictor
+// slot groups [tab[P + 1 + r], tab[P + 2 + r]) of those nodes.  Each keeps the
+// whole state S in LDS (every slot may read any parent) but only its own
+// nodes' next-state words, function values and selection masks.  Per
+// transition:
+//   A  own blocks, as in the one-block form: flips into Gm, masks into M
+//   -- barrier
+//   C  own slots: the K-input multiplexers, restricted to the chains that
+//      selected the predictor, OR-ed into Fm[node] (the function values)
+//   -- barrier
+//   X  publish the own nodes' Gm and Fm words and the block's perturbed-chain
+//      word to the group's exchange area (agent-coherent stores), wait until
+//      every block of the group has arrived at this transition on the group's
+//      counter, then read all of them: with P the OR of the perturbed-chain
+//      words, node i of the next state is P & (S_i ^ flips_i) | ~P & f_i.
+// The wait is bounded: a block that waits about a second gives up, sets the
+// group's error word and ends; the host then reports the failure.  Block 0 of
+// the group records the indicators and writes the state back.
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) k_step_split(const StepItem *__restrict__ items)
+{
+    const StepItem it = load_item(items, blockIdx.x);
+    if (it.nchains == 0) return;         // padding of an XCD-aware launch
+    const BsView v = load_bs_view(it.sim);
+    const PBN_CAS SplitGroup *sg = (const PBN_CAS SplitGroup *)it.grp;
+    const uint32_t P = sg->nparts, r = it.part, groups = sg->groups;
+    const cu32 tab = (cu32)sg->tab;
+    PBN_GAS uint64_t *xch = (PBN_GAS uint64_t *)sg->xch;
+    PBN_GAS uint32_t *ctr = (PBN_GAS uint32_t *)sg->ctr;
+    PBN_GAS uint32_t *errw = (PBN_GAS uint32_t *)sg->err;
+    const uint32_t n = v.n, W = v.W, omega = v.omega;
+    const uint32_t G = blockDim.x >> 6;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t chain0 = it.chain0;
+    const uint32_t c = chain0 + lane;
+    const bool active = lane < it.nchains;
+    const uint32_t blo = tab[r], bhi = tab[r + 1], glo = tab[P + 1 + r], ghi = tab[P + 2 + r];
+    const uint32_t i_lo = 16 * blo, i_hi = min(16 * bhi, n), n_own = i_hi - i_lo;
+    const uint32_t m_lo = v.nd_info[2 * i_lo] >> 8;
+    const uint32_t m_hi = i_hi < n ? v.nd_info[2 * i_hi] >> 8 : v.msel_total;
+    const cu32 fgK = tab + split_head(P);
+    const cu32 rec = tab + split_rec_off(P, groups);
+    uint64_t *S = lds_bs;
+    uint64_t *Gm = S + n;
+    uint64_t *Fm = Gm + n_own;
+    uint64_t *M = Fm + n_own;
+    uint64_t *Pw = M + (m_hi - m_lo);
+    uint32_t *Q = (uint32_t *)(Pw + 2 * G) + wave * 3 * kQCap;
+    uint32_t *acc = (uint32_t *)(Pw + 2 * G) + G * 3 * kQCap + lane;
+    uint32_t *abort_flag = (uint32_t *)(Pw + 2 * G) + G * 3 * kQCap + 64 * kMaxProps;
+    const uint64_t words_cap = v.d->words_cap;
+    const bool recorder = r == 0;
+
+    {
+        gu32 state = (gu32)v.d->state;
+        for (uint32_t w = wave; w < W; w += G) {
+            const uint32_t word = active ? state[(size_t)w * omega + c] : 0u;
+            const uint32_t nb = min(32u, n - 32 * w);
+            for (uint32_t b = 0; b < nb; ++b) {
+                const uint64_t m = __ballot((word >> b) & 1u);
+                if (lane == 0) S[32 * w + b] = m;
+            }
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < n_own; i += 64 * G) Gm[i] = Fm[i] = 0ull;
+    for (uint32_t i = threadIdx.x; i < m_hi - m_lo; i += 64 * G) M[i] = 0ull;
+    if (threadIdx.x < 2 * G) Pw[threadIdx.x] = 0ull;
+    if (threadIdx.x == 0) *abort_flag = 0u;
+    uint64_t pos = it.pos0;
+    const uint32_t nprops = v.nprops;
+    if (wave == 0 && recorder) {
+        for (uint32_t q = 0; q < nprops; ++q) {
+            uint32_t a = 0;
+            if (active && it.nrec > 0 && (pos & 31)) {
+                gu32 bits = (gu32)v.d->bits;
+                const uint32_t old = bits[((size_t)q * words_cap + (pos >> 5)) * omega + c];
+                a = old & ((1u << (pos & 31)) - 1u);
+            }
+            acc[64 * q] = a;
+        }
+    }
+    __syncthreads();
+
+    const uint32_t p_thr = v.p_thr, thr8 = p_thr >> 24, thr8x4 = thr8 * 0x01010101u;
+    const uint32_t total = it.nburn + it.nrec * it.thin;
+    uint32_t since = 0;
+    bool pending = false;
+    auto record = [&]() {
+        const uint32_t bpos = (uint32_t)(pos & 31);
+        for (uint32_t q = 0; q < nprops; ++q) {
+            uint64_t xm = ~0ull;
+            for (uint32_t m = v.d->pn_off[q]; m < v.d->pn_off[q + 1]; ++m) {
+                const uint64_t sv = S[v.d->pn_node[m]];
+                xm &= v.d->pn_val[m] ? sv : ~sv;
+            }
+            const uint32_t a = acc[64 * q] | ((uint32_t)((xm >> lane) & 1ull) << bpos);
+            if (bpos == 31) {
+                if (active) ((gu32)v.d->bits)[((size_t)q * words_cap + (pos >> 5)) * omega + c] = a;
+                acc[64 * q] = 0;
+            } else {
+                acc[64 * q] = a;
+            }
+        }
+    };
+    for (uint32_t s = 0; s < total; ++s) {
+        const uint32_t t = it.t0 + s;
+        uint64_t *Pt = Pw + (s & 1) * G;
+        // ---- A: own blocks, lane = chain
+        uint64_t P_acc = 0;
+        uint32_t qlen = 0;
+        if (lane == 0) Pt[wave] = 0ull;
+        for (uint32_t b = blo + wave;; b += G) {
+            const bool last = b >= bhi;
+            if (qlen != 0 && (last || qlen + 128 > kQCap)) {
+                resolve(v, t, chain0, Q, qlen, Gm, i_lo, M, m_lo, &Pt[wave], lane);
+                qlen = 0;
+            }
+            if (last) break;
+            draw_block(v, t, c, lane, b, v.blk_sel[b], thr8, thr8x4, Gm, i_lo, M, m_lo, Q, qlen, P_acc);
+        }
+        if (P_acc && lane == 0) lds_or(&Pt[wave], P_acc);
+        __syncthreads();
+
+        // ---- C: own slots, lane = slot
+        if (pending && wave == 0 && recorder) {
+            record();
+            ++pos;
+        }
+        pending = false;
+        for (uint32_t g = glo + wave; g < ghi; g += G) {
+            const uint32_t K = fgK[g];
+            const PBN_CAS u32x4 *rp = (const PBN_CAS u32x4 *)(rec + 8 * ((size_t)64 * g + lane));
+            const u32x4 r0 = rp[0], r1 = rp[1];
+            const uint32_t node = r0.x, tlo = r0.y, thi = r0.z, mlo = r0.w, mhi = r1.x;
+            const uint32_t p01 = r1.y, p23 = r1.z, p45 = r1.w;
+            uint64_t x[6];
+            x[0] = S[p01 & 0xFFFFu];
+            x[1] = K > 1 ? S[p01 >> 16] : 0ull;
+            x[2] = K > 2 ? S[p23 & 0xFFFFu] : 0ull;
+            x[3] = K > 3 ? S[p23 >> 16] : 0ull;
+            x[4] = K > 4 ? S[p45 & 0xFFFFu] : 0ull;
+            x[5] = K > 5 ? S[p45 >> 16] : 0ull;
+            const uint64_t f = eval_slot(K, tlo, thi, x);
+            if (node != kNoNode) {
+                const uint64_t below = mlo == kNoMask ? 0ull : M[mlo - m_lo];
+                const uint64_t upto = mhi == kNoMask ? ~0ull : M[mhi - m_lo];
+                const uint64_t val = f & upto & ~below;
+                if (val) lds_or(&Fm[node - i_lo], val);
+            }
+        }
+        __syncthreads();
+
+        // ---- X: exchange through the group's area, parity s & 1
+        PBN_GAS uint64_t *X = xch + (size_t)(s & 1) * 2 * n;
+        PBN_GAS uint64_t *XP = xch + (size_t)4 * n + (size_t)(s & 1) * P;
+        for (uint32_t k = threadIdx.x; k < n_own; k += 64 * G) {
+            __hip_atomic_store(&X[2 * (size_t)(i_lo + k)], Gm[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&X[2 * (size_t)(i_lo + k) + 1], Fm[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (threadIdx.x == 0) {
+            uint64_t pr = 0;
+            for (uint32_t w = 0; w < G; ++w) pr |= Pt[w];
+            __hip_atomic_store(&XP[r], pr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // every wave's stores complete before the block arrives
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t target = P * (s + 1);
+            uint32_t spins = 0;
+            while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if (++spins > kSplitSpins) {
+                    *abort_flag = 1u;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __syncthreads();
+        if (*abort_flag) {
+            if (threadIdx.x == 0) __hip_atomic_store(errw, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        uint64_t Pall = 0;
+        for (uint32_t q = 0; q < P; ++q) Pall |= __hip_atomic_load(&XP[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (uint32_t i = threadIdx.x; i < n; i += 64 * G) {
+            const uint64_t g = __hip_atomic_load(&X[2 * (size_t)i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t f = __hip_atomic_load(&X[2 * (size_t)i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            S[i] = (Pall & (S[i] ^ g)) | (~Pall & f);
+        }
+        for (uint32_t k = threadIdx.x; k < n_own; k += 64 * G) Gm[k] = Fm[k] = 0ull;
+        if (s >= it.nburn && ++since == it.thin) {
+            since = 0;
+            pending = true;
+        }
+        __syncthreads();
+    }
+    if (pending && wave == 0 && recorder) {
+        record();
+        ++pos;
+    }
+    if (!recorder) return;
+    if (wave == 0 && active && it.nrec > 0 && (pos & 31)) {
+        gu32 bits = (gu32)v.d->bits;
+        for (uint32_t q = 0; q < nprops; ++q) bits[((size_t)q * words_cap + (pos >> 5)) * omega + c] = acc[64 * q];
+    }
+    gu32 state = (gu32)v.d->state;
+    for (uint32_t w = wave; w < W; w += G) {
+        uint32_t word = 0;
+        const uint32_t nb = min(32u, n - 32 * w);
+        for (uint32_t b = 0; b < nb; ++b) word |= (uint32_t)((S[32 * w + b] >> lane) & 1ull) << b;
+        if (active) state[(size_t)w * omega + c] = word;
+    }
+}
+
 static int check_bs(hipError_t e, const char *what, std::string &err)
 {
     if (e == hipSuccess) return PBN_OK;
@@ -523,6 +751,32 @@ static int check_bs(hipError_t e, const char *what, std::string &err)
 size_t bs_lds_bytes(uint32_t n, uint32_t msel_total, uint32_t G)
 {
     return (size_t)8 * (2 * (size_t)n + msel_total + 2 * G) + (size_t)4 * 3 * kQCap * G + (size_t)4 * 64 * kMaxProps;
+}
+
+size_t split_lds_bytes(uint32_t n, uint32_t n_own, uint32_t m_own, uint32_t G)
+{
+    return (size_t)8 * ((size_t)n + 2 * (size_t)n_own + m_own + 2 * G) + (size_t)4 * 3 * kQCap * G +
+           (size_t)4 * 64 * kMaxProps + 16;
+}
+
+int launch_step_split(const StepItem *d_items, uint32_t nitems, uint32_t G, size_t lds, void *stream,
+                      std::string &err)
+{
+    if (nitems == 0) return PBN_OK;
+    if (G != 1 && G != 2 && G != 4 && G != 8 && G != 16) {
+        err = "node-split kernel: waves per block must be 1, 2, 4, 8 or 16";
+        return PBN_EINVAL;
+    }
+    if (lds > 160 * 1024) {
+        err = "node-split state exceeds LDS";
+        return PBN_ELIMIT;
+    }
+    if (lds > 64 * 1024) {
+        int rc = allow_full_lds((const void *)k_step_split, err);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_step_split, dim3(nitems), dim3(64 * G), lds, (hipStream_t)stream, d_items);
+    return check_bs(hipGetLastError(), "k_step_split launch", err);
 }
 
 int launch_step_bs(const StepItem *d_items, uint32_t nitems, uint32_t G, bool small, size_t lds, void *stream,

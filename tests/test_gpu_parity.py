@@ -114,6 +114,64 @@ def test_burn_in_and_thinning(kernel):
     assert sim.position() == (50, 163)
 
 
+# node-split form: a 64-chain group spread over P cooperating blocks
+SPLIT_CASES = ["medium", "ragged_k6_p05", "ragged_l6_k5", "high_p", "n300_l4"]
+
+
+@pytest.fixture(params=[2, 3, 5], ids=["split2", "split3", "split5"])
+def split(request):
+    pkg.set_split(request.param)
+    yield request.param
+    pkg.set_split(0)
+
+
+@pytest.mark.parametrize("case", SPLIT_CASES)
+def test_split_trajectories_bit_exact(case, split):
+    net, omega, pats = CASES[case]()
+    text = ps.to_text(net)
+    say("split trajectories {} n={} omega={} parts={}".format(case, net.n, omega, split))
+    sim = pkg.Simulation(pkg.Network(text), omega, 7828, max_props=len(pats), max_len=4096)
+    sim.reset(pats)
+    ch = oracle.Chains(oracle.Net(text), omega, 7828, pats)
+    for steps in (37, 100, 63, 1):
+        sim.run(steps)
+        ch.extend(steps)
+        assert np.array_equal(sim.read_state(), ch.states), steps
+    L = ch.length
+    for q in range(len(pats)):
+        assert np.array_equal(sim.read_bits(q, 0, L), ch.bits[q]), q
+    assert sim.position() == (L, L)
+
+
+def test_split_burn_in_and_thinning(split):
+    net, omega, pats = CASES["n300_l4"]()
+    text = ps.to_text(net)
+    say("split burn-in/thin parts={}".format(split))
+    sim = pkg.Simulation(pkg.Network(text), omega, 99, max_props=1, max_len=1024)
+    sim.reset(pats)
+    sim.run(40, burn_in=11, thin=3)
+    ch = oracle.Chains(oracle.Net(text), omega, 99, pats)
+    ch.extend(11 + 120)
+    assert np.array_equal(sim.read_state(), ch.states)
+    idx = 11 + 3 * np.arange(40) + 2
+    assert np.array_equal(sim.read_bits(0, 0, 40), ch.bits[0][:, idx])
+    assert sim.position() == (40, 131)
+
+
+def test_split_estimate_equals_oracle():
+    job = ps.medium()
+    text = ps.to_text(job.net)
+    say("split estimate: medium two-state, 4 parts")
+    pkg.set_split(4)
+    try:
+        sim = pkg.Simulation(pkg.Network(text), job.chains, job.seed, max_props=1, max_len=CAP)
+        got = sim.estimate(job.patterns, job.r, job.confidence, psrf_max=job.psrf_max)
+    finally:
+        pkg.set_split(0)
+    want = drivers.solve(text, job.chains, job.seed, job.patterns, job.r, job.confidence, job.psrf_max, cap=CAP)
+    assert_same_result(got[0], want[0], "medium split")
+
+
 @pytest.mark.parametrize("mode", [("lane", 0), ("auto", 0)], ids=["lane", "auto"])
 def test_large_sampled_chains(mode):
     pkg.set_kernel(*mode)
