@@ -814,7 +814,7 @@ int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, 
         }
         if (lds > 160 * 1024) continue;
         plan.push_back(Plan{i, P, G, (uint32_t)lds, tab});
-        xwords += 4 * (size_t)sim->net.n + 2 * (size_t)P;
+        xwords += 2 * (size_t)sim->net.n + 2 * (size_t)P;
         extra += P - 1;
     }
     if (plan.empty()) return PBN_OK;
@@ -840,7 +840,7 @@ int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, 
         g.err = ws.d_err;
         g.nparts = p.P;
         g.groups = p.tab.groups;
-        xoff += 4 * (size_t)sim->net.n + 2 * (size_t)p.P;
+        xoff += 2 * (size_t)sim->net.n + 2 * (size_t)p.P;
         for (uint32_t r = 0; r < p.P; ++r) {
             StepItem s = items[i];
             s.part = r;

@@ -94,8 +94,8 @@ struct DevSim {
 //            [P + 1, 2P + 1]  first 64-slot group of part r (tab[2P + 1] = groups)
 //            at split_head(P): K of every slot group, then (16-byte aligned) the
 //            slot records, 8 words each, as in DevSim::fs_rec
-//   xch: u64 [2][2n] (perturbation flips, function values of node i at 2i,
-//        2i + 1) then [2][P] perturbed-chain words, by transition parity
+//   xch: u64 [2][n] next-state words as published by their owners, then
+//        [2][P] perturbed-chain words, by transition parity
 //   ctr: arrivals, one per part and transition, zero at launch
 //   err: set to 1 when a barrier wait times out (the launch then ends early)
 struct SplitGroup {

@@ -533,11 +533,12 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
 //   C  own slots: the K-input multiplexers, restricted to the chains that
 //      selected the predictor, OR-ed into Fm[node] (the function values)
 //   -- barrier
-//   X  publish the own nodes' Gm and Fm words and the block's perturbed-chain
-//      word to the group's exchange area (agent-coherent stores), wait until
-//      every block of the group has arrived at this transition on the group's
-//      counter, then read all of them: with P the OR of the perturbed-chain
-//      words, node i of the next state is P & (S_i ^ flips_i) | ~P & f_i.
+//   X  with Pr the chains this block perturbed, publish for every own node
+//      h_i = Pr & (S_i ^ flips_i) | ~Pr & f_i and the word Pr to the group's
+//      exchange area (agent-coherent stores), wait until every block of the
+//      group has arrived at this transition on the group's counter, then read
+//      them all: node i of part q becomes h_i, except in the chains perturbed
+//      by another part only, which keep S_i.
 // The wait is bounded: a block that waits about a second gives up, sets the
 // group's error word and ends; the host then reports the failure.  Block 0 of
 // the group records the indicators and writes the state back.
@@ -675,18 +676,21 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
         }
         __syncthreads();
 
-        // ---- X: exchange through the group's area, parity s & 1
-        PBN_GAS uint64_t *X = xch + (size_t)(s & 1) * 2 * n;
-        PBN_GAS uint64_t *XP = xch + (size_t)4 * n + (size_t)(s & 1) * P;
+        // ---- X: exchange through the group's area, parity s & 1.  Own node i
+        // is published as h_i = Pr & (S_i ^ flips_i) | ~Pr & f_i with Pr this
+        // block's perturbed chains: exact for the chains this block perturbed
+        // and for the unperturbed ones; the chains perturbed only in other
+        // parts keep S_i, which every reader restores from its own S.
+        PBN_GAS uint64_t *X = xch + (size_t)(s & 1) * n;
+        PBN_GAS uint64_t *XP = xch + (size_t)2 * n + (size_t)(s & 1) * P;
+        uint64_t Pr = 0;
+        for (uint32_t w = 0; w < G; ++w) Pr |= Pt[w];
         for (uint32_t k = threadIdx.x; k < n_own; k += 64 * G) {
-            __hip_atomic_store(&X[2 * (size_t)(i_lo + k)], Gm[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&X[2 * (size_t)(i_lo + k) + 1], Fm[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t h = (Pr & (S[i_lo + k] ^ Gm[k])) | (~Pr & Fm[k]);
+            Fm[k] = h;
+            __hip_atomic_store(&X[i_lo + k], h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        if (threadIdx.x == 0) {
-            uint64_t pr = 0;
-            for (uint32_t w = 0; w < G; ++w) pr |= Pt[w];
-            __hip_atomic_store(&XP[r], pr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        if (threadIdx.x == 0) __hip_atomic_store(&XP[r], Pr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // every wave's stores complete before the block arrives
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __builtin_amdgcn_s_waitcnt(0);
@@ -711,10 +715,14 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
         }
         uint64_t Pall = 0;
         for (uint32_t q = 0; q < P; ++q) Pall |= __hip_atomic_load(&XP[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        for (uint32_t i = threadIdx.x; i < n; i += 64 * G) {
-            const uint64_t g = __hip_atomic_load(&X[2 * (size_t)i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint64_t f = __hip_atomic_load(&X[2 * (size_t)i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            S[i] = (Pall & (S[i] ^ g)) | (~Pall & f);
+        // node i of part q: h_i, except S_i in the chains perturbed outside q
+        for (uint32_t q = 0; q < P; ++q) {
+            const uint32_t a = 16 * tab[q], e = min(16 * tab[q + 1], n);
+            const uint64_t keep = Pall & ~__hip_atomic_load(&XP[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (uint32_t i = a + threadIdx.x; i < e; i += 64 * G) {
+                const uint64_t h = q == r ? Fm[i - i_lo] : __hip_atomic_load(&X[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                S[i] = (h & ~keep) | (S[i] & keep);
+            }
         }
         for (uint32_t k = threadIdx.x; k < n_own; k += 64 * G) Gm[k] = Fm[k] = 0ull;
         if (s >= it.nburn && ++since == it.thin) {
