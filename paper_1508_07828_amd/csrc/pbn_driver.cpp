@@ -29,6 +29,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <queue>
 #include <thread>
 
 #include "pbn_driver.h"
@@ -774,17 +775,49 @@ int split_table(pbn_sim *sim, uint32_t P, pbn_sim::SplitTab &out, std::string &e
     return PBN_OK;
 }
 
-// Spread latency-bound 64-chain groups over several CUs: automatic when the
-// launch has at most 128 blocks (each group then takes up to 256 / blocks
-// parts, at least 8 node blocks per part, at most 16 parts), or a forced part
-// count.  Every node-split group's parts are marked small = 2.
+// Spread latency-bound 64-chain groups over several CUs.  Automatic: while
+// the launch has fewer blocks than the chip has CUs, the spare CUs go, one
+// part at a time, to the group with the largest remaining work per part
+// (node count x transitions / parts), each group taking at most 16 parts of
+// at least 8 node blocks; every block of the launch then has a CU of its own,
+// so a group's parts are resident together.  Forced: P parts for every
+// bit-sliced group (at most one per node block).  The parts of a node-split
+// group are marked small = 2.
 int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, size_t &ngroups)
 {
     ngroups = 0;
-    uint32_t P_auto = 0;
-    if (g_split_mode == 0) {
-        if (items.size() > 128) return PBN_OK;
-        P_auto = (uint32_t)std::min<size_t>(16, 256 / items.size());
+    constexpr size_t kCus = 256;
+    std::vector<uint32_t> parts(items.size(), 1);
+    {
+        std::vector<size_t> cand;
+        for (size_t i = 0; i < items.size(); ++i) {
+            const StepItem &it = items[i];
+            if (it.kernel == 0 || !it.owner || it.nchains == 0) continue;
+            const uint32_t nblk = ((const pbn_sim *)it.owner)->net.nblk;
+            if (g_split_mode >= 2) parts[i] = std::min(std::min(g_split_mode, kSplitMaxParts), nblk);
+            else cand.push_back(i);
+        }
+        if (g_split_mode == 0 && items.size() < kCus && !cand.empty()) {
+            auto work = [&](size_t i) {
+                const StepItem &it = items[i];
+                return (double)it.nodes * (double)(it.nburn + (uint64_t)it.nrec * it.thin) / (double)parts[i];
+            };
+            auto cap = [&](size_t i) {
+                return std::min<uint32_t>(kSplitMaxParts, ((const pbn_sim *)items[i].owner)->net.nblk / 8);
+            };
+            auto lower = [&](size_t a, size_t b) { return work(a) < work(b); };
+            std::priority_queue<size_t, std::vector<size_t>, decltype(lower)> pq(lower);
+            for (size_t i : cand)
+                if (cap(i) >= 2) pq.push(i);
+            size_t spare = kCus - items.size();
+            while (spare > 0 && !pq.empty()) {
+                const size_t i = pq.top();
+                pq.pop();
+                ++parts[i];
+                --spare;
+                if (parts[i] < cap(i)) pq.push(i);
+            }
+        }
     }
     struct Plan {
         size_t idx;
@@ -794,12 +827,10 @@ int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, 
     std::vector<Plan> plan;
     size_t xwords = 0, extra = 0;
     for (size_t i = 0; i < items.size(); ++i) {
-        const StepItem &it = items[i];
-        if (it.kernel == 0 || !it.owner || it.nchains == 0) continue;
-        pbn_sim *sim = (pbn_sim *)it.owner;
-        const uint32_t nblk = sim->net.nblk;
-        const uint32_t P = g_split_mode >= 2 ? std::min(g_split_mode, nblk) : std::min(P_auto, nblk / 8);
+        const uint32_t P = parts[i];
         if (P < 2) continue;
+        pbn_sim *sim = (pbn_sim *)items[i].owner;
+        const uint32_t nblk = sim->net.nblk;
         const uint32_t per = (nblk + P - 1) / P;
         uint32_t G = 16;
         while (G > 1 && G > per) G /= 2;
@@ -1143,9 +1174,16 @@ double step_latency_us(const Net &net, bool latency)
     return probe.kernel ? 2.5 + per * n / probe.kernel : 1.0 + 1.0 * n;
 }
 
-uint64_t slice_len(const pbn_sim *sim, double tick_us, bool latency)
+// split: latency-shaped launches of this round may spread a large network's
+// 64-chain groups over up to min(16, blocks / 8) CUs; a transition then costs
+// about 6 us of exchange plus the node work over all those waves.
+uint64_t slice_len(const pbn_sim *sim, double tick_us, bool latency, bool split)
 {
-    const double q = std::floor(tick_us / step_latency_us(sim->net, latency) / 32.0) * 32.0;
+    double us = step_latency_us(sim->net, latency);
+    const uint32_t parts = std::min<uint32_t>(kSplitMaxParts, sim->net.nblk / 8);
+    if (latency && split && g_split_mode != 1 && parts >= 2 && sim->net.bitsliced)
+        us = std::min(us, 6.0 + 0.25 * sim->net.n / (16.0 * parts));
+    const double q = std::floor(tick_us / us / 32.0) * 32.0;
     return (uint64_t)std::max(32.0, q);
 }
 
@@ -1177,7 +1215,7 @@ int round_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, 
             if (target > sim->max_len) { err = "request beyond the bit-stream capacity"; return PBN_ELIMIT; }
             if (sim->t_done + (target - sim->len) >= (1ull << 32)) { err = "transition index limit"; return PBN_ELIMIT; }
             uint64_t ext = target - sim->len;
-            if (tick_us > 0.0) ext = std::min(ext, slice_len(sim, tick_us, latency != 0));
+            if (tick_us > 0.0) ext = std::min(ext, slice_len(sim, tick_us, latency != 0, allow_fork));
             sim_extend_items(sim, 0, ext, 1, items, latency != 0);
         }
     }

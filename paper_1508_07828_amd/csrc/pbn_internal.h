@@ -108,6 +108,8 @@ struct SplitGroup {
 // Polls of a block's counter wait before it gives up (each poll reads the
 // counter from memory and sleeps, together well over 100 ns).
 constexpr uint32_t kSplitSpins = 1u << 20;
+// Parts of one node-split group, at most.
+constexpr uint32_t kSplitMaxParts = 16;
 constexpr uint32_t split_head(uint32_t P) { return 2 * (P + 1); }
 constexpr uint32_t split_rec_off(uint32_t P, uint32_t groups) { return (split_head(P) + groups + 3) / 4 * 4; }
 // The node-split tables of net for P parts (layout of SplitGroup::tab).

@@ -574,6 +574,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     uint32_t *Q = (uint32_t *)(Pw + 2 * G) + wave * 3 * kQCap;
     uint32_t *acc = (uint32_t *)(Pw + 2 * G) + G * 3 * kQCap + lane;
     uint32_t *abort_flag = (uint32_t *)(Pw + 2 * G) + G * 3 * kQCap + 64 * kMaxProps;
+    uint64_t *xpl = (uint64_t *)(abort_flag + 2);          // the parts' perturbed-chain words
+    uint8_t *owner = (uint8_t *)(xpl + kSplitMaxParts);    // part of each 16-node block
     const uint64_t words_cap = v.d->words_cap;
     const bool recorder = r == 0;
 
@@ -592,6 +594,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     for (uint32_t i = threadIdx.x; i < m_hi - m_lo; i += 64 * G) M[i] = 0ull;
     if (threadIdx.x < 2 * G) Pw[threadIdx.x] = 0ull;
     if (threadIdx.x == 0) *abort_flag = 0u;
+    for (uint32_t b = threadIdx.x; b < v.nblk; b += 64 * G) {
+        uint32_t q = 0;
+        while (q + 1 < P && tab[q + 1] <= b) ++q;
+        owner[b] = (uint8_t)q;
+    }
     uint64_t pos = it.pos0;
     const uint32_t nprops = v.nprops;
     if (wave == 0 && recorder) {
@@ -713,18 +720,39 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             if (threadIdx.x == 0) __hip_atomic_store(errw, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return;
         }
+        if (threadIdx.x < P) xpl[threadIdx.x] = __hip_atomic_load(&XP[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
         uint64_t Pall = 0;
-        for (uint32_t q = 0; q < P; ++q) Pall |= __hip_atomic_load(&XP[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // node i of part q: h_i, except S_i in the chains perturbed outside q
-        for (uint32_t q = 0; q < P; ++q) {
-            const uint32_t a = 16 * tab[q], e = min(16 * tab[q + 1], n);
-            const uint64_t keep = Pall & ~__hip_atomic_load(&XP[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            for (uint32_t i = a + threadIdx.x; i < e; i += 64 * G) {
-                const uint64_t h = q == r ? Fm[i - i_lo] : __hip_atomic_load(&X[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                S[i] = (h & ~keep) | (S[i] & keep);
+        for (uint32_t q = 0; q < P; ++q) Pall |= xpl[q];
+        // node i of part q: h_i, except S_i in the chains perturbed outside q;
+        // the other parts' words are loaded eight at a time before any is used
+        constexpr uint32_t U = 8;
+        for (uint32_t i0 = threadIdx.x; i0 < n; i0 += 64 * G * U) {
+            uint64_t h[U];
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t i = i0 + u * 64 * G;
+                h[u] = 0ull;
+                if (i < n && (i < i_lo || i >= i_hi))
+                    h[u] = __hip_atomic_load(&X[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t i = i0 + u * 64 * G;
+                if (i < n) {
+                    const uint32_t q = owner[i >> 4];
+                    uint64_t hv = h[u];
+                    if (q == r) {
+                        // own node: h from LDS, and the next transition's words cleared
+                        // by the thread that read them
+                        hv = Fm[i - i_lo];
+                        Gm[i - i_lo] = Fm[i - i_lo] = 0ull;
+                    }
+                    const uint64_t keep = Pall & ~xpl[q];
+                    S[i] = (hv & ~keep) | (S[i] & keep);
+                }
             }
         }
-        for (uint32_t k = threadIdx.x; k < n_own; k += 64 * G) Gm[k] = Fm[k] = 0ull;
         if (s >= it.nburn && ++since == it.thin) {
             since = 0;
             pending = true;
@@ -764,7 +792,7 @@ size_t bs_lds_bytes(uint32_t n, uint32_t msel_total, uint32_t G)
 size_t split_lds_bytes(uint32_t n, uint32_t n_own, uint32_t m_own, uint32_t G)
 {
     return (size_t)8 * ((size_t)n + 2 * (size_t)n_own + m_own + 2 * G) + (size_t)4 * 3 * kQCap * G +
-           (size_t)4 * 64 * kMaxProps + 16;
+           (size_t)4 * 64 * kMaxProps + 8 + 8 * kSplitMaxParts + ((n + 15) / 16 + 15) / 16 * 16;
 }
 
 int launch_step_split(const StepItem *d_items, uint32_t nitems, uint32_t G, size_t lds, void *stream,
