@@ -252,10 +252,12 @@ int pbn_set_kernel(int mode, uint32_t waves);
  * device memory once per transition, behind a bounded arrival counter).  It
  * is used only by calls that own the device while they run: run_chains,
  * pbn_batch_run, estimate_prob, a single-network pbn_batch_estimate and the
- * server rounds.  parts: 0 = automatic (launches of at most 128 64-chain
- * groups, up to 256 / groups parts of at least 8 node blocks, at most 16),
- * 1 = never, P >= 2 = P parts for every bit-sliced group whose network has at
- * least P 16-node blocks (fewer otherwise).  Results do not depend on the
+ * server rounds.  parts: 0 = automatic (while a launch has fewer 64-chain
+ * groups than the device has CUs, the spare CUs go one at a time to the group
+ * with the most remaining work per part, each group taking at most 16 parts
+ * of at least 8 16-node blocks), 1 = never, P >= 2 = P parts for every
+ * bit-sliced group whose network has at least P 16-node blocks (fewer
+ * otherwise).  Results do not depend on the
  * choice.  A group whose blocks cannot all be resident gives up after about a
  * second and the call returns PBN_EDEVICE. */
 int pbn_set_split(uint32_t parts);

@@ -482,7 +482,7 @@ int pbn_server_step(pbn_server *srv, uint32_t *active, uint32_t *waiting, uint32
     if (!runs.empty()) {
         // time-sliced: a request that needs a long extension does not hold the
         // others (or the next admissions) for its whole length
-        int rc = pbn::run_round(runs, srv->ws, srv->stream, err, pbn::kTickUs);
+        int rc = pbn::run_round(runs, srv->ws, srv->stream, err, pbn::kServeTickUs);
         if (rc) return fail(rc, err);
     }
     // retire finished requests and free their memory for the next admission

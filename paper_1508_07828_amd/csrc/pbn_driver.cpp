@@ -797,7 +797,13 @@ int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, 
             if (g_split_mode >= 2) parts[i] = std::min(std::min(g_split_mode, kSplitMaxParts), nblk);
             else cand.push_back(i);
         }
-        if (g_split_mode == 0 && items.size() < kCus && !cand.empty()) {
+        bool hinted = false;
+        for (size_t i : cand)
+            if (items[i].parts_hint >= 2) {
+                parts[i] = std::min(items[i].parts_hint, kSplitMaxParts);
+                hinted = true;
+            }
+        if (g_split_mode == 0 && !hinted && items.size() < kCus && !cand.empty()) {
             auto work = [&](size_t i) {
                 const StepItem &it = items[i];
                 return (double)it.nodes * (double)(it.nburn + (uint64_t)it.nrec * it.thin) / (double)parts[i];
@@ -1174,15 +1180,46 @@ double step_latency_us(const Net &net, bool latency)
     return probe.kernel ? 2.5 + per * n / probe.kernel : 1.0 + 1.0 * n;
 }
 
-// split: latency-shaped launches of this round may spread a large network's
-// 64-chain groups over up to min(16, blocks / 8) CUs; a transition then costs
-// about 6 us of exchange plus the node work over all those waves.
-uint64_t slice_len(const pbn_sim *sim, double tick_us, bool latency, bool split)
+// Node-split parts per simulation of one launch: the CUs beyond the launch's
+// 64-chain groups go, a part at a time, to the simulation with the most work
+// per part (n x transitions / parts); one more part costs one CU per 64-chain
+// group of that simulation.  At most kSplitMaxParts parts of at least 8 node
+// blocks, bit-sliced networks only.
+static void plan_parts(const std::vector<std::pair<pbn_sim *, uint64_t>> &ext, std::vector<uint32_t> &parts)
+{
+    constexpr uint64_t kCus = 256;
+    uint64_t used = 0;
+    for (const auto &e : ext) used += (e.first->omega + 63) / 64;
+    if (used >= kCus) return;
+    uint64_t spare = kCus - used;
+    auto cap = [&](size_t k) {
+        const Net &net = ext[k].first->net;
+        return net.bitsliced ? std::min<uint32_t>(kSplitMaxParts, net.nblk / 8) : 1u;
+    };
+    auto work = [&](size_t k) { return (double)ext[k].first->net.n * (double)ext[k].second / parts[k]; };
+    auto lower = [&](size_t a, size_t b) { return work(a) < work(b); };
+    std::priority_queue<size_t, std::vector<size_t>, decltype(lower)> pq(lower);
+    for (size_t k = 0; k < ext.size(); ++k)
+        if (cap(k) >= 2) pq.push(k);
+    while (!pq.empty()) {
+        const size_t k = pq.top();
+        pq.pop();
+        const uint64_t groups = (ext[k].first->omega + 63) / 64;
+        if (groups > spare) continue;
+        ++parts[k];
+        spare -= groups;
+        if (parts[k] < cap(k)) pq.push(k);
+    }
+}
+
+// parts: the network's 64-chain groups are spread over that many CUs in the
+// node-split form (forced part counts included); a transition then costs
+// about 6 us of exchange plus the one-block time over the parts.
+uint64_t slice_len(const pbn_sim *sim, double tick_us, bool latency, uint32_t parts)
 {
     double us = step_latency_us(sim->net, latency);
-    const uint32_t parts = std::min<uint32_t>(kSplitMaxParts, sim->net.nblk / 8);
-    if (latency && split && g_split_mode != 1 && parts >= 2 && sim->net.bitsliced)
-        us = std::min(us, 6.0 + 0.25 * sim->net.n / (16.0 * parts));
+    if (g_split_mode >= 2) parts = std::min(std::min(g_split_mode, kSplitMaxParts), sim->net.nblk);
+    if (latency && parts >= 2 && g_split_mode != 1 && sim->net.bitsliced) us = std::min(us, 6.0 + us / parts);
     const double q = std::floor(tick_us / us / 32.0) * 32.0;
     return (uint64_t)std::max(32.0, q);
 }
@@ -1201,6 +1238,7 @@ int round_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, 
     }
     // 1. extensions for runs with no request ready at their current length
     std::vector<StepItem> items;
+    std::vector<std::pair<pbn_sim *, uint64_t>> ext;
     for (SimRun *run : runs) {
         if (run->finished()) continue;
         pbn_sim *sim = run->sim;
@@ -1214,10 +1252,20 @@ int round_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, 
         if (!ready) {
             if (target > sim->max_len) { err = "request beyond the bit-stream capacity"; return PBN_ELIMIT; }
             if (sim->t_done + (target - sim->len) >= (1ull << 32)) { err = "transition index limit"; return PBN_ELIMIT; }
-            uint64_t ext = target - sim->len;
-            if (tick_us > 0.0) ext = std::min(ext, slice_len(sim, tick_us, latency != 0, allow_fork));
-            sim_extend_items(sim, 0, ext, 1, items, latency != 0);
+            ext.push_back({sim, target - sim->len});
         }
+    }
+    // node-split parts per simulation (time-sliced rounds that own the device),
+    // decided before slicing so that each slice is about tick_us long
+    std::vector<uint32_t> parts(ext.size(), 1);
+    if (tick_us > 0.0 && allow_fork && latency && g_split_mode == 0) plan_parts(ext, parts);
+    for (size_t k = 0; k < ext.size(); ++k) {
+        pbn_sim *sim = ext[k].first;
+        uint64_t e = ext[k].second;
+        if (tick_us > 0.0) e = std::min(e, slice_len(sim, tick_us, latency != 0, allow_fork ? parts[k] : 1));
+        const size_t first = items.size();
+        sim_extend_items(sim, 0, e, 1, items, latency != 0);
+        for (size_t i = first; i < items.size(); ++i) items[i].parts_hint = parts[k];
     }
     int rc = launch_items(items, ws, stream, err, allow_fork, allow_fork);
     if (rc) return rc;

@@ -142,6 +142,11 @@ constexpr uint64_t kLatencyWaves = 256 * 24;
 uint64_t latency_waves(const pbn_sim *sim);
 // Kernel time per extension slice of a time-sliced round (microseconds).
 constexpr double kTickUs = 5000.0;
+// Server rounds: shorter slices, since a request's result waits for the end of
+// the round it finishes in (continuous batching admits and answers at round
+// boundaries); measured on the serving stream, 1.5 ms balanced the median
+// against the latency of the largest requests.
+constexpr double kServeTickUs = 1500.0;
 // The express lane of a batch takes its latency shape once its unfinished work
 // is at most this many waves (a few CUs' worth beside the bulk).
 constexpr uint64_t kExpressLatencyWaves = 512;

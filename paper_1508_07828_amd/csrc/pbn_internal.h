@@ -130,6 +130,8 @@ struct StepItem {
     uint32_t part;               // node-split form: this block's part
     const SplitGroup *grp;       // node-split form: the group (null otherwise)
     void *owner;                 // host-side: the simulation the item advances
+    uint32_t parts_hint;         // host-side: node-split parts planned for it (0 = none)
+    uint32_t pad_;
 };
 
 enum QueryKind : uint32_t { kQueryWindow = 0, kQueryBatch = 1 };

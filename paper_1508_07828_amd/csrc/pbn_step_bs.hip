@@ -704,10 +704,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __syncthreads();
         if (threadIdx.x == 0) {
-            __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t target = P * (s + 1);
+            // the last block to arrive need not poll
+            const uint32_t seen = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
             uint32_t spins = 0;
-            while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            while (seen < target && __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                 if (++spins > kSplitSpins) {
                     *abort_flag = 1u;
                     break;
@@ -720,15 +721,12 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             if (threadIdx.x == 0) __hip_atomic_store(errw, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return;
         }
-        if (threadIdx.x < P) xpl[threadIdx.x] = __hip_atomic_load(&XP[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        uint64_t Pall = 0;
-        for (uint32_t q = 0; q < P; ++q) Pall |= xpl[q];
-        // node i of part q: h_i, except S_i in the chains perturbed outside q;
-        // the other parts' words are loaded eight at a time before any is used
+        // node i of part q: h_i, except S_i in the chains perturbed outside q.
+        // Every thread issues its first eight node words, the first P threads
+        // the parts' perturbed-chain words (into LDS), before any is used.
         constexpr uint32_t U = 8;
-        for (uint32_t i0 = threadIdx.x; i0 < n; i0 += 64 * G * U) {
-            uint64_t h[U];
+        uint64_t h[U];
+        auto load_batch = [&](uint32_t i0) {
 #pragma unroll
             for (uint32_t u = 0; u < U; ++u) {
                 const uint32_t i = i0 + u * 64 * G;
@@ -736,6 +734,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
                 if (i < n && (i < i_lo || i >= i_hi))
                     h[u] = __hip_atomic_load(&X[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
+        };
+        auto apply_batch = [&](uint32_t i0, uint64_t Pall) {
 #pragma unroll
             for (uint32_t u = 0; u < U; ++u) {
                 const uint32_t i = i0 + u * 64 * G;
@@ -752,6 +752,18 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
                     S[i] = (hv & ~keep) | (S[i] & keep);
                 }
             }
+        };
+        uint64_t Pall = 0;
+        // every thread runs the first pass (and its barrier), whatever n is
+        for (uint32_t i0 = threadIdx.x, first = 1; first || i0 < n; i0 += 64 * G * U, first = 0) {
+            load_batch(i0);
+            if (first) {
+                if (threadIdx.x < P)
+                    xpl[threadIdx.x] = __hip_atomic_load(&XP[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __syncthreads();
+                for (uint32_t q = 0; q < P; ++q) Pall |= xpl[q];
+            }
+            apply_batch(i0, Pall);
         }
         if (s >= it.nburn && ++since == it.thin) {
             since = 0;
