@@ -34,9 +34,17 @@ __device__ __forceinline__ void philox4(uint32_t c0, uint32_t c1, uint32_t c2, u
         // one 32x32->64 product per word (v_mad_u64_u32) instead of separate
         // high and low multiplies: about 1.3x the Philox rate on gfx950
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
-        c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        if (r < 2) {
+            // the first rounds mix words that are often wave-uniform (transition,
+            // block, stream tag): plain XORs stay on the scalar unit there
+            c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+            c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        } else {
+            // three-input XOR in one v_bitop3_b32 (truth table 0x96)
+            c0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+            c2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
+        }
         c1 = (uint32_t)p1;
-        c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
         c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
