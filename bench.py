@@ -343,9 +343,14 @@ def main() -> int:
 
 
 def kernel_sha() -> str:
+    """Hash of the sources the step kernel is compiled from (kernel file and the
+    headers it includes), so recorded counter traffic is used only while it
+    still describes the same kernel."""
     import hashlib
-    src = os.path.join(ROOT, "paper_1508_07828_amd", "csrc", "pbn_step_bs.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in ("pbn_step_bs.hip", "pbn_device.h", "pbn_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1508_07828_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def copy_probe(mib: int = 1024, reps: int = 4) -> int:
