@@ -161,21 +161,23 @@ def single_workload(pkg, torch, name: str, steps: int, warmup: int, cpu_s: float
         "config": {"workload": "{}: one random PBN, n={}, {} chains, {} state set(s), {} r={} s={}, psrf {}".format(
             name, job.net.n, job.chains, len(job.patterns), job.method, job.r, job.confidence, job.psrf_max),
             "chain_len": int(sim.position()[0]), "transitions": int(sim.position()[1])},
-        "roofline": roofline_of(prof, total_t),
+        "roofline": roofline_of(prof, total_t, batched=False),
         "results": [{k: r[k] for k in ("prob", "ci_lo", "ci_hi", "psi", "n", "N", "M", "kappa", "batches")} for r in res],
-        "cpu_baseline": None if no_cpu else cpu_baseline([job], cpu_s),
+        "cpu_baseline": None if no_cpu else cpu_baseline([job], cpu_s, "the {} configuration".format(name)),
     }
     return line
 
 
-def roofline_of(prof: dict, total_t: float) -> dict:
+def roofline_of(prof: dict, total_t: float, batched: bool = True) -> dict:
     launches = max(1, prof["launches"])
     avg_launch_s = prof["kernel_ms"] / launches / 1e3
     ops_per_launch = prof["alg_ops"] / launches
     achieved = ops_per_launch / max(avg_launch_s, 1e-12)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32_OPS / 1e12, "unit": "Tops/s",
                 "frac": achieved / PEAK_INT32_OPS, "traffic": None,
-                "kernel": "k_step_bs", "launches": int(prof["launches"]),
+                # the node-split form when most dispatches used it (latency-bound plain solves)
+                "kernel": "k_step_split" if 2 * prof["split_launches"] > prof["launches"] else "k_step_bs",
+                "launches": int(prof["launches"]), "split_launches": int(prof["split_launches"]),
                 "avg_launch_ms": avg_launch_s * 1e3,
                 "alg_ops_per_launch": ops_per_launch,
                 "kernel_node_updates_per_s": prof["node_updates"] / max(prof["kernel_ms"] / 1e3, 1e-12),
@@ -183,15 +185,16 @@ def roofline_of(prof: dict, total_t: float) -> dict:
                 # launches of the lanes overlap: the chip-wide rate over the timed region
                 "aggregate_tops": prof["alg_ops"] / total_t / 1e12,
                 "aggregate_frac": prof["alg_ops"] / total_t / PEAK_INT32_OPS}
+    # counter traffic recorded on the batched workload's k_step_bs dispatches
     tr = os.path.join(ROOT, "profiles", "k_step_bs_traffic.json")
-    if os.path.exists(tr):
+    if batched and roofline["kernel"] == "k_step_bs" and os.path.exists(tr):
         info = json.load(open(tr))
         if info.get("kernel_source_sha") == kernel_sha():
             roofline["traffic"] = info.get("bytes_per_launch")
     return roofline
 
 
-def cpu_baseline(jobs, budget_s: float):
+def cpu_baseline(jobs, budget_s: float, label: str = "the batched workload"):
     import oracle
     threads = min(os.cpu_count() or 1, 16)
     done_nu, t_used, used = 0.0, 0.0, 0
@@ -206,9 +209,9 @@ def cpu_baseline(jobs, budget_s: float):
         done_nu += float(steps) * j.chains * j.net.n
         used += 1
     return dict(value=done_nu / t_used, unit="node-updates/s", cores=threads, kind="oracle",
-                sample="first {} networks of the batched workload, all their chains, {} recorded steps each "
+                sample="first {} network(s) of {}, all their chains, {} recorded steps each "
                        "(CPU simulator with indicator recording, {} threads over chains, {:.1f} s)".format(
-                           used, steps, threads, t_used))
+                           used, label, steps, threads, t_used))
 
 
 def main() -> int:

@@ -236,6 +236,7 @@ typedef struct {
     double node_updates;         /* chain_steps x n                          */
     double alg_ops;              /* see above                                */
     double philox_evals;         /* expected Philox4x32-10 evaluations       */
+    uint64_t split_launches;     /* launches of the node-split form (k_step_split) among them */
 } pbn_profile;
 
 int pbn_profile_enable(int on);

@@ -1028,6 +1028,7 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
                 mark.ops += cs * it.ops_per_step;
                 mark.philox += cs * it.philox_per_step;
             }
+            mark.split = (g.cls >> 16) == 2;
             profile_begin(mark, s);
         }
         const int r = g.kernel == 0           ? launch_step(d, (uint32_t)g.count, g.maxW, s, err)
@@ -1122,6 +1123,7 @@ int profile_collect(pbn_profile *out, std::string &err)
         p.acc.node_updates += m.node_updates;
         p.acc.alg_ops += m.ops;
         p.acc.philox_evals += m.philox;
+        p.acc.split_launches += m.split ? 1 : 0;
         p.pool.push_back(m.start);
         p.pool.push_back(m.stop);
     }

@@ -191,6 +191,7 @@ int run_to_completion(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t st
 struct ProfileMark {
     hipEvent_t start = nullptr, stop = nullptr;
     double chain_steps = 0, node_updates = 0, ops = 0, philox = 0;
+    bool split = false;
 };
 bool profiling();
 void profile_begin(ProfileMark &m, hipStream_t stream);
