@@ -262,6 +262,12 @@ int pbn_set_kernel(int mode, uint32_t waves);
  * choice.  A group whose blocks cannot all be resident gives up after about a
  * second and the call returns PBN_EDEVICE. */
 int pbn_set_split(uint32_t parts);
+/* Polls of its group's arrival counter that a node-split block makes before it
+ * gives up (0 = the default, 2^20, about a second).  For tests of the failure
+ * path: with a tiny value a group whose parts do not arrive together ends
+ * early and the call returns PBN_EDEVICE; the chains' state is then undefined
+ * until the simulation is reset. */
+int pbn_set_split_polls(uint32_t polls);
 int pbn_profile_read(pbn_profile *out);
 int pbn_profile_reset(void);
 

@@ -27,7 +27,7 @@ EXPORTS = (
     "pbn_sim_read_state", "pbn_sim_read_bits", "pbn_sim_position", "pbn_sim_sync", "estimate_prob",
     "pbn_batch_run", "pbn_batch_estimate", "pbn_server_create", "pbn_server_free", "pbn_server_submit",
     "pbn_server_step", "pbn_server_poll", "pbn_server_memory", "pbn_normal_quantile", "pbn_t_quantile",
-    "pbn_last_error", "pbn_profile_enable", "pbn_profile_read", "pbn_profile_reset", "pbn_set_kernel", "pbn_set_split",
+    "pbn_last_error", "pbn_profile_enable", "pbn_profile_read", "pbn_profile_reset", "pbn_set_kernel", "pbn_set_split", "pbn_set_split_polls",
     "pbn_autotune", "pbn_autotune_reset",
 )
 
@@ -128,6 +128,7 @@ def lib():
         "pbn_profile_reset": (i32, []),
         "pbn_set_kernel": (i32, [i32, u32]),
         "pbn_set_split": (i32, [u32]),
+        "pbn_set_split_polls": (i32, [u32]),
         "pbn_autotune": (i32, [vp, ctypes.POINTER(TuneRow), u32, ctypes.POINTER(u32)]),
         "pbn_autotune_reset": (i32, []),
     }
@@ -160,6 +161,11 @@ def set_kernel(mode: str = "auto", waves: int = 0) -> None:
 def set_split(parts: int = 0) -> None:
     """Node-split form: 0 automatic, 1 never, P >= 2 forced P parts per 64-chain group."""
     _check(lib().pbn_set_split(parts))
+
+
+def set_split_polls(polls: int = 0) -> None:
+    """Counter polls before a node-split block gives up (0 = default; tests of the failure path)."""
+    _check(lib().pbn_set_split_polls(polls))
 
 
 class TuneRow(ctypes.Structure):

@@ -528,6 +528,12 @@ int pbn_set_split(uint32_t parts)
     return PBN_OK;
 }
 
+int pbn_set_split_polls(uint32_t polls)
+{
+    pbn::set_split_spins(polls);
+    return PBN_OK;
+}
+
 int pbn_autotune(void *hip_stream, pbn_tune_row *rows, uint32_t cap, uint32_t *count)
 {
     std::string err;

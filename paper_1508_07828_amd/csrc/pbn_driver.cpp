@@ -672,9 +672,11 @@ void set_kernel_mode(int mode, uint32_t waves)
 
 namespace {
 uint32_t g_split_mode = 0;
+uint32_t g_split_spins = kSplitSpins;
 }  // namespace
 
 void set_split_mode(uint32_t parts) { g_split_mode = parts; }
+void set_split_spins(uint32_t polls) { g_split_spins = polls ? polls : kSplitSpins; }
 
 uint64_t latency_waves(const pbn_sim *sim)
 {
@@ -877,6 +879,8 @@ int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, 
         g.err = ws.d_err;
         g.nparts = p.P;
         g.groups = p.tab.groups;
+        g.spins = g_split_spins;
+        g.pad_ = 0;
         xoff += 2 * (size_t)sim->net.n + 2 * (size_t)p.P;
         for (uint32_t r = 0; r < p.P; ++r) {
             StepItem s = items[i];

@@ -211,6 +211,8 @@ void set_kernel_mode(int mode, uint32_t waves);
 // Node-split form: 0 = automatic, 1 = never, P >= 2 = P parts wherever the
 // network has P node blocks (launches that allow it).
 void set_split_mode(uint32_t parts);
+// Polls a node-split part makes before it gives up (0 = the default).
+void set_split_spins(uint32_t polls);
 
 // Launch step items for several sims (sorted by cost) on stream.  allow_split:
 // the launch owns the device (nothing else runs beside it that could hold the

@@ -104,9 +104,11 @@ struct SplitGroup {
     uint32_t *ctr;
     uint32_t *err;
     uint32_t nparts, groups;
+    uint32_t spins, pad_;        // polls of the counter before a part gives up
 };
 // Polls of a block's counter wait before it gives up (each poll reads the
-// counter from memory and sleeps, together well over 100 ns).
+// counter from memory and sleeps, together well over 100 ns); tests of the
+// failure path lower it.
 constexpr uint32_t kSplitSpins = 1u << 20;
 // Parts of one node-split group, at most.
 constexpr uint32_t kSplitMaxParts = 16;

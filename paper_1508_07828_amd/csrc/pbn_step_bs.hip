@@ -548,7 +548,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     if (it.nchains == 0) return;         // padding of an XCD-aware launch
     const BsView v = load_bs_view(it.sim);
     const PBN_CAS SplitGroup *sg = (const PBN_CAS SplitGroup *)it.grp;
-    const uint32_t P = sg->nparts, r = it.part, groups = sg->groups;
+    const uint32_t P = sg->nparts, r = it.part, groups = sg->groups, max_spins = sg->spins;
     const cu32 tab = (cu32)sg->tab;
     PBN_GAS uint64_t *xch = (PBN_GAS uint64_t *)sg->xch;
     PBN_GAS uint32_t *ctr = (PBN_GAS uint32_t *)sg->ctr;
@@ -709,7 +709,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             const uint32_t seen = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
             uint32_t spins = 0;
             while (seen < target && __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                if (++spins > kSplitSpins) {
+                if (++spins >= max_spins) {
                     *abort_flag = 1u;
                     break;
                 }

@@ -158,6 +158,38 @@ def test_split_burn_in_and_thinning(split):
     assert sim.position() == (40, 131)
 
 
+def test_split_gives_up_cleanly():
+    """With a one-poll limit a part that reaches a transition's barrier before
+    its group gives up at once: the launch ends early (no hang), the call
+    reports the failure, and a reset restores a simulation that matches the
+    oracle again."""
+    net, omega, pats = CASES["n300_l4"]()
+    text = ps.to_text(net)
+    say("split failure path: 5 parts, one poll")
+    sim = pkg.Simulation(pkg.Network(text), omega, 7828, max_props=1, max_len=4096)
+    failed = False
+    pkg.set_split(5)
+    pkg.set_split_polls(1)
+    try:
+        for attempt in range(5):
+            sim.reset(pats)
+            try:
+                sim.run(300)
+            except pkg.PbnError as e:
+                assert e.code == pkg.PBN_EDEVICE and "gave up" in str(e), e
+                failed = True
+                break
+    finally:
+        pkg.set_split_polls(0)
+        pkg.set_split(0)
+    assert failed
+    sim.reset(pats)
+    ch = oracle.Chains(oracle.Net(text), omega, 7828, pats)
+    sim.run(37)
+    ch.extend(37)
+    assert np.array_equal(sim.read_state(), ch.states)
+
+
 def test_split_estimate_equals_oracle():
     job = ps.medium()
     text = ps.to_text(job.net)
