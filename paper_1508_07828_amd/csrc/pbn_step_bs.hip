@@ -163,6 +163,11 @@ __device__ __forceinline__ void push(bool mine, uint32_t hdr, uint32_t flo, uint
 }
 
 // Resolve queued ties with the refinement words (stream tag + 1), lane = entry.
+// Both kinds run one code path: a selection entry's node, threshold and mask
+// index are fixed per entry (loaded before its flags are walked), a
+// perturbation entry's chain is; each flag then names the other coordinate,
+// and a refined draw below the threshold sets one bit of an LDS word (the mask
+// M for a selection, the next state Gm for a perturbation).
 __device__ __forceinline__ void resolve(const BsView &v, uint32_t t, uint32_t chain0, const uint32_t *Q,
                                         uint32_t qlen, uint64_t *Gm, uint32_t i_lo, uint64_t *M, uint32_t m_lo,
                                         uint64_t *Pw_mine, uint32_t lane)
@@ -171,41 +176,38 @@ __device__ __forceinline__ void resolve(const BsView &v, uint32_t t, uint32_t ch
     const uint32_t pthr24 = v.p_thr & 0xFFFFFFu;
     for (uint32_t e = lane; e < qlen; e += 64) {
         const uint32_t hdr = Q[e];
-        const uint32_t kind = hdr & 1u, b = hdr >> 7;
+        const bool sel = (hdr & 1u) != 0;
+        const uint32_t b = hdr >> 7;
         uint64_t f = (uint64_t)Q[kQCap + e] | ((uint64_t)Q[2 * kQCap + e] << 32);
-        const uint32_t tag = (kind ? kTagSel : kTagPert) + 1;
+        const uint32_t tag = (sel ? kTagSel : kTagPert) + 1;
+        // per entry: a selection's node i_s, threshold (low 24 bits) and mask word;
+        // a perturbation's chain
+        const uint32_t i_s = 16 * b + ((hdr >> 1) & 15u), j_s = (hdr >> 5) & 3u;
+        uint32_t thr = pthr24, midx = 0;
+        if (sel) {
+            thr = v.fn_thr[v.nd_first[i_s] + j_s] & 0xFFFFFFu;
+            midx = (v.nd_info[2 * i_s] >> 8) + j_s - m_lo;
+        }
+        const uint32_t cl_p = (hdr >> 1) & 63u;
         uint32_t rq = 0xFFFFFFFFu, r[4] = {0u, 0u, 0u, 0u};
         bool flipped = false;
         while (f) {
             const uint32_t x = (uint32_t)__builtin_ctzll(f);
             f &= f - 1;
-            uint32_t cl, i, j;
-            if (kind == 0) {
-                cl = (hdr >> 1) & 63u;
-                i = 16 * b + 4 * (x & 7u) + (x >> 3);
-                j = 0;
-            } else {
-                cl = x;
-                i = 16 * b + ((hdr >> 1) & 15u);
-                j = (hdr >> 5) & 3u;
-            }
+            const uint32_t cl = sel ? x : cl_p;
+            const uint32_t i = sel ? i_s : 16 * b + 4 * (x & 7u) + (x >> 3);
             const uint32_t key = (cl << 24) | (i >> 2);
             if (key != rq) {
                 rq = key;
                 philox4(t, chain0 + cl, i >> 2, tag, v.key, r);
             }
             const uint32_t r24 = pick4(r, i & 3u) & 0xFFFFFFu;
-            if (kind == 0) {
-                if (r24 < pthr24) {
-                    lds_or(&Gm[i - i_lo], 1ull << cl);
-                    flipped = true;
-                }
-            } else {
-                const uint32_t T = v.fn_thr[v.nd_first[i] + j];
-                if (r24 < (T & 0xFFFFFFu)) lds_or(&M[(v.nd_info[2 * i] >> 8) + j - m_lo], 1ull << cl);
+            if (r24 < thr) {
+                lds_or(sel ? &M[midx] : &Gm[i - i_lo], 1ull << cl);
+                flipped |= !sel;
             }
         }
-        if (flipped) lds_or(Pw_mine, 1ull << ((hdr >> 1) & 63u));
+        if (flipped) lds_or(Pw_mine, 1ull << cl_p);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
