@@ -57,7 +57,9 @@ enum { PBN_TWO_STATE = 0, PBN_SKART = 1 };
 /* Limits: n <= 65535 nodes, l(i) <= 64 functions per node, k <= 16 parents per
  * function, at most PBN_MAX_PROPS state sets per simulation and
  * PBN_MAX_TERMS (node, value) terms over all of them, transitions per chain
- * below 2^32. */
+ * below 2^32.  Every n is simulated: networks whose bit-sliced state does not
+ * fit in LDS run the lane-per-chain kernel, whose per-chain state rows move
+ * from LDS to library-owned device scratch beyond n = 10240. */
 #define PBN_MAX_PROPS 8
 #define PBN_MAX_TERMS 64
 

@@ -150,6 +150,21 @@ int Workspace::ensure_split(size_t groups, size_t xch_words, std::string &err)
     return PBN_OK;
 }
 
+int Workspace::ensure_rows(size_t words, std::string &err)
+{
+    if (words <= cap_rows) return PBN_OK;
+    const size_t nc = std::max(words, 2 * cap_rows);
+    if (d_rows) (void)hipFree(d_rows);
+    d_rows = nullptr;
+    cap_rows = 0;
+    if (hipMalloc((void **)&d_rows, nc * sizeof(uint32_t)) != hipSuccess) {
+        err = "workspace state rows";
+        return PBN_ENOMEM;
+    }
+    cap_rows = nc;
+    return PBN_OK;
+}
+
 int Workspace::check_split(std::string &err)
 {
     if (!split_used) return PBN_OK;
@@ -164,6 +179,9 @@ int Workspace::check_split(std::string &err)
 
 void Workspace::release()
 {
+    if (d_rows) (void)hipFree(d_rows);
+    d_rows = nullptr;
+    cap_rows = 0;
     if (d_grp) (void)hipFree(d_grp);
     if (h_grp) (void)hipHostFree(h_grp);
     if (d_ctr) (void)hipFree(d_ctr);
@@ -489,7 +507,6 @@ int sim_setup(pbn_sim *sim, const Net &net, uint32_t omega, uint64_t seed, uint3
 {
     if (omega < 1) { err = "omega must be >= 1"; return PBN_EINVAL; }
     if (max_props > kMaxProps) { err = "too many state sets"; return PBN_ELIMIT; }
-    if (2ull * 64 * (net.W | 1u) * 4 > 160ull * 1024) { err = "network too large for the LDS state rows"; return PBN_ELIMIT; }
     const size_t need = sim_bytes(net, omega, max_props, max_len);
     if (!dev_buf || dev_bytes < need) { err = "device buffer too small"; return PBN_ENOMEM; }
     sim->net = net;
@@ -1001,6 +1018,8 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
         a = b;
     }
     if ((rc = ws.ensure(laid.size(), 0, 0, err))) return rc;
+    for (const Group &g : groups)
+        if (g.kernel == 0 && (rc = ws.ensure_rows(step_rows_words((uint32_t)g.count, g.maxW), err))) return rc;
     std::memcpy(ws.h_items, laid.data(), laid.size() * sizeof(StepItem));
     if (hipMemcpyAsync(ws.d_items, ws.h_items, laid.size() * sizeof(StepItem), hipMemcpyHostToDevice,
                        stream) != hipSuccess) {
@@ -1035,7 +1054,7 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
             mark.split = (g.cls >> 16) == 2;
             profile_begin(mark, s);
         }
-        const int r = g.kernel == 0           ? launch_step(d, (uint32_t)g.count, g.maxW, s, err)
+        const int r = g.kernel == 0           ? launch_step(d, (uint32_t)g.count, g.maxW, ws.d_rows, s, err)
                       : (g.cls >> 16) == 2 ? launch_step_split(d, (uint32_t)g.count, g.kernel, g.lds, s, err)
                                            : launch_step_bs(d, (uint32_t)g.count, g.kernel, (g.cls >> 16) != 0, g.lds, s, err);
         if (prof_on) profile_end(mark, s);

@@ -41,6 +41,10 @@ struct Workspace {
     uint64_t *d_xch = nullptr;
     uint32_t *d_ctr = nullptr, *d_err = nullptr, *h_err = nullptr;
     size_t cap_grp = 0, cap_xch = 0;
+    // lane-per-chain state rows of networks too large for LDS
+    uint32_t *d_rows = nullptr;
+    size_t cap_rows = 0;
+    int ensure_rows(size_t words, std::string &err);
     bool split_used = false;      // the last launch had node-split groups
     int ensure_split(size_t groups, size_t xch_words, std::string &err);
     // after the stream reached the last launch: PBN_EDEVICE if a node-split

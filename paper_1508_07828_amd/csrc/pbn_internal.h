@@ -156,7 +156,11 @@ struct WindowResult {
 int launch_init(const DevSim *dsim, uint32_t omega, uint32_t W, void *stream, std::string &err);
 // Descriptors staged in device memory copied to their simulations, initial states written.
 int launch_setup(const DevSim *d_staging, DevSim *const *d_dst, uint32_t count, void *stream, std::string &err);
-int launch_step(const StepItem *d_items, uint32_t nitems, uint32_t max_W, void *stream,
+// Lane-per-chain step.  Rows of more than 320 words (n > 10240) do not fit in
+// LDS: they then live in `rows`, step_rows_words(nitems, max_W) u32 of device
+// scratch (0 when LDS suffices; rows may then be null).
+size_t step_rows_words(uint32_t nitems, uint32_t max_W);
+int launch_step(const StepItem *d_items, uint32_t nitems, uint32_t max_W, uint32_t *rows, void *stream,
                 std::string &err);
 // Bit-sliced trajectory kernel: G waves per 64-chain block, lds bytes of LDS.
 // small: every wave owns at most one 16-node block and one 64-slot group.

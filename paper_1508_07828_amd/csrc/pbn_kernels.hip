@@ -197,7 +197,11 @@ extern __shared__ uint32_t lds_rows[];
 
 // One 64-lane block per work item; lane = chain.  Two LDS rows per lane
 // (current and next state) of stride S words (S odd: conflict-free rows).
-__global__ void __launch_bounds__(64) k_step(const StepItem *__restrict__ items, uint32_t S)
+// GLOBAL: the two state rows of each chain live in a device scratch area
+// (rows[(block * 64 + lane) * 2 * S ...]) instead of LDS, for networks whose
+// rows do not fit in LDS (more than 320 words, n > 10240); same arithmetic.
+template <bool GLOBAL>
+__global__ void __launch_bounds__(64) k_step(const StepItem *__restrict__ items, uint32_t S, uint32_t *rows)
 {
     const StepItem it = load_item(items, blockIdx.x);
     const View v = load_view(it.sim);
@@ -205,8 +209,14 @@ __global__ void __launch_bounds__(64) k_step(const StepItem *__restrict__ items,
     if (lane >= it.nchains) return;
     const uint32_t c = it.chain0 + lane;
     const uint32_t W = v.W, omega = v.omega, nprops = v.nprops;
-    uint32_t *cur = lds_rows + lane * S;
-    uint32_t *nxt = lds_rows + (64 + lane) * S;
+    uint32_t *cur, *nxt;
+    if (GLOBAL) {
+        cur = rows + ((size_t)blockIdx.x * 64 + lane) * 2 * S;
+        nxt = cur + S;
+    } else {
+        cur = lds_rows + lane * S;
+        nxt = lds_rows + (64 + lane) * S;
+    }
     for (uint32_t w = 0; w < W; ++w) cur[w] = v.state[(size_t)w * omega + c];
 
     uint32_t acc[kMaxProps];
@@ -393,20 +403,31 @@ int allow_full_lds(const void *fn, std::string &err)
     return PBN_OK;
 }
 
-int launch_step(const StepItem *d_items, uint32_t nitems, uint32_t max_W, void *stream, std::string &err)
+size_t step_rows_words(uint32_t nitems, uint32_t max_W)
+{
+    const size_t S = max_W | 1u;
+    return 2 * 64 * S * 4 <= 160 * 1024 ? 0 : (size_t)nitems * 64 * 2 * S;
+}
+
+int launch_step(const StepItem *d_items, uint32_t nitems, uint32_t max_W, uint32_t *rows, void *stream,
+                std::string &err)
 {
     if (nitems == 0) return PBN_OK;
     const uint32_t S = max_W | 1u;
     const size_t lds = (size_t)2 * 64 * S * 4;
     if (lds > 160 * 1024) {
-        err = "state rows exceed LDS";
-        return PBN_ELIMIT;
+        if (!rows) {
+            err = "state rows exceed LDS and no row scratch was given";
+            return PBN_ELIMIT;
+        }
+        hipLaunchKernelGGL(k_step<true>, dim3(nitems), dim3(64), 0, (hipStream_t)stream, d_items, S, rows);
+        return check(hipGetLastError(), "k_step launch", err);
     }
     if (lds > 64 * 1024) {
-        int rc = allow_full_lds((const void *)k_step, err);
+        int rc = allow_full_lds((const void *)k_step<false>, err);
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(k_step, dim3(nitems), dim3(64), lds, (hipStream_t)stream, d_items, S);
+    hipLaunchKernelGGL(k_step<false>, dim3(nitems), dim3(64), lds, (hipStream_t)stream, d_items, S, rows);
     return check(hipGetLastError(), "k_step launch", err);
 }
 

@@ -227,6 +227,25 @@ def test_large_sampled_chains(mode):
     pkg.set_kernel("auto", 0)
 
 
+def test_state_rows_beyond_lds():
+    """n = 12000: neither the bit-sliced state (2n + sum(l-1) words) nor a chain's
+    375-word rows fit in LDS, so the lane-per-chain kernel keeps its rows in
+    device scratch; results stay bit-exact."""
+    net = ps.random_network(np.random.default_rng(77), 12000, (1, 3), (1, 5), 0.001)
+    text = ps.to_text(net)
+    pats = [((0, 1), (11999, 0))]
+    omega = 70
+    say("state rows beyond LDS: n=12000, omega=70")
+    sim = pkg.Simulation(pkg.Network(text), omega, 4242, max_props=1, max_len=256)
+    sim.reset(pats)
+    ch = oracle.Chains(oracle.Net(text), omega, 4242, pats)
+    for steps in (5, 3):
+        sim.run(steps)
+        ch.extend(steps)
+        assert np.array_equal(sim.read_state(), ch.states), steps
+    assert np.array_equal(sim.read_bits(0, 0, 8), ch.bits[0])
+
+
 def test_window_counts_batch_sums_psrf():
     job = ps.medium()
     text = ps.to_text(job.net)
