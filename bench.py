@@ -168,6 +168,68 @@ def single_workload(pkg, torch, name: str, steps: int, warmup: int, cpu_s: float
     return line
 
 
+def multiprop_workload(pkg, torch, steps: int, warmup: int, cpu_s: float, no_cpu: bool) -> dict:
+    """The paper's multi-property experiment shape (Sec. 5.3, Table 2) on a
+    synthetic 96-node network: 7 state sets estimated together (one run whose
+    chains serve every property) against one by one (a run per property), both
+    on the GPU.  Reports the speed-up sum(t_i)/t_multi and the sample-size
+    reduction; each property's result must be identical in both."""
+    job = ps.multiprop()
+    net = pkg.Network(ps.to_text(job.net))
+    max_len = 1 << 15
+    kw = dict(psrf_max=job.psrf_max)
+
+    def solve(pats):
+        sim = pkg.Simulation(net, job.chains, job.seed, max_props=len(pats), max_len=max_len)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        res = sim.estimate(pats, job.r, job.confidence, **kw)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - a
+        nu = float(sim.position()[1]) * job.chains * job.net.n
+        del sim
+        return t, nu, res
+
+    for w in range(warmup):
+        log("warmup {}".format(w))
+        solve(job.patterns)
+    pkg.profile_enable(True)
+    pkg.profile_reset()
+    t_multi, nus, res_multi = [], [], None
+    for k in range(steps):
+        t, nu, res_multi = solve(job.patterns)
+        t_multi.append(t)
+        nus.append(nu)
+        log("simultaneous {}: {:.1f} ms".format(k, t * 1e3))
+    prof = pkg.profile_read()
+    pkg.profile_enable(False)
+    t_one, res_one = [], []
+    for q, pat in enumerate(job.patterns):
+        t, _, r = solve([pat])
+        t_one.append(t)
+        res_one.append(r[0])
+        log("property {} alone: {:.1f} ms".format(q, t * 1e3))
+    same = all(res_one[q][key] == res_multi[q][key] for q in range(len(job.patterns))
+               for key in ("prob", "psi", "n", "N", "M", "chain_len", "status"))
+    t_m = sum(t_multi) / len(t_multi)
+    samples_multi = job.chains * max(r["chain_len"] for r in res_multi)
+    samples_one = sum(job.chains * r["chain_len"] for r in res_one)
+    return {
+        "metric": METRIC, "value": sum(nus) / sum(t_multi), "unit": "node-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": t_m * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "multiprop: 96-node synthetic PBN (107 functions), {} chains, 7 state sets, "
+                               "two-state r={} s={}, psrf {}".format(job.chains, job.r, job.confidence, job.psrf_max)},
+        "multiprop": {"t_multi_ms": t_m * 1e3, "t_one_by_one_ms": [t * 1e3 for t in t_one],
+                      "speedup_sum_ti_over_tmulti": sum(t_one) / t_m,
+                      "samples_multi": samples_multi, "samples_one_by_one": samples_one,
+                      "sample_reduction": samples_one / samples_multi, "results_identical": bool(same),
+                      "N": [int(r["N"]) for r in res_multi], "prob": [r["prob"] for r in res_multi]},
+        "roofline": roofline_of(prof, sum(t_multi), batched=False),
+        "cpu_baseline": None if no_cpu else cpu_baseline([job], cpu_s, "the multiprop configuration"),
+    }
+
+
 def roofline_of(prof: dict, total_t: float, batched: bool = True) -> dict:
     launches = max(1, prof["launches"])
     avg_launch_s = prof["kernel_ms"] / launches / 1e3
@@ -195,23 +257,30 @@ def roofline_of(prof: dict, total_t: float, batched: bool = True) -> dict:
 
 
 def cpu_baseline(jobs, budget_s: float, label: str = "the batched workload"):
+    """The oracle's simulator on the host cores: 256-step extensions of every
+    chain of each job in turn until the time budget is spent (a single job is
+    extended repeatedly)."""
     import oracle
     threads = min(os.cpu_count() or 1, 16)
-    done_nu, t_used, used = 0.0, 0.0, 0
+    done_nu, t_used, used, chunks = 0.0, 0.0, 0, 0
     steps = 256
     for j in jobs:
         if t_used >= budget_s:
             break
         ch = oracle.Chains(oracle.Net(ps.to_text(j.net)), j.chains, j.seed, j.patterns, threads=threads)
-        a = time.perf_counter()
-        ch.extend(steps)
-        t_used += time.perf_counter() - a
-        done_nu += float(steps) * j.chains * j.net.n
         used += 1
+        while True:
+            a = time.perf_counter()
+            ch.extend(steps)
+            t_used += time.perf_counter() - a
+            done_nu += float(steps) * j.chains * j.net.n
+            chunks += 1
+            if len(jobs) > 1 or t_used >= budget_s or chunks >= 64:
+                break
     return dict(value=done_nu / t_used, unit="node-updates/s", cores=threads, kind="oracle",
-                sample="first {} network(s) of {}, all their chains, {} recorded steps each "
+                sample="{} network(s) of {}, all their chains, {} extension(s) of {} recorded steps "
                        "(CPU simulator with indicator recording, {} threads over chains, {:.1f} s)".format(
-                           used, label, steps, threads, t_used))
+                           used, label, chunks, steps, threads, t_used))
 
 
 def main() -> int:
@@ -229,7 +298,7 @@ def main() -> int:
     ap.add_argument("--waves", type=int, default=0, help="bit-sliced waves per block (0 = by n)")
     ap.add_argument("--tune", action="store_true",
                     help="measure the kernel shapes per network size first (untimed) and use them")
-    ap.add_argument("--workload", default="batched", choices=["batched", "tiny", "medium", "large"],
+    ap.add_argument("--workload", default="batched", choices=["batched", "tiny", "medium", "large", "multiprop"],
                     help="batched (default, the headline) or one plain configuration")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter scale)")
     ap.add_argument("--traffic-from", nargs=5, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE", "OUT"),
@@ -259,6 +328,9 @@ def main() -> int:
         for r in tune:
             log("  n={n}: throughput {waves_throughput} waves ({node_updates_per_s:.3e}/s), "
                 "latency {waves_latency} waves ({transition_us:.2f} us)".format(**r))
+    if args.workload == "multiprop":
+        print(json.dumps(multiprop_workload(pkg, torch, args.steps, args.warmup, args.cpu_seconds, args.no_cpu)))
+        return 0
     if args.workload != "batched":
         print(json.dumps(single_workload(pkg, torch, args.workload, args.steps, args.warmup, args.cpu_seconds,
                                          args.no_cpu)))

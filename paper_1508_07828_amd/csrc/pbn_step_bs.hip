@@ -15,9 +15,9 @@
 //   -- barrier (P complete, every M written)
 //   C  lane = predictor slot (sorted by parent count): K-input multiplexer
 //      tree over the parents' masks, restricted to the chains that selected
-//      this predictor and were not perturbed, OR-ed into Gm[node]; wave 0 also
-//      records the state-set indicators of the state reached by the previous
-//      transition
+//      this predictor and were not perturbed, OR-ed into Gm[node]; before
+//      that, wave w records the indicators of state sets w, w + G, ... for the
+//      state reached by the previous transition
 //   -- barrier (every slot done)
 //   D  own nodes: Gm[i] ^= P & S[i] (perturbed chains: S XOR gamma, the
 //      others keep the functions' values), S[i] := 0 (the next transition's
@@ -375,7 +375,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     if (threadIdx.x < 2 * G) Pw[threadIdx.x] = 0ull;
 
     // indicator words under construction, one per state set and chain, in LDS
-    // (wave 0 alone records)
+    // (state set q is recorded by wave q mod G)
     uint32_t *acc = (uint32_t *)(Pw + 2 * G) + G * 3 * kQCap + lane;
     uint64_t pos = it.pos0;
     const uint32_t nprops = v.nprops;
@@ -412,10 +412,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     const uint32_t total = it.nburn + it.nrec * it.thin;
     uint32_t since = 0;
     bool pending = false;             // the state in S awaits recording
-    // the indicators of the current state S, at position pos (wave 0)
+    // the indicators of the current state S, at position pos (this wave's state sets)
     auto record = [&]() {
         const uint32_t bpos = (uint32_t)(pos & 31);
-        for (uint32_t q = 0; q < nprops; ++q) {
+        for (uint32_t q = wave; q < nprops; q += G) {
             uint64_t xm = ~0ull;
             for (uint32_t m = v.d->pn_off[q]; m < v.d->pn_off[q + 1]; ++m) {
                 const uint64_t sv = S[v.d->pn_node[m]];
@@ -451,7 +451,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
         __syncthreads();
 
         // ---- C: predictor slots, lane = slot
-        if (pending && wave == 0) {
+        if (pending) {
             record();
             ++pos;
         }
@@ -505,14 +505,15 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
         uint64_t *tmp = S; S = Gm; Gm = tmp;
     }
     __syncthreads();
-    if (pending && wave == 0) {
+    if (pending) {
         record();
         ++pos;
     }
 
-    if (wave == 0 && active && it.nrec > 0 && (pos & 31)) {
+    if (active && it.nrec > 0 && (pos & 31)) {
         gu32 bits = (gu32)v.d->bits;
-        for (uint32_t q = 0; q < nprops; ++q) bits[((size_t)q * words_cap + (pos >> 5)) * omega + c] = acc[64 * q];
+        for (uint32_t q = wave; q < nprops; q += G)
+            bits[((size_t)q * words_cap + (pos >> 5)) * omega + c] = acc[64 * q];
     }
     // transpose back
     gu32 state = (gu32)v.d->state;
@@ -543,7 +544,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
 //      by another part only, which keep S_i.
 // The wait is bounded: a block that waits about a second gives up, sets the
 // group's error word and ends; the host then reports the failure.  Block 0 of
-// the group records the indicators and writes the state back.
+// the group records the indicators (state set q by its wave q mod G) and
+// writes the state back.
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) k_step_split(const StepItem *__restrict__ items)
 {
     const StepItem it = load_item(items, blockIdx.x);
@@ -622,7 +624,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     bool pending = false;
     auto record = [&]() {
         const uint32_t bpos = (uint32_t)(pos & 31);
-        for (uint32_t q = 0; q < nprops; ++q) {
+        for (uint32_t q = wave; q < nprops; q += G) {
             uint64_t xm = ~0ull;
             for (uint32_t m = v.d->pn_off[q]; m < v.d->pn_off[q + 1]; ++m) {
                 const uint64_t sv = S[v.d->pn_node[m]];
@@ -657,7 +659,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
         __syncthreads();
 
         // ---- C: own slots, lane = slot
-        if (pending && wave == 0 && recorder) {
+        if (pending && recorder) {
             record();
             ++pos;
         }
@@ -773,14 +775,15 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
         }
         __syncthreads();
     }
-    if (pending && wave == 0 && recorder) {
+    if (pending && recorder) {
         record();
         ++pos;
     }
     if (!recorder) return;
-    if (wave == 0 && active && it.nrec > 0 && (pos & 31)) {
+    if (active && it.nrec > 0 && (pos & 31)) {
         gu32 bits = (gu32)v.d->bits;
-        for (uint32_t q = 0; q < nprops; ++q) bits[((size_t)q * words_cap + (pos >> 5)) * omega + c] = acc[64 * q];
+        for (uint32_t q = wave; q < nprops; q += G)
+            bits[((size_t)q * words_cap + (pos >> 5)) * omega + c] = acc[64 * q];
     }
     gu32 state = (gu32)v.d->state;
     for (uint32_t w = wave; w < W; w += G) {

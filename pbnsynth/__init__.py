@@ -181,6 +181,44 @@ def serving(duration_s: float = 60.0, rate: float = 200.0, chains: int = 256,
     return jobs
 
 
+def multiprop(chains: int = 16384, r: float = 1e-4) -> Job:
+    """Shape of the paper's multi-property experiment (Sec. 5.3, Table 2): a
+    96-node network with 107 Boolean functions (11 nodes with two predictors,
+    the others with one) and 7 state sets checked together: a target node's
+    marginal and its joint values with each of three parents of one of its
+    functions, in both parent values (the quantities of a long-term influence
+    analysis).  The biological model itself is not available; structure,
+    tables and selection probabilities are drawn as in random_network."""
+    rng = np.random.default_rng(STRUCT_SEED_BASE + 5)
+    n = 96
+    net = random_network(rng, n, (1, 1), (1, 4), 0.001)
+    for i in (int(v) for v in rng.choice(n, size=11, replace=False)):
+        cs = rng.dirichlet(np.ones(2))
+        k = int(rng.integers(1, 5))
+        parents = tuple(int(v) for v in rng.choice(n, size=k, replace=False))
+        bits = rng.integers(0, 2, size=1 << k)
+        tt = sum(1 << idx for idx in range(1 << k) if bits[idx])
+        first = net.nodes[i][0]
+        net.nodes[i] = [Function(c=float(cs[0]), parents=first.parents, tt=first.tt),
+                        Function(c=float(cs[1]), parents=parents, tt=tt)]
+    # target: a node one of whose functions reads three other nodes
+    target, par = None, None
+    for i in (int(v) for v in rng.permutation(n)):
+        for f in net.nodes[i]:
+            others = [v for v in f.parents if v != i]
+            if len(others) >= 3:
+                target, par = i, others[:3]
+                break
+        if target is not None:
+            break
+    assert target is not None
+    pats: List[Pattern] = [((target, 1),)]
+    for v in par:
+        pats.append(((target, 1), (v, 1)))
+        pats.append(((target, 1), (v, 0)))
+    return Job("multiprop", net, chains, SIM_SEED + 5, pats, r, 0.95, 1.1)
+
+
 def small_network(seed: int, n: int, l_max: int = 3, k_max: int = 3, p: float = 0.01,
                   fixed_l: int | None = None) -> Network:
     """Small random networks for exhaustive tests (n <= 12)."""

@@ -326,6 +326,23 @@ def test_multi_property_equals_solo():
     assert sim.position()[0] == max(w["chain_len"] for w in want)
 
 
+def test_multiprop_equals_oracle_and_solo():
+    """The multi-property shape (96 nodes, 7 state sets): the simultaneous GPU
+    estimate equals the oracle's, and each property equals its solo GPU run."""
+    job = ps.multiprop(chains=256, r=1e-2)
+    text = ps.to_text(job.net)
+    say("multiprop: 96 nodes, 7 state sets, 256 chains")
+    sim = pkg.Simulation(pkg.Network(text), job.chains, job.seed, max_props=7, max_len=CAP)
+    got = sim.estimate(job.patterns, job.r, job.confidence, psrf_max=job.psrf_max)
+    want = drivers.solve(text, job.chains, job.seed, job.patterns, job.r, job.confidence, job.psrf_max, cap=CAP)
+    for q in range(7):
+        assert_same_result(got[q], want[q], q)
+    for q in (0, 4):
+        solo = pkg.Simulation(pkg.Network(text), job.chains, job.seed, max_props=1, max_len=CAP)
+        one = solo.estimate([job.patterns[q]], job.r, job.confidence, psrf_max=job.psrf_max)
+        assert_same_result(one[0], got[q], ("solo", q))
+
+
 def test_batched_equals_oracle():
     jobs = sorted(ps.batched(), key=lambda j: j.net.n * j.chains)[:10]
     say("batched estimate of {} networks".format(len(jobs)))
