@@ -230,6 +230,58 @@ def multiprop_workload(pkg, torch, steps: int, warmup: int, cpu_s: float, no_cpu
     }
 
 
+R_SEQ = 2e-3      # the paper's 1e-4 would take minutes for one chain
+SEQ_LEN = 1 << 22  # positions of the one sequential chain
+
+
+def sequential_workload(pkg, torch, cpu_s: float, no_cpu: bool) -> dict:
+    """The paper's sequential-versus-parallel comparison (Sec. 5.2): for each
+    network, Alg. 1 on one chain against Alg. 3 on the configuration's chains,
+    both on the GPU.  Reports t_sequential/t_parallel, the speed-up corrected for
+    the sample sizes (sp * size_p / size_s), and the paired agreement
+    |p_seq - p_par| < 2r of the paper's check; optionally the oracle's Alg. 1 on
+    one host thread (the paper's sequential baseline runs on one core)."""
+    import oracle
+    from oracle import drivers
+    batched = ps.batched(512)
+    jobs = [ps.medium()] + [min(batched, key=lambda j: abs(j.net.n - target)) for target in (200, 1000)]
+    rows = []
+    for job in jobs:
+        net = pkg.Network(ps.to_text(job.net))
+        pat = job.patterns[:1]
+        job.r = R_SEQ
+
+        def timed(omega, method):
+            sim = pkg.Simulation(net, omega, job.seed, max_props=1, max_len=MAX_LEN if omega > 1 else SEQ_LEN)
+            sim.estimate(pat, job.r, job.confidence, method=method, psrf_max=job.psrf_max)   # warm-up
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            res = sim.estimate(pat, job.r, job.confidence, method=method, psrf_max=job.psrf_max)[0]
+            torch.cuda.synchronize()
+            return time.perf_counter() - a, res
+
+        t_par, rp = timed(job.chains, "two_state")
+        t_seq, rs = timed(1, "sequential")
+        size_p = job.chains * rp["n"]
+        size_s = rs["N"]
+        sp = t_seq / t_par
+        row = {"n": job.net.n, "chains": job.chains, "r": job.r, "p_parallel": rp["prob"], "p_sequential": rs["prob"],
+               "agree_2r": abs(rp["prob"] - rs["prob"]) < 2 * job.r, "t_parallel_ms": t_par * 1e3,
+               "t_sequential_ms": t_seq * 1e3, "speedup": sp, "speedup_E": sp * size_p / max(size_s, 1),
+               "size_parallel": size_p, "size_sequential": size_s, "status_sequential": rs["status"]}
+        if not no_cpu:
+            a = time.perf_counter()
+            ro = drivers.solve(ps.to_text(job.net), 1, job.seed, pat, job.r, job.confidence, job.psrf_max,
+                               method="sequential", cap=SEQ_LEN, threads=1)[0]
+            row["t_sequential_oracle_1thread_ms"] = (time.perf_counter() - a) * 1e3
+            row["speedup_vs_oracle_sequential"] = row["t_sequential_oracle_1thread_ms"] / row["t_parallel_ms"]
+            row["oracle_identical"] = ro["prob"] == rs["prob"] and ro["N"] == rs["N"]
+        log("n={}: parallel {:.1f} ms, sequential {:.1f} ms".format(job.net.n, t_par * 1e3, t_seq * 1e3))
+        rows.append(row)
+    return {"workload": "sequential (Alg. 1, one chain) vs parallel (Alg. 3) two-state, r={}, s=0.95".format(R_SEQ),
+            "pairs": rows, "all_agree_2r": all(r["agree_2r"] for r in rows)}
+
+
 def roofline_of(prof: dict, total_t: float, batched: bool = True) -> dict:
     launches = max(1, prof["launches"])
     avg_launch_s = prof["kernel_ms"] / launches / 1e3
@@ -298,7 +350,7 @@ def main() -> int:
     ap.add_argument("--waves", type=int, default=0, help="bit-sliced waves per block (0 = by n)")
     ap.add_argument("--tune", action="store_true",
                     help="measure the kernel shapes per network size first (untimed) and use them")
-    ap.add_argument("--workload", default="batched", choices=["batched", "tiny", "medium", "large", "multiprop"],
+    ap.add_argument("--workload", default="batched", choices=["batched", "tiny", "medium", "large", "multiprop", "sequential"],
                     help="batched (default, the headline) or one plain configuration")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter scale)")
     ap.add_argument("--traffic-from", nargs=5, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE", "OUT"),
@@ -328,6 +380,9 @@ def main() -> int:
         for r in tune:
             log("  n={n}: throughput {waves_throughput} waves ({node_updates_per_s:.3e}/s), "
                 "latency {waves_latency} waves ({transition_us:.2f} us)".format(**r))
+    if args.workload == "sequential":
+        print(json.dumps(sequential_workload(pkg, torch, args.cpu_seconds, args.no_cpu)))
+        return 0
     if args.workload == "multiprop":
         print(json.dumps(multiprop_workload(pkg, torch, args.steps, args.warmup, args.cpu_seconds, args.no_cpu)))
         return 0

@@ -216,6 +216,45 @@ def estimate_ci_in_parallel(ch: Chains, q: int, psi0: int, psrf_max: float, H_st
 DEFAULTS = dict(psi0=256, eps=1e-10, cap=1 << 26)
 
 
+def estimate_probability(ch: Chains, q: int, m0: int, n0: int, eps: float, r: float, s: float,
+                         cap: int) -> Dict:
+    """Alg. 1 (the sequential two-state Markov chain approach, Sec. 3.1) for
+    property q on the single chain of ch.  M := m0, N := n0 and a trajectory of
+    length l := M + N; repeatedly extend the trajectory to length M + N (l := M +
+    N), estimate alpha, beta from its last N positions and recompute M and N,
+    until M + N <= l; the estimate is the fraction of ones in the last N
+    positions.  Readings: when alpha or beta is undefined (a meta state never left
+    or never reached in the window) N is doubled (and l grows to M + N if
+    shorter); N is at least 1 (the formula gives 0 for a strictly alternating
+    window, alpha = beta = 1)."""
+    assert ch.omega == 1
+    z = stats.z_of_confidence(s)
+    res = dict(status=OK, psi_gr=0, rhat=math.nan, psi=0, n=0, N=0, M=0, prob=math.nan,
+               ci_lo=math.nan, ci_hi=math.nan, kappa=0, batches=0, chain_len=0)
+    M, N = m0, n0
+    l = M + N
+    while True:
+        if l > cap:
+            res.update(status=NOT_CONVERGED, psi=M, n=N, M=M, chain_len=ch.length)
+            return res
+        ch.extend_to(l)
+        ab = stats.alpha_beta(stats.transition_counts(ch.bits[q][:, l - N: l]))
+        if ab is None:
+            N *= 2
+            l = max(l, M + N)
+            continue
+        a, b = ab
+        M = stats.burn_in_M(a, b, eps)
+        # a sample of at least one position (N = 0 when alpha = beta = 1)
+        N = max(1, int(math.ceil(stats.sample_size_N(a, b, z, r))))
+        if M + N <= l:
+            break
+        l = M + N
+    win = ch.bits[q][:, l - N: l]
+    res.update(psi=M, n=N, N=N, M=M, prob=float(np.sum(win)) / N, chain_len=l)
+    return res
+
+
 def solve(text: str, omega: int, seed: int, patterns, r: float, s: float, psrf_max: float,
           method: str = "two_state", psi0: int = 256, eps: float = 1e-10, cap: int = 1 << 26,
           threads: int | None = None) -> List[Dict]:
@@ -229,6 +268,8 @@ def solve(text: str, omega: int, seed: int, patterns, r: float, s: float, psrf_m
             out.append(estimate_probability_in_parallel(ch, 0, psi0, psrf_max, eps, r, s, cap))
         elif method == "skart":
             out.append(estimate_ci_in_parallel(ch, 0, psi0, psrf_max, r, s, cap))
+        elif method == "sequential":
+            out.append(estimate_probability(ch, 0, psi0, 4 * psi0, eps, r, s, cap))
         else:
             raise ValueError(method)
     return out

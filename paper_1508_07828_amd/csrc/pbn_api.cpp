@@ -299,7 +299,11 @@ int pbn_batch_estimate(pbn_sim *const *sims, uint32_t count, const pbn_pattern *
     for (uint32_t i = 0; i < count; ++i) {
         pbn_sim *s = sims[i];
         if (!s) return fail(PBN_EINVAL, "null simulation");
-        if (s->omega < 2) return fail(PBN_EINVAL, "Gelman-Rubin needs omega >= 2 chains");
+        const bool seq = opts && opts->method == PBN_SEQ_TWO_STATE;
+        if (seq && s->omega != 1) return fail(PBN_EINVAL, "the sequential method (Alg. 1) runs one chain: omega = 1");
+        if (!seq && s->omega < 2) return fail(PBN_EINVAL, "Gelman-Rubin needs omega >= 2 chains");
+        if (opts && (opts->method < PBN_TWO_STATE || opts->method > PBN_SEQ_TWO_STATE))
+            return fail(PBN_EINVAL, "unknown method");
         if (!(r[i] > 0.0) || !(conf[i] > 0.0 && conf[i] < 1.0)) return fail(PBN_EINVAL, "r must be > 0 and s in (0,1)");
         if (nprops[i] < 1 || !valid_patterns(props + prop_off[i], nprops[i])) return fail(PBN_EINVAL, "bad state sets");
         // work already queued on a simulation's own stream finishes first

@@ -293,8 +293,33 @@ Machine::Machine(const MachineParams &p, uint32_t prop) : P_(p), prop_(prop)
     res_.status = PBN_OK;
     z_ = normal_quantile(0.5 * (1.0 + P_.conf));
     psi_ = P_.psi0;
+    if (P_.method == PBN_SEQ_TWO_STATE) {
+        // Alg. 1: M := m0, N := n0, l := M + N, a trajectory of length l
+        st_ = kSeqTwoState;
+        M_ = P_.psi0;
+        N_ = 4 * P_.psi0;
+        l_ = M_ + N_;
+        seq_next(0);
+        return;
+    }
     if (2 * psi_ > P_.cap) not_converged(0);
     else ask_window(psi_, 2 * psi_);
+}
+
+// Alg. 1: the next window is the last N positions of the trajectory of length
+// l (extended to l first when it is shorter).
+void Machine::seq_next(uint64_t chain_len)
+{
+    if (l_ > P_.cap) {
+        res_.status = PBN_ENOTCONV;
+        res_.psi = M_;
+        res_.n = N_;
+        res_.M = M_;
+        res_.chain_len = chain_len;
+        done_ = true;
+        return;
+    }
+    ask_window(l_ - N_, l_);
 }
 
 void Machine::ask_window(uint64_t lo, uint64_t hi)
@@ -402,6 +427,44 @@ void Machine::feed_window(const WindowResult &w, uint64_t chain_len)
         ask_batch();
         return;
     }
+    case kSeqTwoState: {
+        // alpha, beta from the last N positions; undefined (a meta state never
+        // left, or never seen): the sample is doubled
+        const bool undefined = (w.n00 + w.n01 == 0) || (w.n10 + w.n11 == 0);
+        double a = 0.0, b = 0.0;
+        if (!undefined) {
+            a = (double)w.n01 / (double)(w.n00 + w.n01);
+            b = (double)w.n10 / (double)(w.n10 + w.n11);
+        }
+        if (undefined || a + b == 0.0) {
+            N_ *= 2;
+            l_ = std::max(l_, M_ + N_);
+            return seq_next(chain_len);
+        }
+        a_ = a;
+        b_ = b;
+        const double Nf = std::ceil(formula_N(a, b, z_, P_.r));
+        if (!(Nf < 9.0e15)) return not_converged(chain_len);
+        M_ = formula_M(a, b, P_.eps);
+        N_ = std::max<uint64_t>(1, (uint64_t)Nf);     // at least one position (alpha = beta = 1 gives 0)
+        if (M_ + N_ <= l_) {
+            // until M + N <= l: the estimate comes from the last N positions
+            st_ = kSeqFinal;
+            ask_window(l_ - N_, l_);
+            return;
+        }
+        l_ = M_ + N_;
+        return seq_next(chain_len);
+    }
+    case kSeqFinal:
+        res_.psi = M_;
+        res_.M = M_;
+        res_.n = N_;
+        res_.N = N_;
+        res_.prob = (double)w.T1 / (double)N_;
+        res_.chain_len = l_;
+        done_ = true;
+        return;
     default:
         return;
     }

@@ -80,7 +80,7 @@ public:
     const pbn_result &result() const { return res_; }
 
 private:
-    enum State { kGR, kTwoState, kSkartSkew, kSkartRandomness, kSkartCI };
+    enum State { kGR, kTwoState, kSkartSkew, kSkartRandomness, kSkartCI, kSeqTwoState, kSeqFinal };
     void ask_window(uint64_t lo, uint64_t hi);
     void ask_batch();
     void not_converged(uint64_t chain_len);
@@ -99,6 +99,9 @@ private:
     // Skart-P
     uint64_t base_ = 0, kappa_ = 0, p_ = 0;
     int tries_ = 0;
+    // Alg. 1 (one chain): burn-in M, trajectory length l
+    uint64_t M_ = 0, l_ = 0;
+    void seq_next(uint64_t chain_len);
 };
 
 }  // namespace pbn

@@ -283,6 +283,18 @@ def test_estimate_two_state(name):
     assert_same_result(got[0], want[0], name)
 
 
+@pytest.mark.parametrize("case", ["tiny", "medium", "ragged_k6_p05", "ragged_k7_p05", "n300_l4"])
+def test_sequential_equals_oracle(case):
+    """Alg. 1 (the sequential two-state method on one chain) against the oracle."""
+    net, _, pats = CASES[case]()
+    text = ps.to_text(net)
+    say("sequential two-state " + case)
+    sim = pkg.Simulation(pkg.Network(text), 1, 2024, max_props=1, max_len=CAP)
+    got = sim.estimate(pats[:1], 0.02, 0.95, method="sequential")
+    want = drivers.solve(text, 1, 2024, pats[:1], 0.02, 0.95, 1.1, method="sequential", cap=CAP)
+    assert_same_result(got[0], want[0], case)
+
+
 def test_estimate_two_state_seeds_and_reruns():
     # several seeds and a small psi0 so that Alg. 3's burn-in re-run (M > psi) occurs
     job = ps.tiny()

@@ -42,3 +42,17 @@ def test_skart_covers():
         assert max(r["prob"] - r["ci_lo"], r["ci_hi"] - r["prob"]) <= 0.01
         cover += r["ci_lo"] <= truth <= r["ci_hi"]
     assert cover >= 88
+
+
+def test_sequential_within_r():
+    """Alg. 1 (one chain): within r of the exact pi at the binomial-bound rate,
+    and its stop rule M + N <= l holds at the end."""
+    j, txt, truth = _truth()
+    hits = 0
+    for k in range(200):
+        r = drivers.solve(txt, 1, 3000 + k, j.patterns, 0.01, 0.95, 1.1, method="sequential", threads=1)[0]
+        assert r["status"] == 0
+        assert r["M"] + r["N"] <= r["chain_len"]
+        assert r["n"] == r["N"] and r["psi"] == r["M"]
+        hits += abs(r["prob"] - truth) < 0.01
+    assert hits >= 179

@@ -158,3 +158,26 @@ def test_alg3_hand_trace():
     for key in ("psi_gr", "psi", "n", "N", "M", "chain_len"):
         assert res[key] == int(g[key][0]), key
     assert res["prob"] == float(g["prob"][0])
+
+
+class _Alternating:
+    """A one-chain stand-in whose recorded indicator alternates 0, 1, 0, 1, ..."""
+    omega = 1
+
+    def __init__(self):
+        self.length = 0
+        self.bits = [np.zeros((1, 0), dtype=np.uint8)]
+
+    def extend_to(self, l):
+        self.length = max(self.length, l)
+        self.bits = [(np.arange(self.length) % 2).astype(np.uint8)[None, :]]
+
+
+def test_sequential_alternating_window():
+    """Alg. 1 on a strictly alternating indicator: alpha = beta = 1, so the
+    burn-in is 0 (|1 - alpha - beta| = 1) and the formula's sample size is 0,
+    read as one position: the estimate is the last position of the initial
+    trajectory of m0 + n0 = 20 positions (position 20: a one)."""
+    r = drivers.estimate_probability(_Alternating(), 0, 4, 16, 1e-10, 0.01, 0.95, 1 << 20)
+    assert (r["status"], r["M"], r["N"], r["chain_len"], r["prob"]) == (0, 0, 1, 20, 1.0)
+
