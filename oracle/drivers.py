@@ -30,6 +30,20 @@ Readings of the paper (where it is silent or garbled) that this file follows:
     most 10 times); CI = skewness- (Willink) and lag-1 autoregression-adjusted
     t interval on the batch means; if its half-width H exceeds H* the batch size
     grows to ceil(kappa (H/H*)^2).
+  * Alg. 4 (Skart on one chain): an initial trajectory of eta = 1280 positions
+    from position 1; the skewness of its last l = 1024 positions sets the batch
+    size as in Alg. 5; p = 1280 batches of kappa positions from position 1; the
+    randomness test (the von Neumann ratio above, one chain) runs on the spaced
+    batch means, i.e. every (d+1)-th batch, each one preceded by d spacer
+    batches, for d = 0, 1, ..., 10 on the same data, and passes at the first d
+    that passes; when every spacer fails, kappa := ceil(sqrt(2) kappa), p :=
+    ceil(0.9 p) and the spacers are tried again on the longer trajectory (at
+    most 10 such increases; after the last one the spacer stays at 10).  The
+    first zeta = d*kappa positions are then skipped and the CI of Alg. 5 is
+    computed on the p' = p - d nonspaced batches after them; if H exceeds H*
+    the batch size grows to ceil(kappa (H/H*)^2), p' stays, and the skipped
+    part stays d batches long (zeta = d*kappa with the new kappa), so the
+    trajectory has kappa (p' + d) positions.
 """
 from __future__ import annotations
 
@@ -255,6 +269,61 @@ def estimate_probability(ch: Chains, q: int, m0: int, n0: int, eps: float, r: fl
     return res
 
 
+def _spaced_passes(y: np.ndarray, d: int) -> bool:
+    """Randomness test on the spaced batch means of one chain: batches
+    d, 2d+1, 3d+2, ... (0-based), each preceded by d spacer batches."""
+    return von_neumann_passes(y[d::d + 1].reshape(1, -1))
+
+
+def estimate_ci(ch: Chains, q: int, H_star: float, s: float, cap: int) -> Dict:
+    """Alg. 4 (the sequential Skart method, Sec. 3.2) for property q on the
+    single chain of ch; the readings are listed in the module docstring."""
+    assert ch.omega == 1
+    alpha = 1.0 - s
+    res = dict(status=OK, psi_gr=0, rhat=math.nan, psi=0, n=0, N=0, M=0, prob=math.nan,
+               ci_lo=math.nan, ci_hi=math.nan, kappa=0, batches=0, chain_len=0)
+    eta, l = 1280, 1024
+    if eta > cap:
+        res.update(status=NOT_CONVERGED, chain_len=ch.length)
+        return res
+    ch.extend_to(eta)
+    B = stats.skewness(ch.bits[q][0, eta - l: eta])
+    kappa = 16 if abs(B) > 4.0 else 1
+    p = eta
+    grows = 0
+    while True:
+        if kappa * p > cap:
+            res.update(status=NOT_CONVERGED, chain_len=ch.length)
+            return res
+        y = _batch_means(ch, q, 0, kappa, p)[0]
+        d = next((d for d in range(11) if _spaced_passes(y, d)), None)
+        if d is not None:
+            break
+        if grows == 10:
+            d = 10
+            break
+        kappa = int(math.ceil(math.sqrt(2.0) * kappa))
+        p = int(math.ceil(0.9 * p))
+        grows += 1
+    pp = p - d
+    while True:
+        zeta = d * kappa
+        if zeta + kappa * pp > cap:
+            res.update(status=NOT_CONVERGED, chain_len=ch.length)
+            return res
+        Y = _batch_means(ch, q, zeta, kappa, pp)
+        mu, lo, hi = adjusted_ci(Y, alpha)
+        H = max(mu - lo, hi - mu)
+        if H > H_star:
+            ratio = H / H_star
+            kappa = int(math.ceil(kappa * (ratio * ratio)))
+            continue
+        break
+    n = kappa * pp
+    res.update(prob=mu, ci_lo=lo, ci_hi=hi, kappa=kappa, batches=pp, psi=zeta, n=n, chain_len=zeta + n)
+    return res
+
+
 def solve(text: str, omega: int, seed: int, patterns, r: float, s: float, psrf_max: float,
           method: str = "two_state", psi0: int = 256, eps: float = 1e-10, cap: int = 1 << 26,
           threads: int | None = None) -> List[Dict]:
@@ -270,6 +339,8 @@ def solve(text: str, omega: int, seed: int, patterns, r: float, s: float, psrf_m
             out.append(estimate_ci_in_parallel(ch, 0, psi0, psrf_max, r, s, cap))
         elif method == "sequential":
             out.append(estimate_probability(ch, 0, psi0, 4 * psi0, eps, r, s, cap))
+        elif method == "sequential_skart":
+            out.append(estimate_ci(ch, 0, r, s, cap))
         else:
             raise ValueError(method)
     return out

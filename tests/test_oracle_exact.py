@@ -56,3 +56,20 @@ def test_sequential_within_r():
         assert r["n"] == r["N"] and r["psi"] == r["M"]
         hits += abs(r["prob"] - truth) < 0.01
     assert hits >= 179
+
+
+def test_sequential_skart_covers():
+    """Alg. 4 (one chain, H* = 0.01, 95%): the CI covers the exact value at the
+    binomial-bound rate, its half-width meets H*, and the skipped warm-up is a
+    whole number of batches."""
+    j, txt, truth = _truth()
+    cover = 0
+    for k in range(100):
+        r = drivers.solve(txt, 1, 7000 + k, j.patterns, 0.01, 0.95, 1.1, method="sequential_skart",
+                          threads=1)[0]
+        assert r["status"] == 0
+        assert max(r["prob"] - r["ci_lo"], r["ci_hi"] - r["prob"]) <= 0.01
+        assert r["psi"] % r["kappa"] == 0 and r["psi"] // r["kappa"] <= 10
+        assert r["chain_len"] == r["psi"] + r["kappa"] * r["batches"]
+        cover += r["ci_lo"] <= truth <= r["ci_hi"]
+    assert cover >= 88

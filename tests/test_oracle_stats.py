@@ -181,3 +181,68 @@ def test_sequential_alternating_window():
     r = drivers.estimate_probability(_Alternating(), 0, 4, 16, 1e-10, 0.01, 0.95, 1 << 20)
     assert (r["status"], r["M"], r["N"], r["chain_len"], r["prob"]) == (0, 0, 1, 20, 1.0)
 
+
+
+class _Pattern:
+    """A one-chain stand-in whose recorded indicator at 0-based position i is f(i)."""
+    omega = 1
+
+    def __init__(self, f):
+        self.f = f
+        self.length = 0
+        self.bits = [np.zeros((1, 0), dtype=np.uint8)]
+
+    def extend_to(self, l):
+        self.length = max(self.length, l)
+        self.bits = [np.array([self.f(i) for i in range(self.length)], dtype=np.uint8)[None, :]]
+
+
+def test_sequential_skart_spacer_skips_warm_up():
+    """Alg. 4 on the indicator 000111000111...: the adjacent batch means (kappa
+    = 1: the skewness of a half-ones window is near 0) are strongly correlated,
+    so the test fails without a spacer; with one spacer batch the tested means
+    are x1, x3, x5, ... = 0,1,1,0,1,1,... (negatively correlated), which passes.
+    The first zeta = 1 position is skipped and the estimate is the mean of
+    positions 2..1280 (1-based): 213 whole periods of 6 minus the leading zero
+    at position 1, i.e. 639 ones out of 1279."""
+    r = drivers.estimate_ci(_Pattern(lambda i: (i // 3) % 2), 0, 0.1, 0.95, 1 << 20)
+    assert (r["status"], r["kappa"], r["psi"], r["batches"], r["chain_len"]) == (0, 1, 1, 1279, 1280)
+    assert r["prob"] == 639 / 1279
+    assert r["ci_lo"] < r["prob"] < r["ci_hi"]
+
+
+def test_sequential_skart_reduces_to_t_interval():
+    """Alg. 4 on the alternating indicator 0101...: kappa = 1 (skewness 0), no
+    spacer (lag-1 correlation -1 passes), lag-1 correlation <= 0 gives A = 1 and
+    640 ones out of 1280 give zero skewness, so the CI is the textbook Student
+    t interval on 1280 observations."""
+    t = sst.t.ppf(0.975, 1279)
+    half = t * math.sqrt((320.0 / 1279.0) / 1280.0)
+    r = drivers.estimate_ci(_Pattern(lambda i: i % 2), 0, 0.1, 0.95, 1 << 20)
+    assert (r["status"], r["kappa"], r["psi"], r["batches"], r["chain_len"]) == (0, 1, 0, 1280, 1280)
+    assert r["prob"] == 0.5
+    assert abs(r["ci_lo"] - (0.5 - half)) < 1e-12 and abs(r["ci_hi"] - (0.5 + half)) < 1e-12
+
+
+def test_sequential_skart_batch_growth():
+    """The same indicator with H* = 0.01: the t half-width above (about 0.0274)
+    exceeds H*, so kappa grows to ceil((H/H*)^2) = 8; batches of 8 alternating
+    positions all have mean 1/2, the CI collapses to a point and the procedure
+    ends with 1280 batches of 8 (10240 positions)."""
+    t = sst.t.ppf(0.975, 1279)
+    H = t * math.sqrt((320.0 / 1279.0) / 1280.0)
+    assert math.ceil((H / 0.01) ** 2) == 8
+    r = drivers.estimate_ci(_Pattern(lambda i: i % 2), 0, 0.01, 0.95, 1 << 20)
+    assert (r["status"], r["kappa"], r["psi"], r["batches"], r["chain_len"]) == (0, 8, 0, 1280, 10240)
+    assert (r["prob"], r["ci_lo"], r["ci_hi"]) == (0.5, 0.5, 0.5)
+
+
+def test_sequential_skart_constant_and_cap():
+    """An indicator that is always 1 has unbounded skewness (kappa = 16) and
+    equal batch means (the randomness test passes, the CI is a point at 1);
+    with a cap below 16*1280 positions it does not converge."""
+    r = drivers.estimate_ci(_Pattern(lambda i: 1), 0, 0.01, 0.95, 1 << 20)
+    assert (r["status"], r["kappa"], r["psi"], r["batches"], r["chain_len"]) == (0, 16, 0, 1280, 20480)
+    assert (r["prob"], r["ci_lo"], r["ci_hi"]) == (1.0, 1.0, 1.0)
+    r = drivers.estimate_ci(_Pattern(lambda i: 1), 0, 0.01, 0.95, 20479)
+    assert r["status"] == drivers.NOT_CONVERGED
