@@ -236,12 +236,13 @@ SEQ_LEN = 1 << 22  # positions of the one sequential chain
 
 def sequential_workload(pkg, torch, cpu_s: float, no_cpu: bool) -> dict:
     """The paper's sequential-versus-parallel comparison (Sec. 5.2): for each
-    network, Alg. 1 on one chain against Alg. 3 on the configuration's chains,
-    both on the GPU.  Reports t_sequential/t_parallel, the speed-up corrected for
-    the sample sizes (sp * size_p / size_s), and the paired agreement
-    |p_seq - p_par| < 2r of the paper's check; optionally the oracle's Alg. 1 on
-    one host thread (the paper's sequential baseline runs on one core)."""
-    import oracle
+    network, the sequential method on one chain against the parallel method on
+    the configuration's chains, both on the GPU, for the two-state pair (Alg. 1
+    against Alg. 3) and the Skart pair (Alg. 4 against Alg. 5).  Reports
+    t_sequential/t_parallel, the speed-up corrected for the sample sizes (sp *
+    size_p / size_s), and the paired agreement |p_seq - p_par| < 2r of the
+    paper's check; optionally the oracle's sequential method on one host thread
+    (the paper's sequential baseline runs on one core)."""
     from oracle import drivers
     batched = ps.batched(512)
     jobs = [ps.medium()] + [min(batched, key=lambda j: abs(j.net.n - target)) for target in (200, 1000)]
@@ -260,25 +261,33 @@ def sequential_workload(pkg, torch, cpu_s: float, no_cpu: bool) -> dict:
             torch.cuda.synchronize()
             return time.perf_counter() - a, res
 
-        t_par, rp = timed(job.chains, "two_state")
-        t_seq, rs = timed(1, "sequential")
-        size_p = job.chains * rp["n"]
-        size_s = rs["N"]
-        sp = t_seq / t_par
-        row = {"n": job.net.n, "chains": job.chains, "r": job.r, "p_parallel": rp["prob"], "p_sequential": rs["prob"],
-               "agree_2r": abs(rp["prob"] - rs["prob"]) < 2 * job.r, "t_parallel_ms": t_par * 1e3,
-               "t_sequential_ms": t_seq * 1e3, "speedup": sp, "speedup_E": sp * size_p / max(size_s, 1),
-               "size_parallel": size_p, "size_sequential": size_s, "status_sequential": rs["status"]}
-        if not no_cpu:
-            a = time.perf_counter()
-            ro = drivers.solve(ps.to_text(job.net), 1, job.seed, pat, job.r, job.confidence, job.psrf_max,
-                               method="sequential", cap=SEQ_LEN, threads=1)[0]
-            row["t_sequential_oracle_1thread_ms"] = (time.perf_counter() - a) * 1e3
-            row["speedup_vs_oracle_sequential"] = row["t_sequential_oracle_1thread_ms"] / row["t_parallel_ms"]
-            row["oracle_identical"] = ro["prob"] == rs["prob"] and ro["N"] == rs["N"]
-        log("n={}: parallel {:.1f} ms, sequential {:.1f} ms".format(job.net.n, t_par * 1e3, t_seq * 1e3))
-        rows.append(row)
-    return {"workload": "sequential (Alg. 1, one chain) vs parallel (Alg. 3) two-state, r={}, s=0.95".format(R_SEQ),
+        for par, seq in (("two_state", "sequential"), ("skart", "sequential_skart")):
+            t_par, rp = timed(job.chains, par)
+            t_seq, rs = timed(1, seq)
+            # sample sizes without burn-in: omega n for the parallel methods,
+            # N (Alg. 1) or the CI batches' positions (Alg. 4) for the sequential ones
+            size_p = job.chains * rp["n"]
+            size_s = rs["N"] if seq == "sequential" else rs["n"]
+            sp = t_seq / t_par
+            row = {"method": par, "n": job.net.n, "chains": job.chains, "r": job.r,
+                   "p_parallel": rp["prob"], "p_sequential": rs["prob"],
+                   "agree_2r": abs(rp["prob"] - rs["prob"]) < 2 * job.r, "t_parallel_ms": t_par * 1e3,
+                   "t_sequential_ms": t_seq * 1e3, "speedup": sp, "speedup_E": sp * size_p / max(size_s, 1),
+                   "size_parallel": size_p, "size_sequential": size_s,
+                   "status_parallel": rp["status"], "status_sequential": rs["status"]}
+            if not no_cpu:
+                a = time.perf_counter()
+                ro = drivers.solve(ps.to_text(job.net), 1, job.seed, pat, job.r, job.confidence, job.psrf_max,
+                                   method=seq, cap=SEQ_LEN, threads=1)[0]
+                row["t_sequential_oracle_1thread_ms"] = (time.perf_counter() - a) * 1e3
+                row["speedup_vs_oracle_sequential"] = row["t_sequential_oracle_1thread_ms"] / row["t_parallel_ms"]
+                # integers identical; the Skart mean sums batch means in another order (1e-12 relative)
+                row["oracle_identical"] = (abs(ro["prob"] - rs["prob"]) <= 1e-12 * max(1.0, abs(ro["prob"]))
+                                           and ro["n"] == rs["n"] and ro["chain_len"] == rs["chain_len"])
+            log("n={} {}: parallel {:.1f} ms, sequential {:.1f} ms".format(job.net.n, par, t_par * 1e3, t_seq * 1e3))
+            rows.append(row)
+    return {"workload": "sequential (one chain: Alg. 1, Alg. 4) vs parallel (Alg. 3, Alg. 5), r={}, s=0.95".format(
+                R_SEQ),
             "pairs": rows, "all_agree_2r": all(r["agree_2r"] for r in rows)}
 
 

@@ -52,7 +52,7 @@ enum {
     PBN_ELIMIT = 6      /* a structural limit was exceeded (see the limits below)     */
 };
 
-enum { PBN_TWO_STATE = 0, PBN_SKART = 1, PBN_SEQ_TWO_STATE = 2 };
+enum { PBN_TWO_STATE = 0, PBN_SKART = 1, PBN_SEQ_TWO_STATE = 2, PBN_SEQ_SKART = 3 };
 
 /* Limits: n <= 65535 nodes, l(i) <= 64 functions per node, k <= 16 parents per
  * function, at most PBN_MAX_PROPS state sets per simulation and
@@ -77,10 +77,15 @@ typedef struct {
 } pbn_pattern;
 
 typedef struct {
-    int method;                   /* PBN_TWO_STATE (Alg. 3), PBN_SKART (Alg. 5), or
+    int method;                   /* PBN_TWO_STATE (Alg. 3), PBN_SKART (Alg. 5),
                                      PBN_SEQ_TWO_STATE (Alg. 1: the sequential two-state
                                      method on a single chain, omega = 1; initial burn-in
-                                     m0 = psi0 and sample n0 = 4 psi0, no Gelman-Rubin)  */
+                                     m0 = psi0 and sample n0 = 4 psi0, no Gelman-Rubin), or
+                                     PBN_SEQ_SKART (Alg. 4: the sequential Skart method on
+                                     a single chain, omega = 1: 1280 initial positions,
+                                     spaced randomness test with up to 10 spacer batches,
+                                     the spacer batches skipped as warm-up, no
+                                     Gelman-Rubin; psi0 and psrf_max are unused)          */
     uint64_t psi0;                /* initial Gelman-Rubin psi (Alg. 2); 0 -> 256          */
     double psrf_max;              /* "close to 1": converged when R < psrf_max; 0 -> 1.1  */
     double eps;                   /* Alg. 1's epsilon for M; 0 -> 1e-10                   */

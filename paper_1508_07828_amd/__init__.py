@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpbnssa.so")
 
 PBN_OK, PBN_EINVAL, PBN_EFORMAT, PBN_ENOMEM, PBN_EDEVICE, PBN_ENOTCONV, PBN_ELIMIT = range(7)
-TWO_STATE, SKART, SEQ_TWO_STATE = 0, 1, 2
+TWO_STATE, SKART, SEQ_TWO_STATE, SEQ_SKART = 0, 1, 2, 3
 MAX_PROPS = 8
 
 EXPORTS = (
@@ -221,7 +221,8 @@ class _Patterns:
 
 def make_opts(method: str = "two_state", psi0: int = 256, psrf_max: float = 1.1, eps: float = 1e-10,
               max_len: int = 0) -> Opts:
-    code = {"two_state": TWO_STATE, "skart": SKART, "sequential": SEQ_TWO_STATE}[method]
+    code = {"two_state": TWO_STATE, "skart": SKART, "sequential": SEQ_TWO_STATE,
+            "sequential_skart": SEQ_SKART}[method]
     return Opts(code, psi0, psrf_max, eps, max_len)
 
 

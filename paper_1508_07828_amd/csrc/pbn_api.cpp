@@ -299,11 +299,12 @@ int pbn_batch_estimate(pbn_sim *const *sims, uint32_t count, const pbn_pattern *
     for (uint32_t i = 0; i < count; ++i) {
         pbn_sim *s = sims[i];
         if (!s) return fail(PBN_EINVAL, "null simulation");
-        const bool seq = opts && opts->method == PBN_SEQ_TWO_STATE;
-        if (seq && s->omega != 1) return fail(PBN_EINVAL, "the sequential method (Alg. 1) runs one chain: omega = 1");
-        if (!seq && s->omega < 2) return fail(PBN_EINVAL, "Gelman-Rubin needs omega >= 2 chains");
-        if (opts && (opts->method < PBN_TWO_STATE || opts->method > PBN_SEQ_TWO_STATE))
+        if (opts && (opts->method < PBN_TWO_STATE || opts->method > PBN_SEQ_SKART))
             return fail(PBN_EINVAL, "unknown method");
+        const bool seq = opts && (opts->method == PBN_SEQ_TWO_STATE || opts->method == PBN_SEQ_SKART);
+        if (seq && s->omega != 1)
+            return fail(PBN_EINVAL, "the sequential methods (Alg. 1, Alg. 4) run one chain: omega = 1");
+        if (!seq && s->omega < 2) return fail(PBN_EINVAL, "Gelman-Rubin needs omega >= 2 chains");
         if (!(r[i] > 0.0) || !(conf[i] > 0.0 && conf[i] < 1.0)) return fail(PBN_EINVAL, "r must be > 0 and s in (0,1)");
         if (nprops[i] < 1 || !valid_patterns(props + prop_off[i], nprops[i])) return fail(PBN_EINVAL, "bad state sets");
         // work already queued on a simulation's own stream finishes first
@@ -436,6 +437,8 @@ int pbn_server_submit(pbn_server *srv, const pbn_net *net, uint32_t omega, uint6
     if (!srv || !net || !id || nprops < 1 || nprops > PBN_MAX_PROPS || !valid_patterns(props, nprops))
         return fail(PBN_EINVAL, "bad argument");
     if (omega < 2 || !(r > 0.0) || !(confidence > 0.0 && confidence < 1.0)) return fail(PBN_EINVAL, "bad parameters");
+    if (opts && opts->method != PBN_TWO_STATE && opts->method != PBN_SKART)
+        return fail(PBN_EINVAL, "the server runs the parallel methods (Alg. 3, Alg. 5)");
     auto rq = std::make_unique<ServeReq>();
     rq->id = srv->next_id++;
     rq->net = net->net;

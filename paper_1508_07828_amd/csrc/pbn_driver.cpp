@@ -283,6 +283,15 @@ bool randomness_passes(const int32_t *bsum, uint32_t omega, uint64_t m, uint64_t
     return C <= normal_quantile(1.0 - 0.2) * std::sqrt(1.0 / npairs);
 }
 
+// Alg. 4's randomness test on one chain's spaced batch means: batches d, 2d+1,
+// 3d+2, ... (0-based), each one preceded by d spacer batches.
+bool spaced_randomness_passes(const int32_t *bsum, uint64_t p, uint64_t d, uint64_t kappa)
+{
+    std::vector<int32_t> sel;
+    for (uint64_t b = d; b < p; b += d + 1) sel.push_back(bsum[b]);
+    return randomness_passes(sel.data(), 1, sel.size(), kappa);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ machine
@@ -300,6 +309,15 @@ Machine::Machine(const MachineParams &p, uint32_t prop) : P_(p), prop_(prop)
         N_ = 4 * P_.psi0;
         l_ = M_ + N_;
         seq_next(0);
+        return;
+    }
+    if (P_.method == PBN_SEQ_SKART) {
+        // Alg. 4: an initial trajectory of eta = 1280 positions; the skewness
+        // of its last l = 1024 sets the batch size
+        st_ = kSeqSkartSkew;
+        psi_ = 0;
+        if (kSeqSkartEta > P_.cap) not_converged(0);
+        else ask_window(kSeqSkartEta - kSeqSkartTail, kSeqSkartEta);
         return;
     }
     if (2 * psi_ > P_.cap) not_converged(0);
@@ -427,6 +445,24 @@ void Machine::feed_window(const WindowResult &w, uint64_t chain_len)
         ask_batch();
         return;
     }
+    case kSeqSkartSkew: {
+        bool big;
+        if (w.T1 == 0 || (uint64_t)w.T1 == kSeqSkartTail) {
+            big = true;                          // zero variance: skewness unbounded
+        } else {
+            const double q = (double)w.T1 / (double)kSeqSkartTail;
+            const double B = (1.0 - 2.0 * q) / std::sqrt(q * (1.0 - q));
+            big = std::fabs(B) > 4.0;
+        }
+        kappa_ = big ? 16 : 1;
+        p_ = kSeqSkartEta;
+        base_ = 0;
+        tries_ = 0;
+        st_ = kSeqSkartRandomness;
+        if (kappa_ * p_ > P_.cap) return not_converged(chain_len);
+        ask_batch();
+        return;
+    }
     case kSeqTwoState: {
         // alpha, beta from the last N positions; undefined (a meta state never
         // left, or never seen): the sample is doubled
@@ -487,6 +523,27 @@ void Machine::feed_batch(const int32_t *bsum, uint64_t chain_len)
         ask_batch();
         return;
     }
+    if (st_ == kSeqSkartRandomness) {
+        // spacers d = 0..10 on the same batch means; when all fail, longer
+        // batches (at most 10 times, then the spacer stays at 10)
+        uint64_t d = 0;
+        while (d <= kSeqSkartMaxSpacer && !spaced_randomness_passes(bsum, p_, d, kappa_)) ++d;
+        if (d > kSeqSkartMaxSpacer && tries_ >= 10) d = kSeqSkartMaxSpacer;
+        if (d <= kSeqSkartMaxSpacer) {
+            // skip zeta = d kappa positions: the CI uses the p' = p - d batches after them
+            d_ = d;
+            base_ = d_ * kappa_;
+            p_ -= d_;
+            st_ = kSkartCI;
+            return skart_ci(bsum + d_, chain_len);
+        }
+        kappa_ = (uint64_t)std::ceil(std::sqrt(2.0) * (double)kappa_);
+        p_ = (uint64_t)std::ceil(0.9 * (double)p_);
+        ++tries_;
+        if (kappa_ * p_ > P_.cap) return not_converged(chain_len);
+        ask_batch();
+        return;
+    }
     if (st_ == kSkartCI) skart_ci(bsum, chain_len);
 }
 
@@ -527,6 +584,7 @@ void Machine::skart_ci(const int32_t *bsum, uint64_t chain_len)
     if (H > P_.r) {
         const double ratio = H / P_.r;
         kappa_ = (uint64_t)std::ceil((double)kappa_ * (ratio * ratio));
+        if (P_.method == PBN_SEQ_SKART) base_ = d_ * kappa_;   // the skipped part stays d batches
         if (base_ + kappa_ * (p_ / omega) > P_.cap) return not_converged(chain_len);
         ask_batch();
         return;

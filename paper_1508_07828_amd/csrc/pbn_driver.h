@@ -80,7 +80,12 @@ public:
     const pbn_result &result() const { return res_; }
 
 private:
-    enum State { kGR, kTwoState, kSkartSkew, kSkartRandomness, kSkartCI, kSeqTwoState, kSeqFinal };
+    enum State {
+        kGR, kTwoState, kSkartSkew, kSkartRandomness, kSkartCI,
+        kSeqTwoState, kSeqFinal, kSeqSkartSkew, kSeqSkartRandomness
+    };
+    // Alg. 4: initial trajectory, skewness tail, largest spacer (in batches)
+    static constexpr uint64_t kSeqSkartEta = 1280, kSeqSkartTail = 1024, kSeqSkartMaxSpacer = 10;
     void ask_window(uint64_t lo, uint64_t hi);
     void ask_batch();
     void not_converged(uint64_t chain_len);
@@ -96,11 +101,13 @@ private:
     double z_ = 0.0;
     uint64_t psi_ = 0, psi_gr_ = 0, n_ = 0, N_ = 0;
     double a_ = 0.0, b_ = 0.0;
-    // Skart-P
+    // Skart-P and Alg. 4: first batch position, batch size, batch count
     uint64_t base_ = 0, kappa_ = 0, p_ = 0;
     int tries_ = 0;
     // Alg. 1 (one chain): burn-in M, trajectory length l
     uint64_t M_ = 0, l_ = 0;
+    // Alg. 4 (one chain): spacer batches skipped before the CI batches
+    uint64_t d_ = 0;
     void seq_next(uint64_t chain_len);
 };
 

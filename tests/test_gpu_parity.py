@@ -295,6 +295,63 @@ def test_sequential_equals_oracle(case):
     assert_same_result(got[0], want[0], case)
 
 
+@pytest.mark.parametrize("case", ["tiny", "medium", "ragged_k6_p05", "ragged_k7_p05", "n300_l4"])
+def test_sequential_skart_equals_oracle(case):
+    """Alg. 4 (the sequential Skart method on one chain) against the oracle on
+    three seeds: spacers from 0 to 8 batches, batch sizes from 2 to 16, and one
+    run whose batches grow after every spacer failed (ragged_k6_p05, seed 7)."""
+    net, _, pats = CASES[case]()
+    text = ps.to_text(net)
+    nw = pkg.Network(text)
+    for seed in (2024, 7, 99):
+        say("sequential skart {} seed {}".format(case, seed))
+        sim = pkg.Simulation(nw, 1, seed, max_props=1, max_len=CAP)
+        got = sim.estimate(pats[:1], 0.02, 0.95, method="sequential_skart")
+        want = drivers.solve(text, 1, seed, pats[:1], 0.02, 0.95, 1.1, method="sequential_skart", cap=CAP)
+        assert got[0]["status"] == 0
+        assert_same_result(got[0], want[0], (case, seed))
+
+
+@pytest.mark.parametrize("case,cap", [("medium", 16000), ("tiny", 2000)])
+def test_sequential_skart_cap(case, cap):
+    """A cap on the positions ends Alg. 4 as not converged, in the randomness
+    stage (medium: 16 x 1280 positions) and in the CI stage (tiny: the batch
+    size grows past the cap), with the same report as the oracle's."""
+    job = getattr(ps, case)()
+    text = ps.to_text(job.net)
+    say("sequential skart cap {} {}".format(case, cap))
+    sim = pkg.Simulation(pkg.Network(text), 1, 7, max_props=1, max_len=CAP)
+    got = sim.estimate(job.patterns[:1], 0.02, 0.95, method="sequential_skart", max_len=cap)
+    want = drivers.solve(text, 1, 7, job.patterns[:1], 0.02, 0.95, 1.1, method="sequential_skart", cap=cap)
+    assert got[0]["status"] == pkg.PBN_ENOTCONV
+    assert_same_result(got[0], want[0], case)
+
+
+def test_sequential_batched_equals_oracle():
+    """Several one-chain simulations in one batched call, for each sequential
+    method: every result equals the oracle's solo run."""
+    names = ["tiny", "ragged_k7_p05", "n300_l4", "ragged_k6_p05"]
+    nets = [CASES[c]() for c in names]
+    texts = [ps.to_text(net) for net, _, _ in nets]
+    for method in ("sequential", "sequential_skart"):
+        say("batched " + method)
+        sims = [pkg.Simulation(pkg.Network(t), 1, 40 + i, max_props=1, max_len=CAP) for i, t in enumerate(texts)]
+        got = pkg.batch_estimate(sims, [p[:1] for _, _, p in nets], [0.02] * len(sims), [0.95] * len(sims),
+                                 method=method)
+        for i, (t, (_, _, p)) in enumerate(zip(texts, nets)):
+            want = drivers.solve(t, 1, 40 + i, p[:1], 0.02, 0.95, 1.1, method=method, cap=CAP)
+            assert_same_result(got[i][0], want[0], (method, names[i]))
+
+
+def test_server_rejects_sequential_methods():
+    job = ps.tiny()
+    net = pkg.Network(ps.to_text(job.net))
+    srv = pkg.Server(64 << 20)
+    for method in ("sequential", "sequential_skart"):
+        with pytest.raises(pkg.PbnError):
+            srv.submit(net, 8, 1, job.patterns, 0.02, method=method)
+
+
 def test_estimate_two_state_seeds_and_reruns():
     # several seeds and a small psi0 so that Alg. 3's burn-in re-run (M > psi) occurs
     job = ps.tiny()
