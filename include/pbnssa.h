@@ -56,20 +56,24 @@ enum { PBN_TWO_STATE = 0, PBN_SKART = 1, PBN_SEQ_TWO_STATE = 2, PBN_SEQ_SKART = 
 
 /* Limits: n <= 65535 nodes, l(i) <= 64 functions per node, k <= 16 parents per
  * function, at most PBN_MAX_PROPS state sets per simulation and
- * PBN_MAX_TERMS (node, value) terms over all of them, transitions per chain
- * below 2^32.  Every n is simulated: networks whose bit-sliced state does not
+ * PBN_MAX_TERMS (node, value) terms over all of them, at most PBN_MAX_CHAINS
+ * chains per simulation, transitions per chain below 2^32 and recorded
+ * positions per chain (max_len) at most PBN_MAX_LEN.  Every n is simulated: networks whose bit-sliced state does not
  * fit in LDS run the lane-per-chain kernel, whose per-chain state rows move
  * from LDS to library-owned device scratch beyond n = 10240. */
 #define PBN_MAX_PROPS 8
 #define PBN_MAX_TERMS 64
+#define PBN_MAX_CHAINS (1u << 24)
+#define PBN_MAX_LEN 0xFFFFFFFFull
 
 typedef struct pbn_net pbn_net;      /* parsed + compiled network (host memory, library-owned) */
 typedef struct pbn_sim pbn_sim;      /* omega chains of one network on one device buffer      */
 typedef struct pbn_server pbn_server;
 
 /* A set of states of interest (Sec. 3.1: meta state 1): the conjunction
- * node[m] == val[m] over nterms terms (0-based node ids).  Caller-owned;
- * copied by the call that takes it. */
+ * node[m] == val[m] over nterms terms (0-based node ids, val 0 or 1; any other
+ * value is PBN_EINVAL).  No terms: every state; a node asked to be both 0 and
+ * 1: no state.  Caller-owned; copied by the call that takes it. */
 typedef struct {
     uint32_t nterms;
     const uint32_t *node;
@@ -89,7 +93,10 @@ typedef struct {
     uint64_t psi0;                /* initial Gelman-Rubin psi (Alg. 2); 0 -> 256          */
     double psrf_max;              /* "close to 1": converged when R < psrf_max; 0 -> 1.1  */
     double eps;                   /* Alg. 1's epsilon for M; 0 -> 1e-10                   */
-    uint64_t max_len;             /* cap on recorded positions per chain; 0 -> buffer cap */
+    uint64_t max_len;             /* cap on recorded positions per chain; 0 -> buffer cap;
+                                     the Skart methods stop below 2^31 positions (32-bit
+                                     batch sums), and Gelman-Rubin where omega psi^2 would
+                                     exceed its exact 63-bit sum of squares            */
 } pbn_opts;
 
 /* Result per state set.  prob is the estimate (two-state: ones in the final
@@ -136,15 +143,17 @@ int pbn_net_thresholds(const pbn_net *net, uint32_t node, uint32_t *out, uint32_
 /* ------------------------------------------------------------ simulations */
 
 /* Device bytes needed for omega chains, up to max_props state sets and
- * max_len recorded positions per chain (bit-streams, one bit per position). */
+ * max_len recorded positions per chain (bit-streams, one bit per position);
+ * 0 when omega, max_props or max_len is beyond the limits above. */
 size_t pbn_sim_bytes(const pbn_net *net, uint32_t omega, uint32_t max_props, uint64_t max_len);
 
 /* Create a simulation in a caller-owned device buffer (e.g. a torch tensor)
  * of at least pbn_sim_bytes(...) bytes, on the given HIP stream (NULL = the
  * default stream).  Uploads the compiled network and initialises the chains
  * (transition counter 0, no recorded positions, no state sets).  The buffer
- * must outlive the simulation.  Errors: PBN_EINVAL (omega < 1), PBN_ENOMEM
- * (buffer too small), PBN_EDEVICE. */
+ * must outlive the simulation.  Errors: PBN_EINVAL (omega < 1), PBN_ELIMIT
+ * (omega, max_props or max_len beyond the limits), PBN_ENOMEM (buffer too
+ * small), PBN_EDEVICE. */
 int pbn_sim_create(const pbn_net *net, uint32_t omega, uint64_t seed, uint32_t max_props,
                    uint64_t max_len, void *dev_buf, size_t dev_bytes, void *hip_stream,
                    pbn_sim **out);

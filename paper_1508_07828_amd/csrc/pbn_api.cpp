@@ -2,6 +2,7 @@
 // entry points and the serving loop.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -55,11 +56,36 @@ int window_query(pbn_sim *sim, uint32_t prop, uint64_t lo, uint64_t hi, pbn::Win
     return PBN_OK;
 }
 
+// base + count * size <= limit, decided without wrapping around 2^64.
+bool fits(uint64_t base, uint64_t count, uint64_t size, uint64_t limit)
+{
+    if (base > limit) return false;
+    return size == 0 || count <= (limit - base) / size;
+}
+
+// Transition indices of a chain stay below 2^32 (the counter of the random stream).
+constexpr uint64_t kMaxTransition = (1ull << 32) - 1;
+
+// Recorded positions a simulation can still hold.
+uint64_t position_cap(const pbn_sim *sim) { return sim->words_cap * 32 - 32; }
+
+// Each simulation at most once in a batched call (two runs on one simulation
+// would extend the same chains).
+bool distinct(pbn_sim *const *sims, uint32_t count)
+{
+    std::vector<const pbn_sim *> v(sims, sims + count);
+    std::sort(v.begin(), v.end());
+    return std::adjacent_find(v.begin(), v.end()) == v.end();
+}
+
 bool valid_patterns(const pbn_pattern *props, uint32_t nprops)
 {
     if (nprops && !props) return false;
-    for (uint32_t q = 0; q < nprops; ++q)
+    for (uint32_t q = 0; q < nprops; ++q) {
         if (props[q].nterms && (!props[q].node || !props[q].val)) return false;
+        for (uint32_t m = 0; m < props[q].nterms; ++m)
+            if (props[q].val[m] > 1) return false;
+    }
     return true;
 }
 
@@ -142,10 +168,9 @@ int pbn_sim_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops)
 int run_chains(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin)
 {
     if (!sim || thin < 1) return fail(PBN_EINVAL, "bad argument");
-    if (sim->len + steps > sim->words_cap * 32 - 32) return fail(PBN_ELIMIT, "bit-stream capacity exceeded");
-    if (sim->t_done + burn_in + steps * (uint64_t)thin >= (1ull << 32))
+    if (!fits(sim->len, steps, 1, position_cap(sim))) return fail(PBN_ELIMIT, "bit-stream capacity exceeded");
+    if (!fits(sim->t_done, burn_in, 1, kMaxTransition) || !fits(sim->t_done + burn_in, steps, thin, kMaxTransition))
         return fail(PBN_ELIMIT, "transition index limit (2^32)");
-    if (burn_in + steps * (uint64_t)thin >= (1ull << 32)) return fail(PBN_ELIMIT, "too many transitions");
     std::vector<pbn::StepItem> items;
     pbn::sim_extend_items(sim, burn_in, steps, thin, items, pbn::latency_waves(sim) <= pbn::kLatencyWaves);
     std::string err;
@@ -182,7 +207,9 @@ int pbn_window_counts(pbn_sim *sim, uint32_t prop, uint64_t lo, uint64_t hi, pbn
 int pbn_batch_sums(pbn_sim *sim, uint32_t prop, uint64_t base, uint64_t kappa, uint64_t m, int32_t *out)
 {
     if (!sim || !out || kappa < 1 || m < 1) return fail(PBN_EINVAL, "bad argument");
-    if (prop >= sim->nprops || base + kappa * m > sim->len) return fail(PBN_EINVAL, "batches outside the recorded positions");
+    if (prop >= sim->nprops || !fits(base, kappa, m, sim->len))
+        return fail(PBN_EINVAL, "batches outside the recorded positions");
+    if (kappa > INT32_MAX) return fail(PBN_EINVAL, "batch sums are 32-bit: kappa < 2^31");
     std::string err;
     const uint64_t total = (uint64_t)sim->omega * m;
     int rc = sim->ws.ensure(0, 1, total, err);
@@ -223,7 +250,7 @@ int pbn_sim_read_state(pbn_sim *sim, uint32_t *out)
 
 int pbn_sim_read_bits(pbn_sim *sim, uint32_t prop, uint64_t pos0, uint64_t npos, uint8_t *out)
 {
-    if (!sim || !out || prop >= sim->nprops || pos0 + npos > sim->len) return fail(PBN_EINVAL, "bad argument");
+    if (!sim || !out || prop >= sim->nprops || !fits(pos0, npos, 1, sim->len)) return fail(PBN_EINVAL, "bad argument");
     if (npos == 0) return PBN_OK;
     const uint64_t w0 = pos0 / 32, w1 = (pos0 + npos + 31) / 32;
     const size_t words = (size_t)(w1 - w0) * sim->omega;
@@ -266,12 +293,13 @@ int estimate_prob(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops, doubl
 int pbn_batch_run(pbn_sim *const *sims, uint32_t count, const uint64_t *steps, void *hip_stream)
 {
     if (!sims || !steps) return fail(PBN_EINVAL, "null argument");
+    if (!distinct(sims, count)) return fail(PBN_EINVAL, "a simulation appears twice");
     std::vector<pbn::StepItem> items;
     for (uint32_t i = 0; i < count; ++i) {
         pbn_sim *s = sims[i];
         if (!s) return fail(PBN_EINVAL, "null simulation");
-        if (s->len + steps[i] > s->words_cap * 32 - 32) return fail(PBN_ELIMIT, "bit-stream capacity exceeded");
-        if (s->t_done + steps[i] >= (1ull << 32)) return fail(PBN_ELIMIT, "transition index limit (2^32)");
+        if (!fits(s->len, steps[i], 1, position_cap(s))) return fail(PBN_ELIMIT, "bit-stream capacity exceeded");
+        if (!fits(s->t_done, steps[i], 1, kMaxTransition)) return fail(PBN_ELIMIT, "transition index limit (2^32)");
     }
     uint64_t waves = 0;
     for (uint32_t i = 0; i < count; ++i)
@@ -293,6 +321,7 @@ int pbn_batch_estimate(pbn_sim *const *sims, uint32_t count, const pbn_pattern *
                        void *hip_stream, pbn_result *out)
 {
     if (!sims || !nprops || !prop_off || !r || !conf || !out) return fail(PBN_EINVAL, "null argument");
+    if (!distinct(sims, count)) return fail(PBN_EINVAL, "a simulation appears twice");
     std::vector<pbn::SimRun> runs(count);
     std::string err;
     hipStream_t stream = (hipStream_t)hip_stream;
@@ -439,6 +468,7 @@ int pbn_server_submit(pbn_server *srv, const pbn_net *net, uint32_t omega, uint6
     if (omega < 2 || !(r > 0.0) || !(confidence > 0.0 && confidence < 1.0)) return fail(PBN_EINVAL, "bad parameters");
     if (opts && opts->method != PBN_TWO_STATE && opts->method != PBN_SKART)
         return fail(PBN_EINVAL, "the server runs the parallel methods (Alg. 3, Alg. 5)");
+    if (omega > PBN_MAX_CHAINS || max_len > PBN_MAX_LEN) return fail(PBN_ELIMIT, "omega or max_len beyond the limits");
     auto rq = std::make_unique<ServeReq>();
     rq->id = srv->next_id++;
     rq->net = net->net;
@@ -476,7 +506,12 @@ int pbn_server_step(pbn_server *srv, uint32_t *active, uint32_t *waiting, uint32
         std::vector<pbn_pattern> pats(rq->nodes.size());
         for (size_t q = 0; q < pats.size(); ++q) pats[q] = {(uint32_t)rq->nodes[q].size(), rq->nodes[q].data(), rq->vals[q].data()};
         if (!rc) rc = pbn::sim_reset(rq->sim.get(), pats.data(), (uint32_t)pats.size(), srv->stream, err);
-        if (rc) return fail(rc, err);
+        if (rc) {
+            // the request stays queued; its arena block goes back
+            rq->sim.reset();
+            srv->arena.release(off, rq->bytes);
+            return fail(rc, err);
+        }
         rq->run.sim = rq->sim.get();
         const pbn::MachineParams P = pbn::make_params(rq->sim.get(), &rq->opts, rq->r, rq->conf);
         for (uint32_t q = 0; q < pats.size(); ++q) rq->run.machines.emplace_back(P, q);

@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <queue>
 #include <thread>
@@ -320,7 +321,7 @@ Machine::Machine(const MachineParams &p, uint32_t prop) : P_(p), prop_(prop)
         else ask_window(kSeqSkartEta - kSeqSkartTail, kSeqSkartEta);
         return;
     }
-    if (2 * psi_ > P_.cap) not_converged(0);
+    if (!gr_window_fits(psi_)) not_converged(0);
     else ask_window(psi_, 2 * psi_);
 }
 
@@ -338,6 +339,13 @@ void Machine::seq_next(uint64_t chain_len)
         return;
     }
     ask_window(l_ - N_, l_);
+}
+
+// The Gelman-Rubin window [psi, 2 psi) fits under the cap, and its exact sum
+// of squares (omega chains, each at most psi ones) fits in 63 bits.
+bool Machine::gr_window_fits(uint64_t psi) const
+{
+    return 2 * psi <= P_.cap && (double)P_.omega * (double)psi * (double)psi < 9.0e18;
 }
 
 void Machine::ask_window(uint64_t lo, uint64_t hi)
@@ -386,7 +394,7 @@ void Machine::feed_window(const WindowResult &w, uint64_t chain_len)
             }
         } else {
             psi_ *= 2;
-            if (2 * psi_ > P_.cap) return not_converged(chain_len);
+            if (!gr_window_fits(psi_)) return not_converged(chain_len);
             ask_window(psi_, 2 * psi_);
         }
         return;
@@ -618,6 +626,8 @@ size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
 size_t sim_bytes(const Net &net, uint32_t omega, uint32_t max_props, uint64_t max_len)
 {
+    // within these limits the products below stay far from 2^64
+    if (omega > PBN_MAX_CHAINS || max_props > kMaxProps || max_len > PBN_MAX_LEN) return 0;
     const uint64_t words_cap = (max_len + 31) / 32 + 1;
     return a256(sizeof(DevSim)) + a256(net.blob_bytes) + a256((size_t)net.W * omega * 4) +
            a256((size_t)std::max<uint32_t>(max_props, 1) * words_cap * omega * 4);
@@ -628,6 +638,8 @@ int sim_setup(pbn_sim *sim, const Net &net, uint32_t omega, uint64_t seed, uint3
 {
     if (omega < 1) { err = "omega must be >= 1"; return PBN_EINVAL; }
     if (max_props > kMaxProps) { err = "too many state sets"; return PBN_ELIMIT; }
+    if (omega > PBN_MAX_CHAINS) { err = "too many chains"; return PBN_ELIMIT; }
+    if (max_len > PBN_MAX_LEN) { err = "max_len beyond 2^32 - 1 positions"; return PBN_ELIMIT; }
     const size_t need = sim_bytes(net, omega, max_props, max_len);
     if (!dev_buf || dev_bytes < need) { err = "device buffer too small"; return PBN_ENOMEM; }
     sim->net = net;
@@ -686,29 +698,27 @@ int sim_prepare_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops, s
     uint32_t nt = 0;
     d.prop_off[0] = 0;
     for (uint32_t q = 0; q < nprops; ++q) {
-        // group the terms of a conjunction by state word: (word, mask, value)
-        std::vector<std::pair<uint32_t, std::pair<uint32_t, uint32_t>>> words;
+        // group the terms of a conjunction by state word: (s[word] & mask) == value
+        struct WordTerm { uint32_t word, mask, val; bool empty; };
+        std::vector<WordTerm> words;
         for (uint32_t m = 0; m < props[q].nterms; ++m) {
             const uint32_t v = props[q].node[m];
             if (v >= sim->net.n) { err = "state-set node out of range"; return PBN_EINVAL; }
             const uint32_t w = v >> 5, bit = 1u << (v & 31);
-            auto it = std::find_if(words.begin(), words.end(), [&](auto &e) { return e.first == w; });
-            if (it == words.end()) { words.push_back({w, {0u, 0u}}); it = words.end() - 1; }
+            auto it = std::find_if(words.begin(), words.end(), [&](const WordTerm &e) { return e.word == w; });
+            if (it == words.end()) { words.push_back({w, 0u, 0u, false}); it = words.end() - 1; }
             const uint32_t want = props[q].val[m] ? bit : 0u;
-            if ((it->second.first & bit) && ((it->second.second & bit) != want)) {
-                // contradictory terms: the set is empty; encode an impossible test
-                it->second.second |= bit;
-                it->second.first &= ~bit;
-                continue;
-            }
-            it->second.first |= bit;
-            it->second.second |= want;
+            // a node asked to be both 0 and 1 makes the set empty, whatever follows
+            if ((it->mask & bit) && ((it->val & bit) != want)) it->empty = true;
+            it->mask |= bit;
+            it->val |= want & it->mask;
         }
         for (auto &e : words) {
             if (nt >= kMaxTerms) { err = "too many state-set terms"; return PBN_ELIMIT; }
-            d.term_word[nt] = e.first;
-            d.term_mask[nt] = e.second.first;
-            d.term_val[nt] = e.second.second;
+            d.term_word[nt] = e.word;
+            // an empty set: a value bit outside the mask never matches
+            d.term_mask[nt] = e.empty ? 0u : e.mask;
+            d.term_val[nt] = e.empty ? 1u : e.val;
             ++nt;
         }
         d.prop_off[q + 1] = nt;
@@ -1304,6 +1314,8 @@ MachineParams make_params(const pbn_sim *sim, const pbn_opts *opts, double r, do
     p.eps = (opts && opts->eps > 0.0) ? opts->eps : 1e-10;
     uint64_t cap = sim->max_len;
     if (opts && opts->max_len && opts->max_len < cap) cap = opts->max_len;
+    // Skart batch sums are 32-bit: a batch (at most the whole chain) stays below 2^31 positions
+    if (p.method == PBN_SKART || p.method == PBN_SEQ_SKART) cap = std::min<uint64_t>(cap, INT32_MAX);
     p.cap = cap;
     p.r = r;
     p.conf = conf;

@@ -87,6 +87,7 @@ private:
     // Alg. 4: initial trajectory, skewness tail, largest spacer (in batches)
     static constexpr uint64_t kSeqSkartEta = 1280, kSeqSkartTail = 1024, kSeqSkartMaxSpacer = 10;
     void ask_window(uint64_t lo, uint64_t hi);
+    bool gr_window_fits(uint64_t psi) const;
     void ask_batch();
     void not_converged(uint64_t chain_len);
     void finish_two_state(int64_t T1);

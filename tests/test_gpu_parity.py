@@ -97,6 +97,28 @@ def test_trajectories_bit_exact(case, kernel):
     assert sim.position() == (L, L)
 
 
+def test_degenerate_state_sets(kernel):
+    """State sets with repeated and contradictory terms and with no terms: a
+    node asked to be 1 and then 0 twice is the empty set, a repeated term is
+    the term once, no terms is every state; both kernels record the oracle's
+    indicators."""
+    net, omega, _ = CASES["ragged_k6_p05"]()
+    pats = [((0, 1), (0, 0), (0, 0)), ((1, 1), (1, 1)), ((4, 0), (4, 1), (4, 1), (2, 1)),
+            ((3, 1), (35, 0), (3, 1)), ()]
+    text = ps.to_text(net)
+    say("degenerate state sets kernel={}".format(kernel))
+    sim = pkg.Simulation(pkg.Network(text), omega, 5, max_props=len(pats), max_len=1024)
+    sim.reset(pats)
+    sim.run(200)
+    ch = oracle.Chains(oracle.Net(text), omega, 5, pats)
+    ch.extend(200)
+    for q in range(len(pats)):
+        assert np.array_equal(sim.read_bits(q, 0, 200), ch.bits[q]), q
+    assert not ch.bits[0].any() and not ch.bits[2].any() and ch.bits[4].all()
+    with pytest.raises(pkg.PbnError):
+        sim.reset([((0, 2),)])
+
+
 def test_burn_in_and_thinning(kernel):
     net, omega, pats = CASES["ragged_k6_p05"]()
     pats = pats[:2]
@@ -521,3 +543,19 @@ def test_rejects_bad_arguments():
         sim2.window_counts(0, 0, 10)                   # nothing recorded yet
     res = sim2.estimate([((0, 1),)], 1e-4, 0.95, psrf_max=1.1)[0]
     assert res["status"] == pkg.PBN_ENOTCONV           # cap reached before N
+    # sizes whose sums or products wrap around 2^64 are refused on the host
+    big = (1 << 64) - 1
+    for call in (lambda: sim2.run(big, burn_in=1), lambda: sim2.run(2, thin=(1 << 32) - 1),
+                 lambda: pkg.batch_run([sim2], [big]), lambda: sim2.batch_sums(0, 0, 1 << 63, 2),
+                 lambda: sim2.read_bits(0, big, 2),
+                 # one simulation twice in a batched call
+                 lambda: pkg.batch_run([sim2, sim2], [1, 1]),
+                 lambda: pkg.batch_estimate([sim2, sim2], [[((0, 1),)]] * 2, [0.02] * 2, [0.95] * 2)):
+        with pytest.raises(pkg.PbnError):
+            call()
+    with pytest.raises(pkg.PbnError) as e:
+        pkg.Simulation(net, 4, 1, max_props=1, max_len=1 << 32)
+    assert e.value.code == pkg.PBN_ELIMIT
+    with pytest.raises(pkg.PbnError) as e:
+        pkg.Server(64 << 20).submit(net, (1 << 24) + 1, 1, [((0, 1),)], 0.02)
+    assert e.value.code == pkg.PBN_ELIMIT

@@ -89,6 +89,18 @@ def test_limits():
     assert e.value.code == pkg.PBN_ELIMIT
 
 
+def test_sim_bytes_limits():
+    """Simulation sizes beyond the stated limits report 0 bytes instead of a
+    size whose arithmetic wrapped around."""
+    net = pkg.Network(ps.to_text(ps.tiny().net))
+    assert net.sim_bytes(8, 1, 1 << 16) > 0
+    assert net.sim_bytes(1 << 24, 8, 0xFFFFFFFF) > 0
+    assert net.sim_bytes((1 << 24) + 1, 1, 1024) == 0
+    assert net.sim_bytes(8, 9, 1024) == 0
+    assert net.sim_bytes(8, 1, 1 << 32) == 0
+    assert net.sim_bytes(8, 1, (1 << 64) - 1) == 0
+
+
 def test_quantiles_bit_identical():
     rng = np.random.default_rng(3)
     ps_ = list(rng.uniform(1e-12, 1 - 1e-12, 2000)) + [0.975, 0.995, 0.8, 0.5, 1e-300, 0.025]
