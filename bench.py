@@ -291,6 +291,31 @@ def sequential_workload(pkg, torch, cpu_s: float, no_cpu: bool) -> dict:
             "pairs": rows, "all_agree_2r": all(r["agree_2r"] for r in rows)}
 
 
+def isolated_kernel(pkg, torch, jobs, steps: int = 256, chains: int = 65536, target_n: int = 803) -> dict:
+    """The dominant kernel alone on the chip: the batched network nearest
+    target_n nodes with 65536 chains (1024 blocks, every CU busy), extended on
+    one stream, so each launch's event-timed duration is not shared with the
+    other lanes' launches as it is in the batched solve."""
+    job = min(jobs, key=lambda j: abs(j.net.n - target_n))
+    sim = pkg.Simulation(pkg.Network(ps.to_text(job.net)), chains, job.seed, max_props=1, max_len=steps + 64)
+    sim.reset(job.patterns)
+    sim.run(16)
+    sim.sync()
+    pkg.profile_enable(True)
+    pkg.profile_reset()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    sim.run(steps)
+    sim.sync()
+    t = time.perf_counter() - a
+    prof = pkg.profile_read()
+    pkg.profile_enable(False)
+    r = roofline_of(prof, t, batched=False)
+    return {"network_nodes": job.net.n, "chains": chains, "transitions": steps, "kernel": r["kernel"],
+            "launches": r["launches"], "avg_launch_ms": r["avg_launch_ms"], "achieved": r["achieved"],
+            "frac": r["frac"], "node_updates_per_s": r["kernel_node_updates_per_s"]}
+
+
 def roofline_of(prof: dict, total_t: float, batched: bool = True) -> dict:
     launches = max(1, prof["launches"])
     avg_launch_s = prof["kernel_ms"] / launches / 1e3
@@ -356,10 +381,12 @@ def main() -> int:
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-isolated", action="store_true", help="skip the single-network kernel measurement")
     ap.add_argument("--waves", type=int, default=0, help="bit-sliced waves per block (0 = by n)")
     ap.add_argument("--tune", action="store_true",
                     help="measure the kernel shapes per network size first (untimed) and use them")
-    ap.add_argument("--workload", default="batched", choices=["batched", "tiny", "medium", "large", "multiprop", "sequential"],
+    ap.add_argument("--workload", default="batched", choices=["batched", "tiny", "medium", "large", "multiprop", "sequential",
+                                                         "isolated"],
                     help="batched (default, the headline) or one plain configuration")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter scale)")
     ap.add_argument("--traffic-from", nargs=5, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE", "OUT"),
@@ -391,6 +418,9 @@ def main() -> int:
                 "latency {waves_latency} waves ({transition_us:.2f} us)".format(**r))
     if args.workload == "sequential":
         print(json.dumps(sequential_workload(pkg, torch, args.cpu_seconds, args.no_cpu)))
+        return 0
+    if args.workload == "isolated":
+        print(json.dumps(isolated_kernel(pkg, torch, ps.batched(args.count))))
         return 0
     if args.workload == "multiprop":
         print(json.dumps(multiprop_workload(pkg, torch, args.steps, args.warmup, args.cpu_seconds, args.no_cpu)))
@@ -433,6 +463,10 @@ def main() -> int:
     nconv = sum(r[0]["status"] != 0 for r in res)
 
     roofline = roofline_of(prof, total_t)
+    if not args.no_isolated:
+        # the same kernel without the lanes' concurrency (untimed for the bench value)
+        roofline["isolated"] = isolated_kernel(pkg, torch, jobs)
+        log("isolated kernel: {:.3f} of the ALU peak".format(roofline["isolated"]["frac"]))
 
     plain = None
     if not args.no_plain:
