@@ -31,6 +31,13 @@
  *
  * Status codes: every int-returning call returns one of PBN_* below; details
  * of the last error on the calling thread come from pbn_last_error().
+ *
+ * Threads: a handle (network, simulation, server) is used by one thread at a
+ * time; different handles may be used from different threads at once.  The
+ * batched calls share one set of lane streams, so concurrent batched solves
+ * run one after the other.  The node-split form needs the device to itself;
+ * under concurrent calls its parts can give up (PBN_EDEVICE, no hang), so
+ * callers on several threads turn it off with pbn_set_split(1).
  */
 #ifndef PBNSSA_H
 #define PBNSSA_H

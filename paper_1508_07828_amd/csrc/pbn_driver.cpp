@@ -26,10 +26,12 @@
 //   Sec. 4.2  every state set runs its own machine on the shared chains;
 //           the chains grow to the smallest pending requirement.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <queue>
 #include <thread>
 
@@ -807,9 +809,10 @@ void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t t
 // beyond; for latency (the chip holds every block of the work at once) 2, 8
 // or 16 waves, which shortens each transition's critical path.  kernel_mode
 // forces one kernel or wave count (testing and tuning).
+// Process-wide settings, read by launches on any thread.
 namespace {
-int g_kernel_mode = 0;     // 0 auto, 1 lane-per-chain, 2 bit-sliced
-uint32_t g_waves_override = 0;
+std::atomic<int> g_kernel_mode{0};     // 0 auto, 1 lane-per-chain, 2 bit-sliced
+std::atomic<uint32_t> g_waves_override{0};
 }  // namespace
 
 void set_kernel_mode(int mode, uint32_t waves)
@@ -819,8 +822,8 @@ void set_kernel_mode(int mode, uint32_t waves)
 }
 
 namespace {
-uint32_t g_split_mode = 0;
-uint32_t g_split_spins = kSplitSpins;
+std::atomic<uint32_t> g_split_mode{0};
+std::atomic<uint32_t> g_split_spins{kSplitSpins};
 }  // namespace
 
 void set_split_mode(uint32_t parts) { g_split_mode = parts; }
@@ -847,7 +850,8 @@ void choose_kernel(const Net &net, StepItem &it, bool latency)
     it.lds = 0;
     it.small = 0;
     if (g_kernel_mode == 1 || !net.bitsliced) return;
-    uint32_t G = g_waves_override ? g_waves_override : waves_for(net.n, latency);
+    const uint32_t forced = g_waves_override.load();
+    uint32_t G = forced ? forced : waves_for(net.n, latency);
     size_t lds = bs_lds_bytes(net.n, net.msel_total, G);
     // a shape whose LDS does not fit falls back to fewer waves
     while (lds > 160 * 1024 && G > 1 && !g_waves_override) {
@@ -863,11 +867,13 @@ void choose_kernel(const Net &net, StepItem &it, bool latency)
 namespace {
 
 // Streams for concurrent launch groups (default priority, non-blocking).
+// One caller at a time: the fork and join events are shared.
 struct StreamPool {
     static constexpr int kN = 4;
     hipStream_t s[kN] = {};
     hipEvent_t fork = nullptr, join[kN] = {};
     bool ready = false;
+    std::mutex mu;
     int init(std::string &err)
     {
         if (ready) return PBN_OK;
@@ -944,7 +950,7 @@ int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, 
             const StepItem &it = items[i];
             if (it.kernel == 0 || !it.owner || it.nchains == 0) continue;
             const uint32_t nblk = ((const pbn_sim *)it.owner)->net.nblk;
-            if (g_split_mode >= 2) parts[i] = std::min(std::min(g_split_mode, kSplitMaxParts), nblk);
+            if (g_split_mode >= 2) parts[i] = std::min(std::min(g_split_mode.load(), kSplitMaxParts), nblk);
             else cand.push_back(i);
         }
         bool hinted = false;
@@ -1197,6 +1203,7 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
         // largest groups first, spread over the pool's streams, joined back
         std::sort(groups.begin(), groups.end(), [](const Group &a, const Group &b) { return a.cost > b.cost; });
         StreamPool &P = stream_pool();
+        std::lock_guard<std::mutex> hold(P.mu);
         if ((rc = P.init(err))) return rc;
         if (hipEventRecord(P.fork, stream) != hipSuccess) { err = "fork event"; return PBN_EDEVICE; }
         const int used = std::min<int>(StreamPool::kN, (int)groups.size());
@@ -1225,7 +1232,8 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
 
 namespace {
 struct ProfState {
-    bool on = false;
+    std::mutex mu;                    // launches on several threads record marks
+    std::atomic<bool> on{false};
     std::vector<ProfileMark> pending;
     std::vector<hipEvent_t> pool;
     pbn_profile acc{};
@@ -1238,6 +1246,7 @@ ProfState &prof()
 hipEvent_t get_event()
 {
     ProfState &p = prof();
+    std::lock_guard<std::mutex> hold(p.mu);
     if (!p.pool.empty()) {
         hipEvent_t e = p.pool.back();
         p.pool.pop_back();
@@ -1261,12 +1270,15 @@ void profile_begin(ProfileMark &m, hipStream_t stream)
 void profile_end(ProfileMark &m, hipStream_t stream)
 {
     (void)hipEventRecord(m.stop, stream);
-    prof().pending.push_back(m);
+    ProfState &p = prof();
+    std::lock_guard<std::mutex> hold(p.mu);
+    p.pending.push_back(m);
 }
 
 int profile_collect(pbn_profile *out, std::string &err)
 {
     ProfState &p = prof();
+    std::lock_guard<std::mutex> hold(p.mu);
     for (ProfileMark &m : p.pending) {
         if (hipEventSynchronize(m.stop) != hipSuccess) { err = "profile event"; return PBN_EDEVICE; }
         float ms = 0.0f;
@@ -1292,7 +1304,9 @@ void profile_clear()
 {
     std::string err;
     profile_collect(nullptr, err);
-    prof().acc = pbn_profile{};
+    ProfState &p = prof();
+    std::lock_guard<std::mutex> hold(p.mu);
+    p.acc = pbn_profile{};
 }
 
 // ------------------------------------------------------------ rounds
@@ -1376,7 +1390,7 @@ static void plan_parts(const std::vector<std::pair<pbn_sim *, uint64_t>> &ext, s
 uint64_t slice_len(const pbn_sim *sim, double tick_us, bool latency, uint32_t parts)
 {
     double us = step_latency_us(sim->net, latency);
-    if (g_split_mode >= 2) parts = std::min(std::min(g_split_mode, kSplitMaxParts), sim->net.nblk);
+    if (g_split_mode >= 2) parts = std::min(std::min(g_split_mode.load(), kSplitMaxParts), sim->net.nblk);
     if (latency && parts >= 2 && g_split_mode != 1 && sim->net.bitsliced) us = std::min(us, 6.0 + us / parts);
     const double q = std::floor(tick_us / us / 32.0) * 32.0;
     return (uint64_t)std::max(32.0, q);
@@ -1546,8 +1560,10 @@ struct Lane {
         return true;
     }
 };
+// One batched solve at a time: its lanes and events are shared.
 struct LanePool {
     static constexpr int kN = 3;
+    std::mutex mu;
     hipEvent_t ev[kN] = {};
     std::vector<std::unique_ptr<Lane>> lane;
     Lane express;                     // runs on the caller's stream
@@ -1578,6 +1594,7 @@ int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
 {
     if (runs.size() < 2) return run_to_completion(runs, ws, stream, err);
     LanePool &P = lane_pool();
+    std::lock_guard<std::mutex> hold(P.mu);
     int rc = P.init(err);
     if (rc) return rc;
     const int nl = LanePool::kN;

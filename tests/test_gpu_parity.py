@@ -365,6 +365,55 @@ def test_sequential_batched_equals_oracle():
             assert_same_result(got[i][0], want[0], (method, names[i]))
 
 
+def test_threads_use_the_library_at_once():
+    """Two host threads on their own simulations at the same time, one through
+    the batched lanes and one through one-network estimates (which fork over
+    the shared stream pool), both recording profile marks: every result
+    equals the oracle's.  The node-split form is off here, since its parts
+    need the device to themselves."""
+    import threading
+    names = [["tiny", "ragged_k7_p05"], ["ragged_k6_p05", "n300_l4"]]
+    want, got, errors = {}, {}, []
+    for t, group in enumerate(names):
+        for c in group:
+            net, omega, pats = CASES[c]()
+            want[c] = drivers.solve(ps.to_text(net), omega, 60 + t, pats[:1], 0.02, 0.95, 1.1, cap=CAP)[0]
+
+    def work(t, group):
+        try:
+            cases = [CASES[c]() for c in group]
+            sims = [pkg.Simulation(pkg.Network(ps.to_text(net)), omega, 60 + t, max_props=1, max_len=CAP)
+                    for net, omega, _ in cases]
+            for rep in range(3):
+                if t == 0:
+                    res = [r[0] for r in pkg.batch_estimate(sims, [p[:1] for _, _, p in cases], [0.02] * 2,
+                                                            [0.95] * 2, psrf_max=1.1)]
+                else:
+                    res = [sm.estimate(p[:1], 0.02, 0.95, psrf_max=1.1)[0] for sm, (_, _, p) in zip(sims, cases)]
+                for c, r in zip(group, res):
+                    got[(c, rep)] = r
+        except Exception as e:                 # reported by the main thread
+            errors.append(e)
+
+    pkg.set_split(1)
+    pkg.profile_enable(True)
+    try:
+        say("two threads: batched lanes and one-network estimates")
+        th = [threading.Thread(target=work, args=(t, g)) for t, g in enumerate(names)]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join(timeout=100)
+        assert not any(x.is_alive() for x in th)
+    finally:
+        pkg.profile_enable(False)
+        pkg.set_split(0)
+    assert not errors, errors
+    for (c, rep), r in got.items():
+        assert_same_result(r, want[c], (c, rep))
+    assert len(got) == 12
+
+
 def test_server_rejects_sequential_methods():
     job = ps.tiny()
     net = pkg.Network(ps.to_text(job.net))
