@@ -494,30 +494,53 @@ int pbn_server_step(pbn_server *srv, uint32_t *active, uint32_t *waiting, uint32
 {
     if (!srv) return fail(PBN_EINVAL, "null argument");
     std::string err;
-    // admission at the round boundary: first fit, in arrival order
-    for (auto it = srv->queue.begin(); it != srv->queue.end();) {
-        ServeReq *rq = *it;
+    // admission at the round boundary: first fit, in arrival order; the
+    // admitted simulations are laid out one by one and reset in one batch
+    // (one descriptor upload, one set-up launch, no synchronisation)
+    std::vector<ServeReq *> admitted;
+    std::deque<ServeReq *> still;
+    auto undo = [&](int rc) {
+        for (ServeReq *rq : admitted) {
+            rq->sim.reset();
+            srv->arena.release(rq->off, rq->bytes);
+        }
+        return fail(rc, err);          // every request stays queued
+    };
+    for (ServeReq *rq : srv->queue) {
         size_t off;
-        if (!srv->arena.alloc(rq->bytes, &off)) { ++it; continue; }
+        if (!srv->arena.alloc(rq->bytes, &off)) { still.push_back(rq); continue; }
         rq->off = off;
         rq->sim.reset(new pbn_sim());
+        admitted.push_back(rq);
         int rc = pbn::sim_setup(rq->sim.get(), rq->net, rq->omega, rq->seed, (uint32_t)rq->nodes.size(), rq->max_len,
-                                srv->arena_base + off, rq->bytes, srv->stream, err);
-        std::vector<pbn_pattern> pats(rq->nodes.size());
-        for (size_t q = 0; q < pats.size(); ++q) pats[q] = {(uint32_t)rq->nodes[q].size(), rq->nodes[q].data(), rq->vals[q].data()};
-        if (!rc) rc = pbn::sim_reset(rq->sim.get(), pats.data(), (uint32_t)pats.size(), srv->stream, err);
-        if (rc) {
-            // the request stays queued; its arena block goes back
-            rq->sim.reset();
-            srv->arena.release(off, rq->bytes);
-            return fail(rc, err);
+                                srv->arena_base + off, rq->bytes, srv->stream, err, false);
+        if (rc) return undo(rc);
+    }
+    if (!admitted.empty()) {
+        std::vector<pbn_sim *> sims;
+        std::vector<pbn_pattern> pats;
+        std::vector<uint32_t> nprops, prop_off;
+        for (ServeReq *rq : admitted) {
+            sims.push_back(rq->sim.get());
+            prop_off.push_back((uint32_t)pats.size());
+            nprops.push_back((uint32_t)rq->nodes.size());
+            for (size_t q = 0; q < rq->nodes.size(); ++q)
+                pats.push_back({(uint32_t)rq->nodes[q].size(), rq->nodes[q].data(), rq->vals[q].data()});
         }
-        rq->run.sim = rq->sim.get();
-        const pbn::MachineParams P = pbn::make_params(rq->sim.get(), &rq->opts, rq->r, rq->conf);
-        for (uint32_t q = 0; q < pats.size(); ++q) rq->run.machines.emplace_back(P, q);
-        rq->state = 1;
-        srv->active.push_back(rq);
-        it = srv->queue.erase(it);
+        int rc = pbn::sims_reset_batch(sims.data(), (uint32_t)sims.size(), pats.data(), nprops.data(),
+                                       prop_off.data(), srv->ws, srv->stream, err);
+        if (rc) {
+            (void)hipStreamSynchronize(srv->stream);
+            return undo(rc);
+        }
+        for (ServeReq *rq : admitted) {
+            rq->run.sim = rq->sim.get();
+            const pbn::MachineParams P = pbn::make_params(rq->sim.get(), &rq->opts, rq->r, rq->conf);
+            for (uint32_t q = 0; q < rq->nodes.size(); ++q) rq->run.machines.emplace_back(P, q);
+            rq->state = 1;
+            srv->active.push_back(rq);
+        }
+        srv->queue.swap(still);
     }
     std::vector<pbn::SimRun *> runs;
     for (ServeReq *rq : srv->active) runs.push_back(&rq->run);
@@ -525,6 +548,12 @@ int pbn_server_step(pbn_server *srv, uint32_t *active, uint32_t *waiting, uint32
         // time-sliced: a request that needs a long extension does not hold the
         // others (or the next admissions) for its whole length
         int rc = pbn::run_round(runs, srv->ws, srv->stream, err, pbn::kServeTickUs);
+        // the next admission rewrites the pinned descriptor staging: this
+        // round's copy of it has completed once the stream is idle
+        if (!admitted.empty() && hipStreamSynchronize(srv->stream) != hipSuccess && !rc) {
+            err = "stream synchronize";
+            rc = PBN_EDEVICE;
+        }
         if (rc) return fail(rc, err);
     }
     // retire finished requests and free their memory for the next admission

@@ -636,7 +636,7 @@ size_t sim_bytes(const Net &net, uint32_t omega, uint32_t max_props, uint64_t ma
 }
 
 int sim_setup(pbn_sim *sim, const Net &net, uint32_t omega, uint64_t seed, uint32_t max_props,
-              uint64_t max_len, void *dev_buf, size_t dev_bytes, hipStream_t stream, std::string &err)
+              uint64_t max_len, void *dev_buf, size_t dev_bytes, hipStream_t stream, std::string &err, bool reset)
 {
     if (omega < 1) { err = "omega must be >= 1"; return PBN_EINVAL; }
     if (max_props > kMaxProps) { err = "too many state sets"; return PBN_ELIMIT; }
@@ -690,7 +690,7 @@ int sim_setup(pbn_sim *sim, const Net &net, uint32_t omega, uint64_t seed, uint3
         err = "blob upload";
         return PBN_EDEVICE;
     }
-    return sim_reset(sim, nullptr, 0, stream, err);
+    return reset ? sim_reset(sim, nullptr, 0, stream, err) : PBN_OK;
 }
 
 int sim_prepare_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops, std::string &err)

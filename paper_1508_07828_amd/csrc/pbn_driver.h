@@ -137,8 +137,12 @@ struct pbn_sim {
 namespace pbn {
 
 size_t sim_bytes(const Net &net, uint32_t omega, uint32_t max_props, uint64_t max_len);
+// Lay out a simulation in dev_buf and upload the network; with reset, also
+// write its descriptor and initial states (else the caller resets it, e.g. in
+// a batch with sims_reset_batch).
 int sim_setup(pbn_sim *sim, const Net &net, uint32_t omega, uint64_t seed, uint32_t max_props,
-              uint64_t max_len, void *dev_buf, size_t dev_bytes, hipStream_t stream, std::string &err);
+              uint64_t max_len, void *dev_buf, size_t dev_bytes, hipStream_t stream, std::string &err,
+              bool reset = true);
 int sim_prepare_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops, std::string &err);
 int sim_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops, hipStream_t stream, std::string &err);
 // Reset many simulations with one descriptor upload and one setup launch on stream.

@@ -579,6 +579,36 @@ def test_server_isolation():
         assert_same_result(got[0], want[0], j.name)
 
 
+def test_server_admissions_with_several_state_sets():
+    """Requests with two state sets each, two-state and Skart alternating,
+    arriving in two waves (the second while the first is on the device): the
+    batched admission resets each simulation with its own sets, and every
+    result equals the oracle's solo run."""
+    cases = ["ragged_k7_p05", "ragged_k6_p05", "n300_l4", "medium", "ragged_l6_k5", "high_p"]
+    reqs = []
+    for i, c in enumerate(cases):
+        net, _, pats = CASES[c]()
+        pats = (pats + [((0, 0),)])[:2]
+        reqs.append((c, ps.to_text(net), pats, "two_state" if i % 2 == 0 else "skart", 70 + i))
+    srv = pkg.Server(256 << 20)
+    ids = {}
+    say("server: two waves of requests with two state sets")
+    for c, text, pats, method, seed in reqs[:3]:
+        ids[c] = srv.submit(pkg.Network(text), 64, seed, pats, 0.02, max_len=CAP, psrf_max=1.1, method=method)
+    srv.step()
+    for c, text, pats, method, seed in reqs[3:]:
+        ids[c] = srv.submit(pkg.Network(text), 64, seed, pats, 0.02, max_len=CAP, psrf_max=1.1, method=method)
+    rounds = 0
+    while srv.step()[2] < len(reqs):
+        rounds += 1
+        assert rounds < 10000
+    for c, text, pats, method, seed in reqs:
+        got = srv.poll(ids[c])
+        want = drivers.solve(text, 64, seed, pats, 0.02, 0.95, 1.1, method=method, cap=CAP)
+        for q in range(2):
+            assert_same_result(got[q], want[q], (c, method, q))
+
+
 def test_rejects_bad_arguments():
     net = pkg.Network(ps.to_text(ps.tiny().net))
     sim = pkg.Simulation(net, 1, 1, max_props=1, max_len=64)
