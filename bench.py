@@ -377,6 +377,8 @@ def main() -> int:
     ap.add_argument("--count", type=int, default=512)
     ap.add_argument("--plain-sample", type=int, default=48)
     ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serial-seconds", type=float, default=20.0,
+                    help="time budget of the serving leg's serial-solve baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -490,7 +492,7 @@ def main() -> int:
     serving = None
     if not args.no_serve:
         log("serving")
-        serving = run_serving(pkg, torch, args.serve_seconds, 200.0, 16 << 30)
+        serving = run_serving(pkg, torch, args.serve_seconds, 200.0, 16 << 30, args.serial_seconds)
         log("serving: p50 {:.1f} ms p99 {:.1f} ms".format(serving["p50_ms"], serving["p99_ms"]))
 
     cpu = None if args.no_cpu else cpu_baseline(jobs, args.cpu_seconds)
