@@ -81,6 +81,51 @@ def test_rejects_like_oracle(bad):
         oracle.Net(bad)
 
 
+def _nudged(rng, text):
+    """The network text with one to three numbers moved a little (ids and counts
+    by small steps or past the 16-bit range, probabilities by zero, halving,
+    doubling or 1e-13 relative)."""
+    t = text.split(" ")
+    for _ in range(rng.randint(1, 3)):
+        i = rng.randrange(len(t))
+        w = t[i].strip()
+        try:
+            t[i] = t[i].replace(w, str(int(w) + rng.choice([-1, 1, -2, 2, 15, -15, 65536])))
+        except ValueError:
+            try:
+                t[i] = t[i].replace(w, repr(float(w) * rng.choice([0.0, 0.5, 2.0, 1 + 1e-13, 1 - 1e-13])))
+            except ValueError:
+                pass
+    return " ".join(t)
+
+
+def test_parser_agrees_with_oracle_on_nudged_networks():
+    """1500 networks with a few numbers nudged: the library accepts exactly
+    what the oracle's parser accepts, and compiles the same thresholds."""
+    import random
+    rng = random.Random(1508)
+    base = [ps.to_text(ps.tiny().net), ps.to_text(ps.small_network(3, 40, l_max=4, k_max=6, p=0.05)),
+            ps.to_text(ps.random_network(np.random.default_rng(100), 33, (1, 4), (1, 6), 0.01))]
+    accepted = 0
+    for _ in range(1500):
+        text = _nudged(rng, rng.choice(base))
+        try:
+            a = pkg.Network(text)
+        except pkg.PbnError:
+            a = None
+        try:
+            b = oracle.Net(text)
+        except ValueError:
+            b = None
+        assert (a is None) == (b is None), text
+        if a is not None:
+            accepted += 1
+            assert a.n == b.n and a.info.p_thr == b.p_thr
+            for i in range(a.n):
+                assert a.thresholds(i) == b.thresholds(i)
+    assert 200 < accepted < 1400
+
+
 def test_limits():
     big_k = "PBN 20 0.5\n" + "".join(
         "N {} 1\nF 1.0 17 {} 0\n".format(i, " ".join(str(v) for v in range(17))) for i in range(20))
