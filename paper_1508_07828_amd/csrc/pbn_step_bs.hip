@@ -212,6 +212,15 @@ __device__ __forceinline__ void resolve(const BsView &v, uint32_t t, uint32_t ch
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
+// A register with no defined contents and no instruction to produce it, for
+// accumulators whose lanes are read only after being written.
+__device__ __forceinline__ uint32_t unspecified()
+{
+    uint32_t x;
+    asm volatile("" : "=v"(x));
+    return x;
+}
+
 // A-phase work of one 16-node block b, lane = chain: the perturbation draws
 // (flips into Gm, chains with a flip into P_acc, ties queued) and, when some
 // node of the block has two or more predictors (lmax >= 2), the selection
@@ -260,8 +269,12 @@ __device__ __forceinline__ void draw_block(const BsView &v, uint32_t t, uint32_t
         // its chain flags
         const PBN_CAS uint32_t *info = v.nd_info + 32 * (size_t)b;
         const PBN_CAS u32x8 *quads = (const PBN_CAS u32x8 *)info;
-        uint32_t al[3] = {0u, 0u, 0u}, ah[3] = {0u, 0u, 0u};
-        uint32_t eh = 0, el = 0, eu = 0, ne = 0;
+        // lanes of al, ah (masks) and eh, el, eu (queued ties) are read only
+        // where they were written, so they start unspecified (no register
+        // copies to clear them); mv must start at 0 (l = 0: no masks)
+        uint32_t al[3] = {unspecified(), unspecified(), unspecified()};
+        uint32_t ah[3] = {unspecified(), unspecified(), unspecified()};
+        uint32_t eh = unspecified(), el = unspecified(), eu = unspecified(), ne = 0;
         uint32_t mv = 0;                  // lane k: node k's record (l | mask offset << 8)
         // node records four at a time (one scalar load each), the next
         // quad's load issued before the current quad's compares
