@@ -246,3 +246,39 @@ def test_sequential_skart_constant_and_cap():
     assert (r["prob"], r["ci_lo"], r["ci_hi"]) == (1.0, 1.0, 1.0)
     r = drivers.estimate_ci(_Pattern(lambda i: 1), 0, 0.01, 0.95, 20479)
     assert r["status"] == drivers.NOT_CONVERGED
+
+
+class _TwoAlternating(_Pattern):
+    """Two chains whose recorded indicators both alternate 0, 1, 0, 1, ..."""
+    omega = 2
+
+    def __init__(self):
+        super().__init__(lambda i: i % 2)
+
+    def extend_to(self, l):
+        super().extend_to(l)
+        self.bits = [np.repeat(self.bits[0], 2, axis=0)]
+
+
+def test_skart_p_hand_worked():
+    """Alg. 2 then Alg. 5 on two alternating chains, psi0 = 4.  The first window
+    (positions 5..8) has equal chain means, so B = 0 and R = sqrt(1 - 1/psi) =
+    sqrt(3)/2: converged at psi = 4.  Skart-P then reads 640 positions per chain
+    from position 5 (1280 observations, zero skewness: kappa = 1); the adjacent
+    batch means alternate (the randomness test passes, lag-1 correlation -1
+    gives A = 1) and 640 ones of 1280 give zero skewness, so the CI is the
+    Student t interval on 1280 values around 1/2.  With H* = 0.01 the half-width
+    (about 0.0274) asks for kappa = ceil((H/H*)^2) = 8, where every batch mean is
+    1/2: a point CI after 4 + 8 * 640 positions."""
+    t = sst.t.ppf(0.975, 1279)
+    half = t * math.sqrt((320.0 / 1279.0) / 1280.0)
+    r = drivers.estimate_ci_in_parallel(_TwoAlternating(), 0, 4, 1.1, 0.1, 0.95, 1 << 20)
+    assert (r["status"], r["psi_gr"], r["psi"], r["kappa"], r["batches"], r["n"], r["chain_len"]) == \
+        (0, 4, 4, 1, 1280, 640, 644)
+    assert abs(r["rhat"] - math.sqrt(3.0) / 2.0) < 1e-15
+    assert r["prob"] == 0.5
+    assert abs(r["ci_lo"] - (0.5 - half)) < 1e-12 and abs(r["ci_hi"] - (0.5 + half)) < 1e-12
+    assert math.ceil((half / 0.01) ** 2) == 8
+    r = drivers.estimate_ci_in_parallel(_TwoAlternating(), 0, 4, 1.1, 0.01, 0.95, 1 << 20)
+    assert (r["status"], r["kappa"], r["batches"], r["n"], r["chain_len"]) == (0, 8, 1280, 5120, 5124)
+    assert (r["prob"], r["ci_lo"], r["ci_hi"]) == (0.5, 0.5, 0.5)
