@@ -229,10 +229,15 @@ int pbn_batch_estimate(pbn_sim *const *sims, uint32_t count, const pbn_pattern *
  * chains stay on the device across extension rounds; each call to
  * pbn_server_step runs one round for every active request (one batched
  * extension launch, one batched reduction launch) and admits waiting requests
- * into freed space at the round boundary (continuous batching). */
+ * into freed space at the round boundary (continuous batching; the requests
+ * admitted at one boundary are initialised together). */
 int pbn_server_create(void *dev_arena, size_t arena_bytes, void *hip_stream, pbn_server **out);
 void pbn_server_free(pbn_server *srv);
-/* Queue a request (the network is copied).  *id receives its handle. */
+/* Queue a request (the network is copied).  *id receives its handle.
+ * omega >= 2 chains (at most PBN_MAX_CHAINS), max_len <= PBN_MAX_LEN, and a
+ * parallel method (PBN_TWO_STATE or PBN_SKART; opts NULL means two-state).
+ * Errors: PBN_EINVAL (bad arguments or a sequential method), PBN_ELIMIT
+ * (beyond the limits), PBN_ENOMEM (footprint larger than the whole arena). */
 int pbn_server_submit(pbn_server *srv, const pbn_net *net, uint32_t omega, uint64_t seed,
                       const pbn_pattern *props, uint32_t nprops, double r, double confidence,
                       const pbn_opts *opts, uint64_t max_len, uint64_t *id);
