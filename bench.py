@@ -169,7 +169,7 @@ def single_workload(pkg, torch, name: str, steps: int, warmup: int, cpu_s: float
 
 
 def multiprop_workload(pkg, torch, steps: int, warmup: int, cpu_s: float, no_cpu: bool) -> dict:
-    """The paper's multi-property experiment shape (Sec. 5.3, Table 2) on a
+    """The paper's multi-property experiment shape (Sec. 5.2, Table 2) on a
     synthetic 96-node network: 7 state sets estimated together (one run whose
     chains serve every property) against one by one (a run per property), both
     on the GPU.  Reports the speed-up sum(t_i)/t_multi and the sample-size
@@ -235,10 +235,10 @@ SEQ_LEN = 1 << 22  # positions of the one sequential chain
 
 
 def sequential_workload(pkg, torch, cpu_s: float, no_cpu: bool) -> dict:
-    """The paper's sequential-versus-parallel comparison (Sec. 5.2): for each
+    """The paper's sequential-versus-parallel comparison (Sec. 5.1, Table 1): for each
     network, the sequential method on one chain against the parallel method on
     the configuration's chains, both on the GPU, for the two-state pair (Alg. 1
-    against Alg. 3) and the Skart pair (Alg. 4 against Alg. 5).  Reports
+    against Alg. 4) and the Skart pair (Alg. 2 against Alg. 5).  Reports
     t_sequential/t_parallel, the speed-up corrected for the sample sizes (sp *
     size_p / size_s), and the paired agreement |p_seq - p_par| < 2r of the
     paper's check; optionally the oracle's sequential method on one host thread
@@ -265,7 +265,7 @@ def sequential_workload(pkg, torch, cpu_s: float, no_cpu: bool) -> dict:
             t_par, rp = timed(job.chains, par)
             t_seq, rs = timed(1, seq)
             # sample sizes without burn-in: omega n for the parallel methods,
-            # N (Alg. 1) or the CI batches' positions (Alg. 4) for the sequential ones
+            # N (Alg. 1) or the CI batches' positions (Alg. 2) for the sequential ones
             size_p = job.chains * rp["n"]
             size_s = rs["N"] if seq == "sequential" else rs["n"]
             sp = t_seq / t_par
@@ -286,7 +286,7 @@ def sequential_workload(pkg, torch, cpu_s: float, no_cpu: bool) -> dict:
                                            and ro["n"] == rs["n"] and ro["chain_len"] == rs["chain_len"])
             log("n={} {}: parallel {:.1f} ms, sequential {:.1f} ms".format(job.net.n, par, t_par * 1e3, t_seq * 1e3))
             rows.append(row)
-    return {"workload": "sequential (one chain: Alg. 1, Alg. 4) vs parallel (Alg. 3, Alg. 5), r={}, s=0.95".format(
+    return {"workload": "sequential (one chain: Alg. 1, Alg. 2) vs parallel (Alg. 4, Alg. 5), r={}, s=0.95".format(
                 R_SEQ),
             "pairs": rows, "all_agree_2r": all(r["agree_2r"] for r in rows)}
 

@@ -12,8 +12,8 @@
  * the selected functions, otherwise s(t+1) = s(t) XOR gamma(t).
  *
  * Method (Sec. 3-4): omega chains run in parallel; Gelman & Rubin's potential
- * scale reduction factor (Alg. 2) certifies convergence; then either the
- * two-state Markov chain approach (Alg. 3, sample size N and burn-in M of
+ * scale reduction factor (Alg. 3) certifies convergence; then either the
+ * two-state Markov chain approach (Alg. 4, sample size N and burn-in M of
  * Alg. 1) or a parallel Skart batch-means procedure (Alg. 5) decides how long
  * the chains must run to estimate the steady-state probability of a set of
  * states within precision r at confidence s.
@@ -88,16 +88,16 @@ typedef struct {
 } pbn_pattern;
 
 typedef struct {
-    int method;                   /* PBN_TWO_STATE (Alg. 3), PBN_SKART (Alg. 5),
+    int method;                   /* PBN_TWO_STATE (Alg. 4), PBN_SKART (Alg. 5),
                                      PBN_SEQ_TWO_STATE (Alg. 1: the sequential two-state
                                      method on a single chain, omega = 1; initial burn-in
                                      m0 = psi0 and sample n0 = 4 psi0, no Gelman-Rubin), or
-                                     PBN_SEQ_SKART (Alg. 4: the sequential Skart method on
+                                     PBN_SEQ_SKART (Alg. 2: the sequential Skart method on
                                      a single chain, omega = 1: 1280 initial positions,
                                      spaced randomness test with up to 10 spacer batches,
                                      the spacer batches skipped as warm-up, no
                                      Gelman-Rubin; psi0 and psrf_max are unused)          */
-    uint64_t psi0;                /* initial Gelman-Rubin psi (Alg. 2); 0 -> 256          */
+    uint64_t psi0;                /* initial Gelman-Rubin psi (Alg. 3); 0 -> 256          */
     double psrf_max;              /* "close to 1": converged when R < psrf_max; 0 -> 1.1  */
     double eps;                   /* Alg. 1's epsilon for M; 0 -> 1e-10                   */
     uint64_t max_len;             /* cap on recorded positions per chain; 0 -> buffer cap;
@@ -108,7 +108,7 @@ typedef struct {
 
 /* Result per state set.  prob is the estimate (two-state: ones in the final
  * window / (omega n); Skart: grand batch mean).  ci_lo/ci_hi only for Skart.
- * psi_gr: psi returned by Alg. 2; psi: final window start (after Alg. 3's
+ * psi_gr: psi returned by Alg. 3; psi: final window start (after Alg. 4's
  * burn-in re-runs); n: window length per chain; N, M: Alg. 1's sample size and
  * burn-in of the last pass; kappa, batches: Skart batch size and count;
  * chain_len: positions this state set needed; status: PBN_OK or PBN_ENOTCONV
@@ -176,7 +176,7 @@ int pbn_sim_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops);
  * the bit-stream capacity or the 2^32 transition limit would be exceeded. */
 int run_chains(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin);
 
-/* Gelman-Rubin R (Alg. 2) of state set `prop` over the last psi recorded
+/* Gelman-Rubin R (Alg. 3) of state set `prop` over the last psi recorded
  * positions of every chain (positions len-psi+1..len).  Synchronises.
  * *rhat = +inf when the within-chain variance W is 0. */
 int psrf(pbn_sim *sim, uint32_t prop, uint64_t psi, double *rhat);
@@ -197,7 +197,7 @@ int pbn_sim_read_bits(pbn_sim *sim, uint32_t prop, uint64_t pos0, uint64_t npos,
 int pbn_sim_position(const pbn_sim *sim, uint64_t *len, uint64_t *transitions);
 int pbn_sim_sync(pbn_sim *sim);
 
-/* Full estimate (Alg. 2 then Alg. 3 or Alg. 5) for nprops state sets sharing
+/* Full estimate (Alg. 3 then Alg. 4 or Alg. 5) for nprops state sets sharing
  * the chains (Sec. 4.2, multiple properties): the chains restart from s(0);
  * each set runs its own procedure; the chains are extended to the smallest
  * pending requirement.  confidence is s (two-state) or 1 - alpha (Skart); for

@@ -8,12 +8,12 @@ Layers:
   * ``sim.c``      plain C simulator (Philox4x32-10 stream, parser, transitions,
                    state-of-interest indicators), built into ``liboracle.so``;
   * ``stats``      the paper's formulas (Gelman-Rubin, two-state M/N, Skart-P);
-  * ``drivers``    Alg. 2 (GR), Alg. 3 (parallel two-state), Alg. 5 (parallel
+  * ``drivers``    Alg. 3 (GR), Alg. 4 (parallel two-state), Alg. 5 (parallel
                    Skart) over oracle chains, and the one-chain Alg. 1
-                   (sequential two-state) and Alg. 4 (sequential Skart);
+                   (sequential two-state) and Alg. 2 (sequential Skart);
   * ``exact``      brute-force 2^n transition matrix and stationary distribution.
 
-The Skart procedures (Alg. 4, Alg. 5) follow a stated reading where the paper
+The Skart procedures (Alg. 2, Alg. 5) follow a stated reading where the paper
 defers to the published Skart method, whose constants it does not give: they
 are pinned by hand-worked cases, the textbook t-interval special case and CI
 coverage of exact stationary probabilities, but their parity against the

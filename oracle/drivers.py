@@ -8,11 +8,11 @@ property (state set) runs its own state machine on chains that depend only on
 properties share the chains; the oracle therefore solves each property alone.
 
 Readings of the paper (where it is silent or garbled) that this file follows:
-  * Alg. 2: the scalar monitored is the property's 0-1 indicator; s_i uses the
+  * Alg. 3: the scalar monitored is the property's 0-1 indicator; s_i uses the
     denominator psi-1; the chains first reach 2*psi0 positions, and each check
     uses positions psi+1..2psi; "close to 1" means R < psrf_max; a check with
     W == 0 counts as not converged; the returned psi is the last one checked.
-  * Alg. 3: the first pass estimates alpha, beta from the existing second halves
+  * Alg. 4: the first pass estimates alpha, beta from the existing second halves
     (positions psi+1..2psi) without extending; the extension is
     ceil((N - omega*n)/omega) and the inner loop ends when it is <= 0; the
     estimate of alpha, beta uses all pairs of consecutive positions inside each
@@ -30,7 +30,7 @@ Readings of the paper (where it is silent or garbled) that this file follows:
     most 10 times); CI = skewness- (Willink) and lag-1 autoregression-adjusted
     t interval on the batch means; if its half-width H exceeds H* the batch size
     grows to ceil(kappa (H/H*)^2).
-  * Alg. 4 (Skart on one chain): an initial trajectory of eta = 1280 positions
+  * Alg. 2 (Skart on one chain): an initial trajectory of eta = 1280 positions
     from position 1; the skewness of its last l = 1024 positions sets the batch
     size as in Alg. 5; p = 1280 batches of kappa positions from position 1; the
     randomness test (the von Neumann ratio above, one chain) runs on the spaced
@@ -68,7 +68,7 @@ class NotConverged(Exception):
 
 
 def generate_converged_chains(ch: Chains, q: int, psi0: int, psrf_max: float, cap: int):
-    """Alg. 2 for property q; returns (psi, R)."""
+    """Alg. 3 for property q; returns (psi, R)."""
     psi = psi0
     while True:
         if 2 * psi > cap:
@@ -82,7 +82,7 @@ def generate_converged_chains(ch: Chains, q: int, psi0: int, psrf_max: float, ca
 
 def estimate_probability_in_parallel(ch: Chains, q: int, psi0: int, psrf_max: float, eps: float,
                                      r: float, s: float, cap: int) -> Dict:
-    """Alg. 3 for property q on chains ch."""
+    """Alg. 4 for property q on chains ch."""
     omega = ch.omega
     z = stats.z_of_confidence(s)
     res = dict(status=OK, psi_gr=0, rhat=math.nan, psi=0, n=0, N=0, M=0, prob=math.nan,
@@ -276,7 +276,7 @@ def _spaced_passes(y: np.ndarray, d: int) -> bool:
 
 
 def estimate_ci(ch: Chains, q: int, H_star: float, s: float, cap: int) -> Dict:
-    """Alg. 4 (the sequential Skart method, Sec. 3.2) for property q on the
+    """Alg. 2 (the sequential Skart method, Sec. 3.2) for property q on the
     single chain of ch; the readings are listed in the module docstring."""
     assert ch.omega == 1
     alpha = 1.0 - s

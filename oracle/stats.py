@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-* Gelman-Rubin PSRF: Alg. 2 (Sec. 4.1), the per-chain means and standard
+* Gelman-Rubin PSRF: Alg. 3 (Sec. 4.1), the per-chain means and standard
   deviations of the last psi values, B, W, sigma^2 and R.
 * Two-state Markov chain sample sizes: Alg. 1, the M and N formulas of its
   burn-in / sample-size step (Sec. 3.1), with alpha and beta estimated from
@@ -96,7 +96,7 @@ def t_quantile(p: float, nu: float) -> float:
 # ------------------------------------------------------- Gelman-Rubin
 
 def psrf(window: np.ndarray) -> float:
-    """R-hat of Alg. 2 for a [omega][psi] window of one scalar per position.
+    """R-hat of Alg. 3 for a [omega][psi] window of one scalar per position.
 
     mu_i and s_i are the mean and standard deviation (denominator psi-1) of
     chain i's window; B = psi/(omega-1) sum (mu_i-mu)^2; W = mean s_i^2;

@@ -332,7 +332,7 @@ int pbn_batch_estimate(pbn_sim *const *sims, uint32_t count, const pbn_pattern *
             return fail(PBN_EINVAL, "unknown method");
         const bool seq = opts && (opts->method == PBN_SEQ_TWO_STATE || opts->method == PBN_SEQ_SKART);
         if (seq && s->omega != 1)
-            return fail(PBN_EINVAL, "the sequential methods (Alg. 1, Alg. 4) run one chain: omega = 1");
+            return fail(PBN_EINVAL, "the sequential methods (Alg. 1, Alg. 2) run one chain: omega = 1");
         if (!seq && s->omega < 2) return fail(PBN_EINVAL, "Gelman-Rubin needs omega >= 2 chains");
         if (!(r[i] > 0.0) || !(conf[i] > 0.0 && conf[i] < 1.0)) return fail(PBN_EINVAL, "r must be > 0 and s in (0,1)");
         if (nprops[i] < 1 || !valid_patterns(props + prop_off[i], nprops[i])) return fail(PBN_EINVAL, "bad state sets");
@@ -467,7 +467,7 @@ int pbn_server_submit(pbn_server *srv, const pbn_net *net, uint32_t omega, uint6
         return fail(PBN_EINVAL, "bad argument");
     if (omega < 2 || !(r > 0.0) || !(confidence > 0.0 && confidence < 1.0)) return fail(PBN_EINVAL, "bad parameters");
     if (opts && opts->method != PBN_TWO_STATE && opts->method != PBN_SKART)
-        return fail(PBN_EINVAL, "the server runs the parallel methods (Alg. 3, Alg. 5)");
+        return fail(PBN_EINVAL, "the server runs the parallel methods (Alg. 4, Alg. 5)");
     if (omega > PBN_MAX_CHAINS || max_len > PBN_MAX_LEN) return fail(PBN_ELIMIT, "omega or max_len beyond the limits");
     auto rq = std::make_unique<ServeReq>();
     rq->id = srv->next_id++;

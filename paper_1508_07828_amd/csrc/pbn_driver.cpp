@@ -1,14 +1,14 @@
-// Host control of the method (Alg. 2, Alg. 3, Alg. 5 and the multi-property
+// Host control of the method (Alg. 3, Alg. 4, Alg. 5 and the multi-property
 // scheme of Sec. 4.2) over device-resident chains.
 //
 // Readings of the paper that this file implements (it is silent or garbled on
 // them):
-//   Alg. 2  the monitored scalar is the state set's 0-1 indicator; s_i uses the
+//   Alg. 3  the monitored scalar is the state set's 0-1 indicator; s_i uses the
 //           denominator psi-1; the chains reach 2*psi0 positions first and each
 //           check uses positions psi+1..2psi; converged when R < psrf_max; a
 //           check with W = 0 is "not converged"; the returned psi is the last
 //           one checked.
-//   Alg. 3  the first pass uses the existing second halves without extending;
+//   Alg. 4  the first pass uses the existing second halves without extending;
 //           the extension is ceil((N - omega n)/omega) and the pass loop ends
 //           when it is <= 0; alpha and beta come from all consecutive pairs
 //           inside each chain's window; if either is undefined the window
@@ -286,7 +286,7 @@ bool randomness_passes(const int32_t *bsum, uint32_t omega, uint64_t m, uint64_t
     return C <= normal_quantile(1.0 - 0.2) * std::sqrt(1.0 / npairs);
 }
 
-// Alg. 4's randomness test on one chain's spaced batch means: batches d, 2d+1,
+// Alg. 2's randomness test on one chain's spaced batch means: batches d, 2d+1,
 // 3d+2, ... (0-based), each one preceded by d spacer batches.
 bool spaced_randomness_passes(const int32_t *bsum, uint64_t p, uint64_t d, uint64_t kappa)
 {
@@ -315,7 +315,7 @@ Machine::Machine(const MachineParams &p, uint32_t prop) : P_(p), prop_(prop)
         return;
     }
     if (P_.method == PBN_SEQ_SKART) {
-        // Alg. 4: an initial trajectory of eta = 1280 positions; the skewness
+        // Alg. 2: an initial trajectory of eta = 1280 positions; the skewness
         // of its last l = 1024 sets the batch size
         st_ = kSeqSkartSkew;
         psi_ = 0;

@@ -84,7 +84,7 @@ private:
         kGR, kTwoState, kSkartSkew, kSkartRandomness, kSkartCI,
         kSeqTwoState, kSeqFinal, kSeqSkartSkew, kSeqSkartRandomness
     };
-    // Alg. 4: initial trajectory, skewness tail, largest spacer (in batches)
+    // Alg. 2: initial trajectory, skewness tail, largest spacer (in batches)
     static constexpr uint64_t kSeqSkartEta = 1280, kSeqSkartTail = 1024, kSeqSkartMaxSpacer = 10;
     void ask_window(uint64_t lo, uint64_t hi);
     bool gr_window_fits(uint64_t psi) const;
@@ -102,12 +102,12 @@ private:
     double z_ = 0.0;
     uint64_t psi_ = 0, psi_gr_ = 0, n_ = 0, N_ = 0;
     double a_ = 0.0, b_ = 0.0;
-    // Skart-P and Alg. 4: first batch position, batch size, batch count
+    // Skart-P and Alg. 2: first batch position, batch size, batch count
     uint64_t base_ = 0, kappa_ = 0, p_ = 0;
     int tries_ = 0;
     // Alg. 1 (one chain): burn-in M, trajectory length l
     uint64_t M_ = 0, l_ = 0;
-    // Alg. 4 (one chain): spacer batches skipped before the CI batches
+    // Alg. 2 (one chain): spacer batches skipped before the CI batches
     uint64_t d_ = 0;
     void seq_next(uint64_t chain_len);
 };

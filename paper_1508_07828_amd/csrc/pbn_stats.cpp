@@ -71,7 +71,7 @@ double t_quantile(double p, double nu)
     return z + g1 / nu + g2 / (nu * nu) + g3 / (nu * nu * nu) + g4 / (nu * nu * nu * nu);
 }
 
-// Gelman-Rubin R of Alg. 2 for 0-1 data from window sums.  With S_c the ones of
+// Gelman-Rubin R of Alg. 3 for 0-1 data from window sums.  With S_c the ones of
 // chain c in a window of psi positions, T1 = sum S_c and T2 = sum S_c^2:
 //   s_c^2 = S_c (psi - S_c) / (psi (psi-1)),  W = (psi T1 - T2) / (omega psi (psi-1)),
 //   B = (omega T2 - T1^2) / (omega (omega-1) psi),

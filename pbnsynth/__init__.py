@@ -182,7 +182,7 @@ def serving(duration_s: float = 60.0, rate: float = 200.0, chains: int = 256,
 
 
 def multiprop(chains: int = 16384, r: float = 1e-4) -> Job:
-    """Shape of the paper's multi-property experiment (Sec. 5.3, Table 2): a
+    """Shape of the paper's multi-property experiment (Sec. 5.2, Table 2): a
     96-node network with 107 Boolean functions (11 nodes with two predictors,
     the others with one) and 7 state sets checked together: a target node's
     marginal and its joint values with each of three parents of one of its

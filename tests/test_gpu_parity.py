@@ -319,7 +319,7 @@ def test_sequential_equals_oracle(case):
 
 @pytest.mark.parametrize("case", ["tiny", "medium", "ragged_k6_p05", "ragged_k7_p05", "n300_l4"])
 def test_sequential_skart_equals_oracle(case):
-    """Alg. 4 (the sequential Skart method on one chain) against the oracle on
+    """Alg. 2 (the sequential Skart method on one chain) against the oracle on
     three seeds: spacers from 0 to 8 batches, batch sizes from 2 to 16, and one
     run whose batches grow after every spacer failed (ragged_k6_p05, seed 7)."""
     net, _, pats = CASES[case]()
@@ -336,7 +336,7 @@ def test_sequential_skart_equals_oracle(case):
 
 @pytest.mark.parametrize("case,cap", [("medium", 16000), ("tiny", 2000)])
 def test_sequential_skart_cap(case, cap):
-    """A cap on the positions ends Alg. 4 as not converged, in the randomness
+    """A cap on the positions ends Alg. 2 as not converged, in the randomness
     stage (medium: 16 x 1280 positions) and in the CI stage (tiny: the batch
     size grows past the cap), with the same report as the oracle's."""
     job = getattr(ps, case)()
@@ -424,7 +424,7 @@ def test_server_rejects_sequential_methods():
 
 
 def test_estimate_two_state_seeds_and_reruns():
-    # several seeds and a small psi0 so that Alg. 3's burn-in re-run (M > psi) occurs
+    # several seeds and a small psi0 so that Alg. 4's burn-in re-run (M > psi) occurs
     job = ps.tiny()
     text = ps.to_text(job.net)
     net = pkg.Network(text)

@@ -3,7 +3,7 @@
 The tiny configuration (n = 10) has a 1024-state chain; its stationary
 distribution is solved exactly in FP64 and P(node0 = 1 and node1 = 1) is
 compared with the oracle's estimates over fixed seeds:
-  * Alg. 3 (two-state, r = 0.01, s = 0.95): the estimate lands within r in at
+  * Alg. 4 (two-state, r = 0.01, s = 0.95): the estimate lands within r in at
     least 179 of 200 runs (179 is the 0.1% quantile of Binomial(200, 0.95));
   * Alg. 5 (Skart-P, H* = 0.01, 95%): the CI covers the exact value in at least
     88 of 100 runs (0.1% quantile of Binomial(100, 0.95)).
@@ -26,8 +26,8 @@ def test_two_state_within_r():
         r = drivers.solve(txt, j.chains, 1000 + k, j.patterns, 0.01, 0.95, 1.1, threads=1)[0]
         assert r["status"] == 0
         assert r["chain_len"] == r["psi"] + r["n"]
-        assert r["N"] <= j.chains * r["n"]           # stop rule of Alg. 3
-        assert r["M"] <= r["psi"]                     # burn-in check of Alg. 3
+        assert r["N"] <= j.chains * r["n"]           # stop rule of Alg. 4
+        assert r["M"] <= r["psi"]                     # burn-in check of Alg. 4
         hits += abs(r["prob"] - truth) < 0.01
     assert hits >= 179
 
@@ -59,7 +59,7 @@ def test_sequential_within_r():
 
 
 def test_sequential_skart_covers():
-    """Alg. 4 (one chain, H* = 0.01, 95%): the CI covers the exact value at the
+    """Alg. 2 (one chain, H* = 0.01, 95%): the CI covers the exact value at the
     binomial-bound rate, its half-width meets H*, and the skipped warm-up is a
     whole number of batches."""
     j, txt, truth = _truth()

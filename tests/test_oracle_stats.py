@@ -1,4 +1,4 @@
-"""Pins for the oracle's statistics (Alg. 1 line-8 formulas, Alg. 2, Skart-P pieces).
+"""Pins for the oracle's statistics (Alg. 1 line-8 formulas, Alg. 3, Skart-P pieces).
 
 * Gelman-Rubin: a worked-by-hand example (golden file) and the identical-chains
   case R = sqrt(1 - 1/psi) (B = 0).
@@ -8,7 +8,7 @@
 * M: the 2x2 transition matrix raised to the M-th power is within eps of its
   limit, and not yet at M-1.
 * Quantiles against scipy; the skewness adjustment inverts Willink's cubic.
-* Alg. 3 control flow on a scripted 0-1 process worked by hand (golden file).
+* Alg. 4 control flow on a scripted 0-1 process worked by hand (golden file).
 """
 import math
 import os
@@ -152,8 +152,8 @@ class ScriptedChains:
         return np.tile(row, (1, self.omega, 1))
 
 
-def test_alg3_hand_trace():
-    g = _golden("alg3_hand_trace.txt")
+def test_parallel_two_state_hand_trace():
+    g = _golden("parallel_two_state_hand_trace.txt")
     res = drivers.estimate_probability_in_parallel(ScriptedChains(2), 0, 4, 1.1, 1e-10, 0.01, 0.95, 1 << 20)
     for key in ("psi_gr", "psi", "n", "N", "M", "chain_len"):
         assert res[key] == int(g[key][0]), key
@@ -198,7 +198,7 @@ class _Pattern:
 
 
 def test_sequential_skart_spacer_skips_warm_up():
-    """Alg. 4 on the indicator 000111000111...: the adjacent batch means (kappa
+    """Alg. 2 on the indicator 000111000111...: the adjacent batch means (kappa
     = 1: the skewness of a half-ones window is near 0) are strongly correlated,
     so the test fails without a spacer; with one spacer batch the tested means
     are x1, x3, x5, ... = 0,1,1,0,1,1,... (negatively correlated), which passes.
@@ -212,7 +212,7 @@ def test_sequential_skart_spacer_skips_warm_up():
 
 
 def test_sequential_skart_reduces_to_t_interval():
-    """Alg. 4 on the alternating indicator 0101...: kappa = 1 (skewness 0), no
+    """Alg. 2 on the alternating indicator 0101...: kappa = 1 (skewness 0), no
     spacer (lag-1 correlation -1 passes), lag-1 correlation <= 0 gives A = 1 and
     640 ones out of 1280 give zero skewness, so the CI is the textbook Student
     t interval on 1280 observations."""
@@ -261,7 +261,7 @@ class _TwoAlternating(_Pattern):
 
 
 def test_skart_p_hand_worked():
-    """Alg. 2 then Alg. 5 on two alternating chains, psi0 = 4.  The first window
+    """Alg. 3 then Alg. 5 on two alternating chains, psi0 = 4.  The first window
     (positions 5..8) has equal chain means, so B = 0 and R = sqrt(1 - 1/psi) =
     sqrt(3)/2: converged at psi = 4.  Skart-P then reads 640 positions per chain
     from position 5 (1280 observations, zero skewness: kappa = 1); the adjacent
