@@ -330,6 +330,39 @@ int pbn_autotune(void *hip_stream, pbn_tune_row *rows, uint32_t cap, uint32_t *c
 /* Back to the built-in shape rule. */
 int pbn_autotune_reset(void);
 
+/* ---------------------------------------------------------------- Skart statistics */
+
+/* Limit on the observations (batch size x batch count) that one Skart CI or
+ * randomness test takes: every moment of the batch means is then computed
+ * exactly in 128-bit integers.  The Skart methods end as not converged beyond
+ * it. */
+#define PBN_SKART_MAX_OBS (1ull << 40)
+
+/* Statistics of one set of Skart batch sums (Sec. 4.3, the parallel Skart
+ * procedure, and Sec. 3.2): the grand mean, the skewness- and lag-1
+ * autoregression-adjusted confidence interval and its half-width
+ * H = max(mu - ci_lo, ci_hi - mu), and the von Neumann randomness test over
+ * within-chain adjacent batch means at level 0.2 (statistic vn_C against the
+ * limit vn_limit; both NaN, and the test passed, with one batch per chain or
+ * all batch means equal). */
+typedef struct {
+    double mu, ci_lo, ci_hi, H;
+    double vn_C, vn_limit;
+    int vn_passes;
+    int reserved;
+} pbn_skart_stats;
+
+/* The statistics estimate_prob's Skart method takes on its batches, for batch
+ * sums computed elsewhere (e.g. by pbn_batch_sums): bsum[c*m + j] is the count
+ * of ones in batch j (of kappa positions) of chain c, omega chains, m batches
+ * each.  Every sum over the batches is exact; floating point enters only in
+ * the final ratios, so equal inputs give bit-equal outputs.  Host only (no
+ * device call).  Errors: PBN_EINVAL (null pointers, omega, m or kappa zero,
+ * confidence not in (0,1), fewer than 101 batches in all, a sum outside
+ * [0, kappa]), PBN_ELIMIT (kappa omega m > PBN_SKART_MAX_OBS). */
+int pbn_skart_batch_stats(const int32_t *bsum, uint32_t omega, uint64_t m, uint64_t kappa,
+                          double confidence, pbn_skart_stats *out);
+
 /* ---------------------------------------------------------------- misc */
 
 /* Phi^{-1}(p) (AS 241) and the Student-t quantile used by the statistics. */

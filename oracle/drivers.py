@@ -29,7 +29,10 @@ Readings of the paper (where it is silent or garbled) that this file follows:
     ceil(sqrt(2) kappa), p := ceil(0.9 p) rounded up to a multiple of omega (at
     most 10 times); CI = skewness- (Willink) and lag-1 autoregression-adjusted
     t interval on the batch means; if its half-width H exceeds H* the batch size
-    grows to ceil(kappa (H/H*)^2).
+    grows to ceil(kappa (H/H*)^2).  The skewness decision on the 0-1 start and
+    every moment of the batch means come from exact integer sums (see
+    ``stats``), so no decision depends on a floating-point summation order; the
+    batches stop, as not converged, beyond 2^40 observations.
   * Alg. 2 (Skart on one chain): an initial trajectory of eta = 1280 positions
     from position 1; the skewness of its last l = 1024 positions sets the batch
     size as in Alg. 5; p = 1280 batches of kappa positions from position 1; the
@@ -128,49 +131,26 @@ def estimate_probability_in_parallel(ch: Chains, q: int, psi0: int, psrf_max: fl
     return res
 
 
-def _batch_means(ch: Chains, q: int, base: int, kappa: int, p: int) -> np.ndarray:
+def _batch_sums(ch: Chains, q: int, base: int, kappa: int, p: int) -> np.ndarray:
+    """Integer batch sums [omega][p/omega]: chain c's batch j holds positions
+    base + j kappa + 1 .. base + (j+1) kappa (1-based)."""
     m = p // ch.omega
     ch.extend_to(base + kappa * m)
-    x = ch.bits[q][:, base: base + kappa * m].astype(np.float64)
-    return x.reshape(ch.omega, m, kappa).sum(axis=2) / kappa       # [omega][m]
+    x = ch.bits[q][:, base: base + kappa * m].astype(np.int64)
+    return x.reshape(ch.omega, m, kappa).sum(axis=2)
 
 
-def von_neumann_passes(Y: np.ndarray, level: float = 0.20) -> bool:
-    """Randomness test over within-chain adjacent batch means (reading of Alg. 5)."""
-    omega, m = Y.shape
-    if m < 2:
-        return True
-    if np.all(Y == Y.flat[0]):
-        return True
-    ybar = float(np.sum(Y)) / Y.size
-    den = float(np.sum((Y - ybar) ** 2))
-    num = float(np.sum((Y[:, 1:] - Y[:, :-1]) ** 2))
-    npairs = omega * (m - 1)
-    C = 1.0 - (num / npairs) / (2.0 * den / (Y.size - 1))
-    return C <= stats.normal_quantile(1.0 - level) * math.sqrt(1.0 / npairs)
+def _batches_fit(base: int, kappa: int, p: int, omega: int, cap: int) -> bool:
+    """p batches of kappa positions from base fit under the cap, and their
+    kappa p observations within the exact-moment limit."""
+    return base + kappa * (p // omega) <= cap and kappa * p <= stats.MAX_BATCH_OBS
 
 
-def adjusted_ci(Y: np.ndarray, alpha: float):
-    """Skewness- and autoregression-adjusted CI on batch means (reading of Alg. 5)."""
-    omega, m = Y.shape
-    pp = Y.size
-    mu = float(np.sum(Y)) / pp
-    if np.all(Y == Y.flat[0]):
-        return mu, mu, mu
-    dev = Y - mu
-    ss = float(np.sum(dev ** 2))
-    S2 = ss / (pp - 1)
-    phi = 0.0
-    if m >= 2:
-        phi = (float(np.sum(dev[:, 1:] * dev[:, :-1])) / (omega * (m - 1))) / (ss / pp)
-    A = (1.0 + phi) / (1.0 - phi) if phi > 0.0 else 1.0
-    skew = (float(np.sum(dev ** 3)) / pp) / (ss / pp) ** 1.5
-    beta = skew / (6.0 * math.sqrt(pp))
-    t_hi = stats.t_quantile(1.0 - alpha / 2.0, pp - 1)
-    se = math.sqrt(A * S2 / pp)
-    lo = mu - stats.willink_G(t_hi, beta) * se
-    hi = mu - stats.willink_G(-t_hi, beta) * se
-    return mu, lo, hi
+def _grown_kappa(kappa: int, H: float, H_star: float) -> int:
+    """Batch size after a CI wider than H*: ceil(kappa (H/H*)^2), evaluated in
+    FP64 and saturated at 2^64 - 1."""
+    ratio = H / H_star
+    return min(int(math.ceil(kappa * (ratio * ratio))), (1 << 64) - 1)
 
 
 def estimate_ci_in_parallel(ch: Chains, q: int, psi0: int, psrf_max: float, H_star: float,
@@ -194,32 +174,31 @@ def estimate_ci_in_parallel(ch: Chains, q: int, psi0: int, psrf_max: float, H_st
         res.update(status=NOT_CONVERGED, chain_len=ch.length)
         return res
     ch.extend_to(base + m0)
-    B = stats.skewness(ch.bits[q][:, base: base + m0].reshape(-1))
-    kappa = 16 if abs(B) > 4.0 else 1
+    ones = int(np.sum(ch.bits[q][:, base: base + m0], dtype=np.int64))
+    kappa = 16 if stats.skewness_exceeds_4(ones, eta0) else 1
     p = eta0
-    if base + kappa * (p // omega) > cap:
+    if not _batches_fit(base, kappa, p, omega, cap):
         res.update(status=NOT_CONVERGED, chain_len=ch.length)
         return res
-    Y = _batch_means(ch, q, base, kappa, p)
+    b = _batch_sums(ch, q, base, kappa, p)
     tries = 0
-    while not von_neumann_passes(Y) and tries < 10:
+    while not stats.von_neumann_passes(b) and tries < 10:
         kappa = int(math.ceil(math.sqrt(2.0) * kappa))
         p = max(omega, _cdiv(int(math.ceil(0.9 * p)), omega) * omega)
         tries += 1
-        if base + kappa * (p // omega) > cap:
+        if not _batches_fit(base, kappa, p, omega, cap):
             res.update(status=NOT_CONVERGED, chain_len=ch.length)
             return res
-        Y = _batch_means(ch, q, base, kappa, p)
+        b = _batch_sums(ch, q, base, kappa, p)
     while True:
-        if base + kappa * (p // omega) > cap:
+        if not _batches_fit(base, kappa, p, omega, cap):
             res.update(status=NOT_CONVERGED, chain_len=ch.length, kappa=kappa, batches=p)
             return res
-        Y = _batch_means(ch, q, base, kappa, p)
-        mu, lo, hi = adjusted_ci(Y, alpha)
+        b = _batch_sums(ch, q, base, kappa, p)
+        mu, lo, hi = stats.adjusted_ci(b, kappa, alpha)
         H = max(mu - lo, hi - mu)
         if H > H_star:
-            ratio = H / H_star
-            kappa = int(math.ceil(kappa * (ratio * ratio)))
+            kappa = _grown_kappa(kappa, H, H_star)
             continue
         break
     n = kappa * (p // omega)
@@ -270,9 +249,9 @@ def estimate_probability(ch: Chains, q: int, m0: int, n0: int, eps: float, r: fl
 
 
 def _spaced_passes(y: np.ndarray, d: int) -> bool:
-    """Randomness test on the spaced batch means of one chain: batches
+    """Randomness test on the spaced batch sums of one chain: batches
     d, 2d+1, 3d+2, ... (0-based), each preceded by d spacer batches."""
-    return von_neumann_passes(y[d::d + 1].reshape(1, -1))
+    return stats.von_neumann_passes(y[d::d + 1].reshape(1, -1))
 
 
 def estimate_ci(ch: Chains, q: int, H_star: float, s: float, cap: int) -> Dict:
@@ -287,15 +266,15 @@ def estimate_ci(ch: Chains, q: int, H_star: float, s: float, cap: int) -> Dict:
         res.update(status=NOT_CONVERGED, chain_len=ch.length)
         return res
     ch.extend_to(eta)
-    B = stats.skewness(ch.bits[q][0, eta - l: eta])
-    kappa = 16 if abs(B) > 4.0 else 1
+    ones = int(np.sum(ch.bits[q][0, eta - l: eta], dtype=np.int64))
+    kappa = 16 if stats.skewness_exceeds_4(ones, l) else 1
     p = eta
     grows = 0
     while True:
         if kappa * p > cap:
             res.update(status=NOT_CONVERGED, chain_len=ch.length)
             return res
-        y = _batch_means(ch, q, 0, kappa, p)[0]
+        y = _batch_sums(ch, q, 0, kappa, p)[0]
         d = next((d for d in range(11) if _spaced_passes(y, d)), None)
         if d is not None:
             break
@@ -311,12 +290,11 @@ def estimate_ci(ch: Chains, q: int, H_star: float, s: float, cap: int) -> Dict:
         if zeta + kappa * pp > cap:
             res.update(status=NOT_CONVERGED, chain_len=ch.length)
             return res
-        Y = _batch_means(ch, q, zeta, kappa, pp)
-        mu, lo, hi = adjusted_ci(Y, alpha)
+        b = _batch_sums(ch, q, zeta, kappa, pp)
+        mu, lo, hi = stats.adjusted_ci(b, kappa, alpha)
         H = max(mu - lo, hi - mu)
         if H > H_star:
-            ratio = H / H_star
-            kappa = int(math.ceil(kappa * (ratio * ratio)))
+            kappa = _grown_kappa(kappa, H, H_star)
             continue
         break
     n = kappa * pp

@@ -11,8 +11,10 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   (1988) 477-484.
 * Student-t quantile: the Cornish-Fisher expansion in 1/nu (Abramowitz and
   Stegun 26.7.5), accurate to ~1e-12 for nu >= 1000 and ~1e-9 for nu >= 100.
-* Skart-P pieces used by Alg. 5 (Sec. 4.3): sample skewness, batch means,
-  von Neumann randomness statistic, skewness- and autoregression-adjusted CI.
+* Skart-P pieces used by Alg. 5 (Sec. 4.3): the skewness decision on 0-1
+  data, the von Neumann randomness statistic and the skewness- and
+  autoregression-adjusted CI on batch means, each from exact integer sums of
+  the batch sums (floating point only in the final ratios).
 """
 from __future__ import annotations
 
@@ -165,6 +167,101 @@ def skewness(x: Sequence[float]) -> float:
     if m2 == 0.0:
         return math.inf
     return m3 / m2 ** 1.5
+
+
+def skewness_exceeds_4(ones: int, count: int) -> bool:
+    """|sample skewness| > 4 for `count` 0-1 observations holding `ones` ones,
+    decided exactly.  With q = ones/count the skewness of 0-1 data is
+    (1-2q)/sqrt(q(1-q)), so |B| > 4 iff (count - 2 ones)^2 > 16 ones (count -
+    ones); with no ones or no zeros the variance is 0 and the skewness is taken
+    as unbounded (Skart's batch size 16 for a strongly skewed start)."""
+    ones, count = int(ones), int(count)
+    if ones == 0 or ones == count:
+        return True
+    return (count - 2 * ones) ** 2 > 16 * ones * (count - ones)
+
+
+# Batch means Y = b / kappa of integer batch sums b[c][j] (chain c, batch j of
+# kappa positions, P = omega m batches in all).  Every sum over the batches is
+# taken exactly in integers; the moments about the grand mean follow from them
+# by exact integer algebra, and floating point enters once per ratio:
+#   S1 = sum b, S2 = sum b^2, S3 = sum b^3;
+#   Q2 = P S2 - S1^2                      = kappa^2 P   sum (Y - mu)^2
+#   Q3 = P^2 S3 - 3 P S1 S2 + 2 S1^3      = kappa^3 P^2 sum (Y - mu)^3
+#   over the omega (m-1) within-chain pairs (b_j, b_{j+1}):
+#   L = sum b_j b_{j+1}, E = sum (b_j + b_{j+1}), D2 = sum (b_{j+1} - b_j)^2;
+#   QL = P^2 L - P S1 E + pairs S1^2      = kappa^2 P^2 sum (Y_{j+1} - mu)(Y_j - mu).
+# The totals are limited to kappa P <= 2^40 observations so that a 128-bit
+# integer holds each of these exactly (both sides stop there as not converged).
+MAX_BATCH_OBS = 1 << 40
+
+
+def batch_moments(bsum) -> dict:
+    """The exact integer aggregates above for bsum[omega][m] (plain loops)."""
+    rows = [[int(v) for v in row] for row in np.asarray(bsum).tolist()]
+    omega, m = len(rows), len(rows[0])
+    P = omega * m
+    S1 = S2 = S3 = L = E = D2 = 0
+    for row in rows:
+        for j in range(m):
+            v = row[j]
+            S1 += v
+            S2 += v * v
+            S3 += v * v * v
+            if j + 1 < m:
+                w = row[j + 1]
+                L += v * w
+                E += v + w
+                D2 += (w - v) * (w - v)
+    pairs = omega * (m - 1)
+    return dict(omega=omega, m=m, P=P, S1=S1, pairs=pairs, D2=D2,
+                Q2=P * S2 - S1 * S1,
+                Q3=P * P * S3 - 3 * P * S1 * S2 + 2 * S1 * S1 * S1,
+                QL=P * P * L - P * S1 * E + pairs * S1 * S1)
+
+
+def von_neumann_passes(bsum, level: float = 0.20) -> bool:
+    """Randomness test over within-chain adjacent batch means (reading of Alg. 5):
+    the von Neumann ratio C = 1 - (sum of squared successive differences / pairs)
+    / (2 sum of squared deviations / (P-1)) against the one-sided normal
+    critical value z_{1-level} / sqrt(pairs).  One batch per chain, or all batch
+    means equal: passes.  From the exact aggregates C = 1 - D2 P (P-1) / (2 pairs
+    Q2), the batch size cancelling."""
+    g = batch_moments(bsum)
+    if g["m"] < 2 or g["Q2"] == 0:
+        return True
+    P, pairs = g["P"], g["pairs"]
+    C = 1.0 - float(g["D2"] * P * (P - 1)) / float(2 * pairs * g["Q2"])
+    return C <= normal_quantile(1.0 - level) * math.sqrt(1.0 / pairs)
+
+
+def adjusted_ci(bsum, kappa: int, alpha: float):
+    """Skewness- and autoregression-adjusted CI on the batch means b/kappa
+    (reading of Alg. 5): grand mean mu; sample variance S^2 (denominator P-1);
+    lag-1 autocorrelation phi of within-chain adjacent means, A = (1+phi)/(1-phi)
+    when phi > 0 else 1; skewness of the means, beta = skew/(6 sqrt(P)); Willink's
+    map G of the t critical values; CI = [mu - G(t_{1-alpha/2}) se, mu -
+    G(-t_{1-alpha/2}) se], se = sqrt(A S^2 / P).  Returns (mu, lo, hi).  From the
+    exact aggregates: mu = S1/(kappa P), phi = QL/(pairs Q2), S^2/P = Q2/(kappa^2 P^2
+    (P-1)), skew = Q3 / Q2^{3/2}; all batch means equal (Q2 = 0) gives the point
+    interval at mu."""
+    g = batch_moments(bsum)
+    K, P = int(kappa), g["P"]
+    mu = float(g["S1"]) / float(K * P)
+    Q2 = g["Q2"]
+    if Q2 == 0:
+        return mu, mu, mu
+    phi = float(g["QL"]) / float(g["pairs"] * Q2) if g["m"] >= 2 else 0.0
+    A = (1.0 + phi) / (1.0 - phi) if phi > 0.0 else 1.0
+    v = float(Q2) / float(K * K * P * P * (P - 1))
+    q2 = float(Q2)
+    skew = float(g["Q3"]) / (q2 * math.sqrt(q2))
+    beta = skew / (6.0 * math.sqrt(float(P)))
+    t_hi = t_quantile(1.0 - alpha / 2.0, float(P - 1))
+    se = math.sqrt(A * v)
+    lo = mu - willink_G(t_hi, beta) * se
+    hi = mu - willink_G(-t_hi, beta) * se
+    return mu, lo, hi
 
 
 def willink_G(zeta: float, beta: float) -> float:

@@ -28,7 +28,7 @@ EXPORTS = (
     "pbn_batch_run", "pbn_batch_estimate", "pbn_server_create", "pbn_server_free", "pbn_server_submit",
     "pbn_server_step", "pbn_server_poll", "pbn_server_memory", "pbn_normal_quantile", "pbn_t_quantile",
     "pbn_last_error", "pbn_profile_enable", "pbn_profile_read", "pbn_profile_reset", "pbn_set_kernel", "pbn_set_split", "pbn_set_split_polls",
-    "pbn_autotune", "pbn_autotune_reset",
+    "pbn_autotune", "pbn_autotune_reset", "pbn_skart_batch_stats",
 )
 
 
@@ -76,6 +76,12 @@ class Profile(ctypes.Structure):
 
 class Counts(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("T1", "T2", "n00", "n01", "n10", "n11")]
+
+
+class SkartStats(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("ci_lo", ctypes.c_double), ("ci_hi", ctypes.c_double),
+                ("H", ctypes.c_double), ("vn_C", ctypes.c_double), ("vn_limit", ctypes.c_double),
+                ("vn_passes", ctypes.c_int), ("reserved", ctypes.c_int)]
 
 
 _lib = None
@@ -131,6 +137,7 @@ def lib():
         "pbn_set_split_polls": (i32, [u32]),
         "pbn_autotune": (i32, [vp, ctypes.POINTER(TuneRow), u32, ctypes.POINTER(u32)]),
         "pbn_autotune_reset": (i32, []),
+        "pbn_skart_batch_stats": (i32, [vp, u32, u64, u64, dbl, ctypes.POINTER(SkartStats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -151,6 +158,19 @@ def normal_quantile(p: float) -> float:
 
 def t_quantile(p: float, nu: float) -> float:
     return float(lib().pbn_t_quantile(p, nu))
+
+
+def skart_batch_stats(bsum, kappa: int, confidence: float) -> Dict:
+    """Skart statistics of integer batch sums bsum[omega][m] (host call)."""
+    b = np.ascontiguousarray(bsum, dtype=np.int32)
+    if b.ndim != 2:
+        raise ValueError("bsum must be [omega][m]")
+    out = SkartStats()
+    _check(lib().pbn_skart_batch_stats(b.ctypes.data, b.shape[0], b.shape[1], int(kappa), float(confidence),
+                                       ctypes.byref(out)))
+    d = {k: getattr(out, k) for k, _ in out._fields_ if k != "reserved"}
+    d["vn_passes"] = bool(d["vn_passes"])
+    return d
 
 
 def set_kernel(mode: str = "auto", waves: int = 0) -> None:

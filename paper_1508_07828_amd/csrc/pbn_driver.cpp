@@ -244,55 +244,22 @@ uint64_t formula_M(double a, double b, double eps)
     return v <= 0.0 ? 0 : (uint64_t)v;
 }
 
-// Skewness adjustment of a t critical value (Willink): ((1+6b(z-b))^{1/3}-1)/(2b);
-// the cube root minus one is expm1(log1p(x)/3) for |x| < 1/2.
-double willink(double zeta, double beta)
-{
-    if (beta == 0.0) return zeta;
-    double x = 6.0 * beta * (zeta - beta);
-    double d = std::fabs(x) < 0.5 ? std::expm1(std::log1p(x) / 3.0) : std::cbrt(1.0 + x) - 1.0;
-    return d / (2.0 * beta);
-}
-
-bool all_equal(const int32_t *v, uint64_t count)
-{
-    for (uint64_t i = 1; i < count; ++i)
-        if (v[i] != v[0]) return false;
-    return true;
-}
-
-// Von Neumann ratio over within-chain adjacent batch means, one-sided at level 0.2.
-bool randomness_passes(const int32_t *bsum, uint32_t omega, uint64_t m, uint64_t kappa)
-{
-    if (m < 2) return true;
-    const uint64_t size = (uint64_t)omega * m;
-    if (all_equal(bsum, size)) return true;
-    const double k = (double)kappa;
-    double sum = 0.0;
-    for (uint64_t e = 0; e < size; ++e) sum += (double)bsum[e] / k;
-    const double ybar = sum / (double)size;
-    double den = 0.0, num = 0.0;
-    for (uint64_t e = 0; e < size; ++e) {
-        double d = (double)bsum[e] / k - ybar;
-        den += d * d;
-    }
-    for (uint32_t c = 0; c < omega; ++c)
-        for (uint64_t b = 0; b + 1 < m; ++b) {
-            double d = (double)bsum[c * m + b + 1] / k - (double)bsum[c * m + b] / k;
-            num += d * d;
-        }
-    const double npairs = (double)((uint64_t)omega * (m - 1));
-    const double C = 1.0 - (num / npairs) / (2.0 * den / (double)(size - 1));
-    return C <= normal_quantile(1.0 - 0.2) * std::sqrt(1.0 / npairs);
-}
-
-// Alg. 2's randomness test on one chain's spaced batch means: batches d, 2d+1,
+// Alg. 2's randomness test on one chain's spaced batch sums: batches d, 2d+1,
 // 3d+2, ... (0-based), each one preceded by d spacer batches.
-bool spaced_randomness_passes(const int32_t *bsum, uint64_t p, uint64_t d, uint64_t kappa)
+bool spaced_randomness_passes(const int32_t *bsum, uint64_t p, uint64_t d)
 {
     std::vector<int32_t> sel;
     for (uint64_t b = d; b < p; b += d + 1) sel.push_back(bsum[b]);
-    return randomness_passes(sel.data(), 1, sel.size(), kappa);
+    return randomness_passes(batch_moments(sel.data(), 1, sel.size()));
+}
+
+// Batch size after a CI wider than H*: ceil(kappa (H/H*)^2) in FP64, saturated
+// at 2^64 - 1.
+uint64_t grown_kappa(uint64_t kappa, double H, double H_star)
+{
+    const double ratio = H / H_star;
+    const double k = std::ceil((double)kappa * (ratio * ratio));
+    return k >= 18446744073709551616.0 ? UINT64_MAX : (uint64_t)k;
 }
 
 }  // namespace
@@ -439,32 +406,16 @@ void Machine::feed_window(const WindowResult &w, uint64_t chain_len)
     }
     case kSkartSkew: {
         const uint64_t eta0 = (uint64_t)cdiv(1280, omega) * omega;
-        bool big;
-        if (w.T1 == 0 || (uint64_t)w.T1 == eta0) {
-            big = true;                          // zero variance: skewness unbounded
-        } else {
-            const double q = (double)w.T1 / (double)eta0;
-            const double B = (1.0 - 2.0 * q) / std::sqrt(q * (1.0 - q));
-            big = std::fabs(B) > 4.0;
-        }
-        kappa_ = big ? 16 : 1;
+        kappa_ = skewness_exceeds_4((uint64_t)w.T1, eta0) ? 16 : 1;
         p_ = eta0;
         tries_ = 0;
         st_ = kSkartRandomness;
-        if (base_ + kappa_ * (p_ / omega) > P_.cap) return not_converged(chain_len);
+        if (!batches_fit()) return not_converged(chain_len);
         ask_batch();
         return;
     }
     case kSeqSkartSkew: {
-        bool big;
-        if (w.T1 == 0 || (uint64_t)w.T1 == kSeqSkartTail) {
-            big = true;                          // zero variance: skewness unbounded
-        } else {
-            const double q = (double)w.T1 / (double)kSeqSkartTail;
-            const double B = (1.0 - 2.0 * q) / std::sqrt(q * (1.0 - q));
-            big = std::fabs(B) > 4.0;
-        }
-        kappa_ = big ? 16 : 1;
+        kappa_ = skewness_exceeds_4((uint64_t)w.T1, kSeqSkartTail) ? 16 : 1;
         p_ = kSeqSkartEta;
         base_ = 0;
         tries_ = 0;
@@ -521,7 +472,7 @@ void Machine::feed_batch(const int32_t *bsum, uint64_t chain_len)
     const uint32_t omega = P_.omega;
     const uint64_t m = p_ / omega;
     if (st_ == kSkartRandomness) {
-        if (randomness_passes(bsum, omega, m, kappa_) || tries_ >= 10) {
+        if (randomness_passes(batch_moments(bsum, omega, m)) || tries_ >= 10) {
             st_ = kSkartCI;
             return skart_ci(bsum, chain_len);
         }
@@ -529,7 +480,7 @@ void Machine::feed_batch(const int32_t *bsum, uint64_t chain_len)
         const uint64_t p09 = (uint64_t)std::ceil(0.9 * (double)p_);
         p_ = std::max<uint64_t>(omega, (uint64_t)cdiv((int64_t)p09, omega) * omega);
         ++tries_;
-        if (base_ + kappa_ * (p_ / omega) > P_.cap) return not_converged(chain_len);
+        if (!batches_fit()) return not_converged(chain_len);
         ask_batch();
         return;
     }
@@ -537,7 +488,7 @@ void Machine::feed_batch(const int32_t *bsum, uint64_t chain_len)
         // spacers d = 0..10 on the same batch means; when all fail, longer
         // batches (at most 10 times, then the spacer stays at 10)
         uint64_t d = 0;
-        while (d <= kSeqSkartMaxSpacer && !spaced_randomness_passes(bsum, p_, d, kappa_)) ++d;
+        while (d <= kSeqSkartMaxSpacer && !spaced_randomness_passes(bsum, p_, d)) ++d;
         if (d > kSeqSkartMaxSpacer && tries_ >= 10) d = kSeqSkartMaxSpacer;
         if (d <= kSeqSkartMaxSpacer) {
             // skip zeta = d kappa positions: the CI uses the p' = p - d batches after them
@@ -560,42 +511,25 @@ void Machine::feed_batch(const int32_t *bsum, uint64_t chain_len)
 void Machine::skart_ci(const int32_t *bsum, uint64_t chain_len)
 {
     const uint32_t omega = P_.omega;
-    const uint64_t m = p_ / omega, pp = p_;
-    const double k = (double)kappa_;
-    double sum = 0.0;
-    for (uint64_t e = 0; e < pp; ++e) sum += (double)bsum[e] / k;
-    const double mu = sum / (double)pp;
-    double lo = mu, hi = mu;
-    if (!all_equal(bsum, pp)) {
-        double ss = 0.0, s3 = 0.0, lag = 0.0;
-        for (uint64_t e = 0; e < pp; ++e) {
-            const double d = (double)bsum[e] / k - mu;
-            ss += d * d;
-            s3 += d * d * d;
-        }
-        double phi = 0.0;
-        if (m >= 2) {
-            for (uint32_t c = 0; c < omega; ++c)
-                for (uint64_t b = 0; b + 1 < m; ++b)
-                    lag += ((double)bsum[c * m + b + 1] / k - mu) * ((double)bsum[c * m + b] / k - mu);
-            phi = (lag / (double)((uint64_t)omega * (m - 1))) / (ss / (double)pp);
-        }
-        const double A = phi > 0.0 ? (1.0 + phi) / (1.0 - phi) : 1.0;
-        const double S2 = ss / (double)(pp - 1);
-        const double skew = (s3 / (double)pp) / std::pow(ss / (double)pp, 1.5);
-        const double beta = skew / (6.0 * std::sqrt((double)pp));
-        const double alpha = 1.0 - P_.conf;
-        const double t_hi = t_quantile(1.0 - alpha / 2.0, (double)(pp - 1));
-        const double se = std::sqrt(A * S2 / (double)pp);
-        lo = mu - willink(t_hi, beta) * se;
-        hi = mu - willink(-t_hi, beta) * se;
-    }
+    const uint64_t m = p_ / omega;
+    double mu, lo, hi;
+    adjusted_ci(batch_moments(bsum, omega, m), kappa_, P_.conf, &mu, &lo, &hi);
     const double H = std::max(mu - lo, hi - mu);
     if (H > P_.r) {
-        const double ratio = H / P_.r;
-        kappa_ = (uint64_t)std::ceil((double)kappa_ * (ratio * ratio));
-        if (P_.method == PBN_SEQ_SKART) base_ = d_ * kappa_;   // the skipped part stays d batches
-        if (base_ + kappa_ * (p_ / omega) > P_.cap) return not_converged(chain_len);
+        kappa_ = grown_kappa(kappa_, H, P_.r);
+        if (P_.method == PBN_SEQ_SKART) {
+            // the skipped part stays d batches
+            if (kappa_ > P_.cap) return not_converged(chain_len);
+            base_ = d_ * kappa_;
+        }
+        if (!batches_fit()) {
+            not_converged(chain_len);
+            if (P_.method == PBN_SKART) {
+                res_.kappa = kappa_;
+                res_.batches = p_;
+            }
+            return;
+        }
         ask_batch();
         return;
     }
@@ -608,6 +542,15 @@ void Machine::skart_ci(const int32_t *bsum, uint64_t chain_len)
     res_.chain_len = base_ + res_.n;
     res_.psi = base_;
     done_ = true;
+}
+
+// p batches of kappa positions from base fit under the cap, and their
+// kappa p observations within the exact-moment limit.
+bool Machine::batches_fit() const
+{
+    const uint64_t m = p_ / P_.omega;
+    if (kappa_ > P_.cap || m > P_.cap) return false;
+    return base_ + kappa_ * m <= P_.cap && (double)kappa_ * (double)p_ <= (double)PBN_SKART_MAX_OBS;
 }
 
 void Machine::finish_two_state(int64_t T1)

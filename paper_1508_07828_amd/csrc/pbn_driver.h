@@ -89,6 +89,7 @@ private:
     void ask_window(uint64_t lo, uint64_t hi);
     bool gr_window_fits(uint64_t psi) const;
     void ask_batch();
+    bool batches_fit() const;
     void not_converged(uint64_t chain_len);
     void finish_two_state(int64_t T1);
     void skart_ci(const int32_t *bsum, uint64_t chain_len);

@@ -180,5 +180,16 @@ int launch_reduce(const Query *d_queries, uint32_t nq, WindowResult *d_win, int3
 double normal_quantile(double p);
 double t_quantile(double p, double nu);
 double rhat_from_sums(int64_t T1, int64_t T2, uint64_t omega, uint64_t psi, bool *defined);
+// Skart: |skewness| > 4 of count 0-1 observations with `ones` ones, exactly.
+bool skewness_exceeds_4(uint64_t ones, uint64_t count);
+// Exact integer aggregates of batch sums b[c m + j] (pbn_stats.cpp).
+struct BatchMoments {
+    uint64_t m = 0, P = 0, pairs = 0;
+    __int128 S1 = 0, D2 = 0, Q2 = 0, Q3 = 0, QL = 0;
+};
+BatchMoments batch_moments(const int32_t *b, uint32_t omega, uint64_t m);
+bool randomness_passes(const BatchMoments &g, double *C_out = nullptr, double *limit_out = nullptr);
+void adjusted_ci(const BatchMoments &g, uint64_t kappa, double conf, double *mu, double *lo, double *hi);
+double willink(double zeta, double beta);
 
 }  // namespace pbn

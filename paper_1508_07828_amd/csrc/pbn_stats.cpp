@@ -1,6 +1,7 @@
 // Host FP64 statistics of the method, evaluated from exact integer aggregates
 // produced by the device reductions.  Compiled with -ffp-contract=off so that
 // every expression rounds exactly as written.
+#include <algorithm>
 #include <cmath>
 
 #include "pbn_internal.h"
@@ -90,7 +91,132 @@ double rhat_from_sums(int64_t T1, int64_t T2, uint64_t omega, uint64_t psi, bool
     return std::sqrt(r2);
 }
 
+// ---------------------------------------------------------------- Skart-P
+//
+// Batch means Y = b / kappa of integer batch sums b[c m + j] (chain c, batch j
+// of kappa positions; P = omega m batches).  Every sum over the batches is
+// exact (128-bit integers); the moments about the grand mean follow by exact
+// integer algebra and floating point enters once per ratio:
+//   S1 = sum b, S2 = sum b^2, S3 = sum b^3
+//   Q2 = P S2 - S1^2                  = kappa^2 P   sum (Y - mu)^2
+//   Q3 = P^2 S3 - 3 P S1 S2 + 2 S1^3  = kappa^3 P^2 sum (Y - mu)^3
+//   over the omega (m-1) within-chain pairs (b_j, b_{j+1}):
+//   L = sum b_j b_{j+1}, E = sum (b_j + b_{j+1}), D2 = sum (b_{j+1} - b_j)^2
+//   QL = P^2 L - P S1 E + pairs S1^2  = kappa^2 P^2 sum (Y_{j+1} - mu)(Y_j - mu)
+// With 0 <= b <= kappa and kappa P <= 2^40 every term is below 2^126.
+
+bool skewness_exceeds_4(uint64_t ones, uint64_t count)
+{
+    // 0-1 data: skewness (1-2q)/sqrt(q(1-q)), q = ones/count; no ones or no
+    // zeros: zero variance, unbounded skewness
+    if (ones == 0 || ones == count) return true;
+    const __int128 d = (__int128)count - 2 * (__int128)ones;
+    return d * d > (__int128)16 * ones * (count - ones);
+}
+
+BatchMoments batch_moments(const int32_t *b, uint32_t omega, uint64_t m)
+{
+    BatchMoments g;
+    __int128 S1 = 0, S2 = 0, S3 = 0, L = 0, E = 0, D2 = 0;
+    for (uint32_t c = 0; c < omega; ++c) {
+        const int32_t *row = b + (uint64_t)c * m;
+        for (uint64_t j = 0; j < m; ++j) {
+            const __int128 v = row[j];
+            S1 += v;
+            S2 += v * v;
+            S3 += v * v * v;
+            if (j + 1 < m) {
+                const __int128 w = row[j + 1];
+                L += v * w;
+                E += v + w;
+                D2 += (w - v) * (w - v);
+            }
+        }
+    }
+    const __int128 P = (__int128)omega * m;
+    g.m = m;
+    g.P = (uint64_t)P;
+    g.pairs = (uint64_t)omega * (m - 1);
+    g.S1 = S1;
+    g.D2 = D2;
+    g.Q2 = P * S2 - S1 * S1;
+    g.Q3 = P * P * S3 - 3 * P * S1 * S2 + 2 * S1 * S1 * S1;
+    g.QL = P * P * L - P * S1 * E + (__int128)g.pairs * S1 * S1;
+    return g;
+}
+
+// Von Neumann ratio over within-chain adjacent batch means, one-sided at level
+// 0.2: C = 1 - (squared successive differences / pairs) / (2 squared
+// deviations / (P-1)) = 1 - D2 P (P-1) / (2 pairs Q2) (the batch size cancels).
+bool randomness_passes(const BatchMoments &g, double *C_out, double *limit_out)
+{
+    if (C_out) *C_out = NAN;
+    if (limit_out) *limit_out = NAN;
+    if (g.m < 2 || g.Q2 == 0) return true;
+    const __int128 P = g.P;
+    const double C = 1.0 - (double)(g.D2 * P * (P - 1)) / (double)(2 * (__int128)g.pairs * g.Q2);
+    const double limit = normal_quantile(1.0 - 0.2) * std::sqrt(1.0 / (double)g.pairs);
+    if (C_out) *C_out = C;
+    if (limit_out) *limit_out = limit;
+    return C <= limit;
+}
+
+// Skewness (Willink) and lag-1 autoregression adjusted t interval on the batch
+// means: mu = S1/(kappa P); phi = QL/(pairs Q2), A = (1+phi)/(1-phi) if phi > 0
+// else 1; se = sqrt(A S^2/P) with S^2/P = Q2/(kappa^2 P^2 (P-1)); skewness
+// Q3/Q2^{3/2}, beta = skew/(6 sqrt P); CI = [mu - G(t) se, mu - G(-t) se] with t
+// the Student t quantile 1 - alpha/2 on P-1 degrees of freedom.  All batch
+// means equal (Q2 = 0): the point interval at mu.
+void adjusted_ci(const BatchMoments &g, uint64_t kappa, double conf, double *mu_out, double *lo_out,
+                 double *hi_out)
+{
+    const __int128 K = kappa, P = g.P;
+    const double mu = (double)g.S1 / (double)(K * P);
+    *mu_out = *lo_out = *hi_out = mu;
+    if (g.Q2 == 0) return;
+    const double phi = g.m >= 2 ? (double)g.QL / (double)((__int128)g.pairs * g.Q2) : 0.0;
+    const double A = phi > 0.0 ? (1.0 + phi) / (1.0 - phi) : 1.0;
+    const double v = (double)g.Q2 / (double)(K * K * P * P * (P - 1));
+    const double q2 = (double)g.Q2;
+    const double skew = (double)g.Q3 / (q2 * std::sqrt(q2));
+    const double beta = skew / (6.0 * std::sqrt((double)g.P));
+    const double alpha = 1.0 - conf;
+    const double t_hi = t_quantile(1.0 - alpha / 2.0, (double)(g.P - 1));
+    const double se = std::sqrt(A * v);
+    *lo_out = mu - willink(t_hi, beta) * se;
+    *hi_out = mu - willink(-t_hi, beta) * se;
+}
+
+// Skewness adjustment of a t critical value (Willink): ((1+6b(z-b))^{1/3}-1)/(2b);
+// the cube root minus one is expm1(log1p(x)/3) for |x| < 1/2.
+double willink(double zeta, double beta)
+{
+    if (beta == 0.0) return zeta;
+    double x = 6.0 * beta * (zeta - beta);
+    double d = std::fabs(x) < 0.5 ? std::expm1(std::log1p(x) / 3.0) : std::cbrt(1.0 + x) - 1.0;
+    return d / (2.0 * beta);
+}
+
 }  // namespace pbn
+
+extern "C" int pbn_skart_batch_stats(const int32_t *bsum, uint32_t omega, uint64_t m, uint64_t kappa,
+                                     double confidence, pbn_skart_stats *out)
+{
+    if (!bsum || !out || omega < 1 || m < 1 || kappa < 1 || !(confidence > 0.0 && confidence < 1.0))
+        return PBN_EINVAL;
+    if (m > PBN_SKART_MAX_OBS || (double)omega * (double)m * (double)kappa > (double)PBN_SKART_MAX_OBS)
+        return PBN_ELIMIT;
+    const uint64_t P = (uint64_t)omega * m;
+    if (P < 101) return PBN_EINVAL;                 // the t quantile is taken for P-1 >= 100
+    for (uint64_t e = 0; e < P; ++e)
+        if (bsum[e] < 0 || (uint64_t)bsum[e] > kappa) return PBN_EINVAL;
+    const pbn::BatchMoments g = pbn::batch_moments(bsum, omega, m);
+    out->vn_passes = pbn::randomness_passes(g, &out->vn_C, &out->vn_limit) ? 1 : 0;
+    pbn::adjusted_ci(g, kappa, confidence, &out->mu, &out->ci_lo, &out->ci_hi);
+    out->H = std::max(out->mu - out->ci_lo, out->ci_hi - out->mu);
+    out->reserved = 0;
+    return PBN_OK;
+}
 
 extern "C" double pbn_normal_quantile(double p) { return pbn::normal_quantile(p); }
 extern "C" double pbn_t_quantile(double p, double nu) { return pbn::t_quantile(p, nu); }

@@ -154,3 +154,50 @@ def test_quantiles_bit_identical():
     for nu in (100, 1279, 5000, 8191):
         for p in (0.975, 0.995, 0.9, 0.025):
             assert pkg.t_quantile(p, nu) == stats.t_quantile(p, nu)
+
+
+def _skart_cases():
+    rng = np.random.default_rng(21)
+    for omega, m, K in ((64, 20, 16), (3, 200, 1), (500, 3, 1000), (1500, 1, 77), (7, 90, 1 << 20),
+                        (8192, 1, 3), (2, 640, 8), (1, 1279, 1), (101, 1, 1 << 16)):
+        walk = np.cumsum(rng.normal(size=(omega, m)), axis=1)
+        q = 1.0 / (1.0 + np.exp(-walk / 3.0 - rng.normal()))
+        yield rng.binomial(K, q), K
+    yield np.full((40, 5), 3), 7                         # all equal
+    b = np.full((40, 5), 3)
+    b[7, 2] = 4
+    yield b, 7                                           # one batch off
+    yield np.tile([0, 1], (3, 100)), 1                   # alternating 0-1 batches
+    for _ in range(40):                                  # small random sets near the t interval's size
+        omega = int(rng.integers(1, 50))
+        m = int(rng.integers(1, 40))
+        if omega * m < 101:
+            m = 101 // omega + 1
+        K = int(rng.integers(1, 5000))
+        yield rng.integers(0, K + 1, size=(omega, m)), K
+
+
+def test_skart_stats_bit_identical():
+    """The library's Skart statistics equal the oracle's bit for bit: both take
+    every sum over the batches exactly, so no decision (randomness test, H > H*)
+    can depend on a summation order.  For each set, an H* placed at H and at its
+    neighbouring doubles decides the same way on both sides."""
+    for b, K in _skart_cases():
+        got = pkg.skart_batch_stats(b, K, 0.95)
+        mu, lo, hi = stats.adjusted_ci(b, K, 0.05)
+        H = max(mu - lo, hi - mu)
+        assert (got["mu"], got["ci_lo"], got["ci_hi"], got["H"]) == (mu, lo, hi, H), (b.shape, K)
+        assert got["vn_passes"] == stats.von_neumann_passes(b), (b.shape, K)
+        for h_star in (H, np.nextafter(H, 0.0), np.nextafter(H, 1.0), H * (1 + 1e-12), H * (1 - 1e-12)):
+            assert (got["H"] > h_star) == (H > h_star)
+
+
+def test_skart_stats_rejects():
+    b = np.ones((2, 60), dtype=np.int32)
+    for args in ((b, 0, 0.95), (b, 1, 1.0), (b[:, :50], 1, 0.95), (b * 3, 2, 0.95), (-b, 1, 0.95)):
+        with pytest.raises(pkg.PbnError) as e:
+            pkg.skart_batch_stats(*args)
+        assert e.value.code == pkg.PBN_EINVAL
+    with pytest.raises(pkg.PbnError) as e:
+        pkg.skart_batch_stats(b, 1 << 34, 0.95)
+    assert e.value.code == pkg.PBN_ELIMIT

@@ -8,6 +8,10 @@
 * M: the 2x2 transition matrix raised to the M-th power is within eps of its
   limit, and not yet at M-1.
 * Quantiles against scipy; the skewness adjustment inverts Willink's cubic.
+* Skart statistics from exact integer batch sums: the textbook moments of the
+  batch means, the t interval when one batch per chain carries no skewness,
+  degenerate and correlated cases, and the exact skewness decision on 0-1 data
+  against scipy.
 * Alg. 4 control flow on a scripted 0-1 process worked by hand (golden file).
 """
 import math
@@ -117,22 +121,117 @@ def test_willink_inverts_cubic():
 
 
 def test_ci_reduces_to_t_interval():
-    # one batch per chain and no skewness adjustment: the textbook t interval
+    # one batch per chain (no lag pairs) and no skewness adjustment: the textbook t interval
     rng = np.random.default_rng(2)
-    Y = rng.normal(0.3, 0.05, size=(2000, 1))
-    mu, lo, hi = drivers.adjusted_ci(Y, 0.05)
+    K = 1000
+    b = rng.binomial(K, 0.3, size=(2000, 1))
+    Y = b / K
+    mu, lo, hi = stats.adjusted_ci(b, K, 0.05)
+    assert mu == b.sum() / (K * b.size)
     se = Y.std(ddof=1) / math.sqrt(Y.size)
     tlo, thi = sst.t.interval(0.95, Y.size - 1, loc=Y.mean(), scale=se)
     skew = sst.skew(Y.ravel())
     # the skewness shift is about beta (1 + 2 t^2) se with beta = skew/(6 sqrt(p)); bound it
     slack = abs(skew) / (6 * math.sqrt(Y.size)) * 12.0 * se + 1e-12
     assert abs(lo - tlo) < slack and abs(hi - thi) < slack
-    # symmetric data: exact match
-    Ys = np.concatenate([Y, 2 * Y.mean() - Y])
-    mu, lo, hi = drivers.adjusted_ci(Ys, 0.05)
+    # symmetric batch sums (each b beside K - b): skewness exactly 0, the t interval itself
+    bs = np.concatenate([b, K - b])
+    Ys = bs / K
+    mu, lo, hi = stats.adjusted_ci(bs, K, 0.05)
+    assert mu == 0.5
     se = Ys.std(ddof=1) / math.sqrt(Ys.size)
     tlo, thi = sst.t.interval(0.95, Ys.size - 1, loc=Ys.mean(), scale=se)
     assert abs(lo - tlo) < 1e-11 and abs(hi - thi) < 1e-11
+
+
+def _textbook(b, K):
+    """The batch-mean statistics from their definitions, in floating point:
+    mean, sum of squared deviations, third central sum, lag-1 products and the
+    von Neumann numerator over within-chain neighbours."""
+    Y = np.asarray(b, dtype=np.float64) / K
+    mu = Y.mean()
+    d = Y - mu
+    ss = float(np.sum(d * d))
+    s3 = float(np.sum(d * d * d))
+    lag = float(np.sum(d[:, 1:] * d[:, :-1]))
+    dn = float(np.sum((Y[:, 1:] - Y[:, :-1]) ** 2))
+    return mu, ss, s3, lag, dn
+
+
+@pytest.mark.parametrize("omega,m,K,seed", [(64, 20, 16, 1), (3, 200, 1, 2), (500, 3, 1000, 3),
+                                            (1500, 1, 77, 4), (7, 90, 1 << 20, 5)])
+def test_batch_moments_match_definitions(omega, m, K, seed):
+    """The exact integer aggregates equal the textbook moments of the batch means
+    (mean, squared and cubed deviations, lag-1 products, squared successive
+    differences) within rounding, on skewed and autocorrelated batch sums."""
+    rng = np.random.default_rng(seed)
+    walk = np.cumsum(rng.normal(size=(omega, m)), axis=1)               # autocorrelated within chains
+    q = 1.0 / (1.0 + np.exp(-walk / 3.0 - 1.5))                           # skewed towards 1
+    b = rng.binomial(K, q)
+    g = stats.batch_moments(b)
+    mu, ss, s3, lag, dn = _textbook(b, K)
+    P = omega * m
+    assert g["P"] == P and g["pairs"] == omega * (m - 1)
+    assert math.isclose(g["S1"] / (K * P), mu, rel_tol=1e-13)
+    assert math.isclose(g["Q2"] / (K * K * P), ss, rel_tol=1e-10)
+    assert math.isclose(g["Q3"] / (K ** 3 * P * P), s3, rel_tol=1e-8, abs_tol=1e-12 * abs(ss) ** 1.5)
+    assert math.isclose(g["QL"] / (K * K * P * P), lag, rel_tol=1e-9, abs_tol=1e-12 * ss)
+    assert math.isclose(g["D2"] / (K * K), dn, rel_tol=1e-12, abs_tol=1e-300)
+    # the interval itself against one built from the textbook moments
+    mu2, lo, hi = stats.adjusted_ci(b, K, 0.05)
+    if m >= 2:
+        phi = (lag / (omega * (m - 1))) / (ss / P)
+    else:
+        phi = 0.0
+    A = (1 + phi) / (1 - phi) if phi > 0 else 1.0
+    se = math.sqrt(A * ss / (P - 1) / P)
+    beta = ((s3 / P) / (ss / P) ** 1.5) / (6 * math.sqrt(P))
+    t = sst.t.ppf(0.975, P - 1)
+    want_lo = mu - stats.willink_G(t, beta) * se
+    want_hi = mu - stats.willink_G(-t, beta) * se
+    assert abs(lo - want_lo) < 1e-9 * se and abs(hi - want_hi) < 1e-9 * se
+    # the von Neumann decision from its definition
+    if m >= 2:
+        C = 1.0 - (dn / (omega * (m - 1))) / (2.0 * ss / (P - 1))
+        crit = sst.norm.ppf(0.8) / math.sqrt(omega * (m - 1))
+        if abs(C - crit) > 1e-9:
+            assert stats.von_neumann_passes(b) == (C <= crit)
+
+
+def test_batch_statistics_degenerate():
+    # all batch means equal: passes the randomness test, point interval
+    b = np.full((10, 30), 5)
+    assert stats.von_neumann_passes(b)
+    assert stats.adjusted_ci(b, 9, 0.05) == (5 / 9, 5 / 9, 5 / 9)
+    # one batch off: a proper interval around the mean
+    b[3, 7] = 6
+    mu, lo, hi = stats.adjusted_ci(b, 9, 0.05)
+    assert lo < mu < hi and mu == (5 * 300 + 1) / (9 * 300)
+    # alternating means within each chain: perfectly negatively correlated neighbours pass
+    alt = np.tile([0, 4], (5, 60))
+    assert stats.von_neumann_passes(alt)
+    # a monotone ramp in every chain: strongly positively correlated, fails
+    ramp = np.tile(np.arange(120) // 10, (5, 1))
+    assert not stats.von_neumann_passes(ramp)
+
+
+def test_skewness_exceeds_4_exactly():
+    """The exact decision on 0-1 data agrees with the sample skewness of the
+    data (scipy, population moments) away from the boundary, and with the
+    boundary worked by hand: 20 q^2 - 20 q + 1 = 0 at q = 0.0528 and 0.9472."""
+    rng = np.random.default_rng(11)
+    for _ in range(300):
+        count = int(rng.integers(100, 3000))
+        ones = int(rng.integers(1, count))
+        x = np.zeros(count)
+        x[:ones] = 1
+        B = sst.skew(x)
+        if abs(abs(B) - 4.0) > 1e-6:
+            assert stats.skewness_exceeds_4(ones, count) == (abs(B) > 4.0), (ones, count)
+    assert stats.skewness_exceeds_4(50, 1000) and not stats.skewness_exceeds_4(60, 1000)   # q = 0.05, 0.06
+    assert stats.skewness_exceeds_4(950, 1000) and not stats.skewness_exceeds_4(940, 1000)
+    assert stats.skewness_exceeds_4(0, 1280) and stats.skewness_exceeds_4(1280, 1280)
+    assert not stats.skewness_exceeds_4(640, 1280)
 
 
 class ScriptedChains:
