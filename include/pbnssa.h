@@ -36,8 +36,9 @@
  * time; different handles may be used from different threads at once.  The
  * batched calls share one set of lane streams, so concurrent batched solves
  * run one after the other.  The node-split form needs the device to itself;
- * under concurrent calls its parts can give up (PBN_EDEVICE, no hang), so
- * callers on several threads turn it off with pbn_set_split(1).
+ * under concurrent calls its parts can give up (then re-run in the one-block
+ * form, about a second later, with the same results), so callers on several
+ * threads turn it off with pbn_set_split(1).
  */
 #ifndef PBNSSA_H
 #define PBNSSA_H
@@ -112,7 +113,8 @@ typedef struct {
  * burn-in re-runs); n: window length per chain; N, M: Alg. 1's sample size and
  * burn-in of the last pass; kappa, batches: Skart batch size and count;
  * chain_len: positions this state set needed; status: PBN_OK or PBN_ENOTCONV
- * (prob then holds NaN or the last estimate). */
+ * (prob then holds NaN or the last estimate), or for a server request that
+ * could not run, the error that ended it (prob NaN). */
 typedef struct {
     double prob, ci_lo, ci_hi, rhat;
     uint64_t psi_gr, psi, n, N, M, kappa, batches, chain_len;
@@ -236,16 +238,25 @@ void pbn_server_free(pbn_server *srv);
 /* Queue a request (the network is copied).  *id receives its handle.
  * omega >= 2 chains (at most PBN_MAX_CHAINS), max_len <= PBN_MAX_LEN, and a
  * parallel method (PBN_TWO_STATE or PBN_SKART; opts NULL means two-state).
- * Errors: PBN_EINVAL (bad arguments or a sequential method), PBN_ELIMIT
- * (beyond the limits), PBN_ENOMEM (footprint larger than the whole arena). */
+ * The state sets are checked here: every node below n, at most PBN_MAX_TERMS
+ * terms in all.  Errors: PBN_EINVAL (bad arguments, a node out of range or a
+ * sequential method), PBN_ELIMIT (beyond the limits), PBN_ENOMEM (footprint
+ * larger than the whole arena). */
 int pbn_server_submit(pbn_server *srv, const pbn_net *net, uint32_t omega, uint64_t seed,
                       const pbn_pattern *props, uint32_t nprops, double r, double confidence,
                       const pbn_opts *opts, uint64_t max_len, uint64_t *id);
-/* One round.  *active / *waiting / *done receive the counts after the round. */
+/* One round.  *active / *waiting / *done receive the counts after the round.
+ * A request that cannot be admitted (its device set-up fails) ends at once,
+ * and a failed round ends every request that was in it: such a request is
+ * done, with the error code as the status of each of its results, and its
+ * arena slot is free again; the step returns the first such error (details in
+ * pbn_last_error) and the server goes on with the other requests at the next
+ * step. */
 int pbn_server_step(pbn_server *srv, uint32_t *active, uint32_t *waiting, uint32_t *done);
 /* Results of a finished request: returns PBN_OK and fills out[nprops] once
- * done, PBN_ENOTCONV-free; returns PBN_EINVAL for unknown ids, and sets
- * *ready = 0 while the request is still queued or running. */
+ * done (each status PBN_OK, PBN_ENOTCONV, or the error that ended the
+ * request); returns PBN_EINVAL for unknown ids, and sets *ready = 0 while the
+ * request is still queued or running. */
 int pbn_server_poll(pbn_server *srv, uint64_t id, int *ready, pbn_result *out);
 /* Bytes of the arena currently in use and the peak so far. */
 int pbn_server_memory(const pbn_server *srv, size_t *in_use, size_t *peak);
@@ -268,6 +279,8 @@ typedef struct {
     double alg_ops;              /* see above                                */
     double philox_evals;         /* expected Philox4x32-10 evaluations       */
     uint64_t split_launches;     /* launches of the node-split form (k_step_split) among them */
+    uint64_t split_fallbacks;    /* node-split groups that gave up waiting and were re-run in
+                                    the one-block form (counted whether or not timing is on) */
 } pbn_profile;
 
 int pbn_profile_enable(int on);
@@ -289,15 +302,17 @@ int pbn_set_kernel(int mode, uint32_t waves);
  * with the most remaining work per part, each group taking at most 16 parts
  * of at least 8 16-node blocks), 1 = never, P >= 2 = P parts for every
  * bit-sliced group whose network has at least P 16-node blocks (fewer
- * otherwise).  Results do not depend on the
- * choice.  A group whose blocks cannot all be resident gives up after about a
- * second and the call returns PBN_EDEVICE. */
+ * otherwise) while the launch stays within one block per CU.  Results do not
+ * depend on the choice.  A group whose blocks are not all resident together
+ * (another process or stream holding CUs) gives up after about a second,
+ * leaving its chains as the launch found them; the call then re-runs that
+ * group in the one-block form (and repeats the round's reductions), so it
+ * still succeeds with the same results, about a second later. */
 int pbn_set_split(uint32_t parts);
 /* Polls of its group's arrival counter that a node-split block makes before it
  * gives up (0 = the default, 2^20, about a second).  For tests of the failure
  * path: with a tiny value a group whose parts do not arrive together ends
- * early and the call returns PBN_EDEVICE; the chains' state is then undefined
- * until the simulation is reset. */
+ * early and is re-run in the one-block form (pbn_profile.split_fallbacks). */
 int pbn_set_split_polls(uint32_t polls);
 int pbn_profile_read(pbn_profile *out);
 int pbn_profile_reset(void);

@@ -68,7 +68,7 @@ class NetInfo(ctypes.Structure):
 class Profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_uint64), ("kernel_ms", ctypes.c_double), ("chain_steps", ctypes.c_double),
                 ("node_updates", ctypes.c_double), ("alg_ops", ctypes.c_double), ("philox_evals", ctypes.c_double),
-                ("split_launches", ctypes.c_uint64)]
+                ("split_launches", ctypes.c_uint64), ("split_fallbacks", ctypes.c_uint64)]
 
     def as_dict(self) -> Dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

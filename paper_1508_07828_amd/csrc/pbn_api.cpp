@@ -469,6 +469,14 @@ int pbn_server_submit(pbn_server *srv, const pbn_net *net, uint32_t omega, uint6
     if (opts && opts->method != PBN_TWO_STATE && opts->method != PBN_SKART)
         return fail(PBN_EINVAL, "the server runs the parallel methods (Alg. 4, Alg. 5)");
     if (omega > PBN_MAX_CHAINS || max_len > PBN_MAX_LEN) return fail(PBN_ELIMIT, "omega or max_len beyond the limits");
+    // the state sets are checked here, so that admission cannot fail on them
+    uint64_t terms = 0;
+    for (uint32_t q = 0; q < nprops; ++q) {
+        for (uint32_t m = 0; m < props[q].nterms; ++m)
+            if (props[q].node[m] >= net->net.n) return fail(PBN_EINVAL, "state-set node out of range");
+        terms += props[q].nterms;
+    }
+    if (terms > PBN_MAX_TERMS) return fail(PBN_ELIMIT, "too many state-set terms");
     auto rq = std::make_unique<ServeReq>();
     rq->id = srv->next_id++;
     rq->net = net->net;
@@ -494,28 +502,55 @@ int pbn_server_step(pbn_server *srv, uint32_t *active, uint32_t *waiting, uint32
 {
     if (!srv) return fail(PBN_EINVAL, "null argument");
     std::string err;
+    // a request that cannot run ends with its error code as every state set's
+    // status, and its arena slot is freed; the other requests go on
+    auto retire = [&](ServeReq *rq, int status) {
+        pbn_result bad{};
+        bad.prob = bad.ci_lo = bad.ci_hi = bad.rhat = NAN;
+        bad.status = status;
+        rq->results.assign(rq->nodes.size(), bad);
+        rq->run.machines.clear();
+        rq->run.sim = nullptr;
+        rq->sim.reset();
+        srv->arena.release(rq->off, rq->bytes);
+        rq->state = 2;
+        ++srv->done;
+    };
     // admission at the round boundary: first fit, in arrival order; the
     // admitted simulations are laid out one by one and reset in one batch
     // (one descriptor upload, one set-up launch, no synchronisation)
     std::vector<ServeReq *> admitted;
     std::deque<ServeReq *> still;
-    auto undo = [&](int rc) {
-        for (ServeReq *rq : admitted) {
-            rq->sim.reset();
-            srv->arena.release(rq->off, rq->bytes);
+    int first_rc = PBN_OK;
+    std::string first_err;
+    auto note = [&](int rc) {
+        if (!first_rc) {
+            first_rc = rc;
+            first_err = err;
         }
-        return fail(rc, err);          // every request stays queued
     };
     for (ServeReq *rq : srv->queue) {
         size_t off;
         if (!srv->arena.alloc(rq->bytes, &off)) { still.push_back(rq); continue; }
         rq->off = off;
         rq->sim.reset(new pbn_sim());
-        admitted.push_back(rq);
         int rc = pbn::sim_setup(rq->sim.get(), rq->net, rq->omega, rq->seed, (uint32_t)rq->nodes.size(), rq->max_len,
                                 srv->arena_base + off, rq->bytes, srv->stream, err, false);
-        if (rc) return undo(rc);
+        if (!rc) {
+            std::vector<pbn_pattern> pats;
+            for (size_t q = 0; q < rq->nodes.size(); ++q)
+                pats.push_back({(uint32_t)rq->nodes[q].size(), rq->nodes[q].data(), rq->vals[q].data()});
+            rc = pbn::sim_prepare_reset(rq->sim.get(), pats.data(), (uint32_t)pats.size(), err);
+        }
+        if (rc) {
+            (void)hipStreamSynchronize(srv->stream);      // its uploads are done before the slot is reused
+            note(rc);
+            retire(rq, rc);
+            continue;
+        }
+        admitted.push_back(rq);
     }
+    srv->queue.swap(still);
     if (!admitted.empty()) {
         std::vector<pbn_sim *> sims;
         std::vector<pbn_pattern> pats;
@@ -531,7 +566,9 @@ int pbn_server_step(pbn_server *srv, uint32_t *active, uint32_t *waiting, uint32
                                        prop_off.data(), srv->ws, srv->stream, err);
         if (rc) {
             (void)hipStreamSynchronize(srv->stream);
-            return undo(rc);
+            note(rc);
+            for (ServeReq *rq : admitted) retire(rq, rc);
+            admitted.clear();
         }
         for (ServeReq *rq : admitted) {
             rq->run.sim = rq->sim.get();
@@ -540,7 +577,6 @@ int pbn_server_step(pbn_server *srv, uint32_t *active, uint32_t *waiting, uint32
             rq->state = 1;
             srv->active.push_back(rq);
         }
-        srv->queue.swap(still);
     }
     std::vector<pbn::SimRun *> runs;
     for (ServeReq *rq : srv->active) runs.push_back(&rq->run);
@@ -554,7 +590,14 @@ int pbn_server_step(pbn_server *srv, uint32_t *active, uint32_t *waiting, uint32
             err = "stream synchronize";
             rc = PBN_EDEVICE;
         }
-        if (rc) return fail(rc, err);
+        if (rc) {
+            // the round's chains are in an unknown state: every request in it
+            // ends with the error, and the queued ones are admitted later
+            (void)hipStreamSynchronize(srv->stream);
+            note(rc);
+            for (ServeReq *rq : srv->active) retire(rq, rc);
+            srv->active.clear();
+        }
     }
     // retire finished requests and free their memory for the next admission
     for (auto it = srv->active.begin(); it != srv->active.end();) {
@@ -571,6 +614,10 @@ int pbn_server_step(pbn_server *srv, uint32_t *active, uint32_t *waiting, uint32
     if (active) *active = (uint32_t)srv->active.size();
     if (waiting) *waiting = (uint32_t)srv->queue.size();
     if (done) *done = srv->done;
+    if (first_rc) {
+        err = first_err;
+        return fail(first_rc, err);
+    }
     return PBN_OK;
 }
 

@@ -115,28 +115,26 @@ int Workspace::ensure_stage(size_t count, std::string &err)
 
 int Workspace::ensure_split(size_t groups, size_t xch_words, std::string &err)
 {
-    if (!d_err) {
-        if (hipMalloc((void **)&d_err, sizeof(uint32_t)) != hipSuccess ||
-            hipHostMalloc((void **)&h_err, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
-            err = "workspace split flag";
-            return PBN_ENOMEM;
-        }
-        *h_err = 0;
-    }
     if (groups > cap_grp) {
         const size_t nc = std::max(groups, 2 * cap_grp);
         if (d_grp) (void)hipFree(d_grp);
         if (h_grp) (void)hipHostFree(h_grp);
         if (d_ctr) (void)hipFree(d_ctr);
+        if (d_stat) (void)hipFree(d_stat);
+        if (h_stat) (void)hipHostFree(h_stat);
         d_grp = h_grp = nullptr;
-        d_ctr = nullptr;
+        d_ctr = d_stat = h_stat = nullptr;
         cap_grp = 0;
+        // group q: arrival counter at word 2q, status word at 2q + 1 (one
+        // clear and one download per launch)
         if (hipMalloc((void **)&d_grp, nc * sizeof(SplitGroup)) != hipSuccess ||
             hipHostMalloc((void **)&h_grp, nc * sizeof(SplitGroup), hipHostMallocDefault) != hipSuccess ||
-            hipMalloc((void **)&d_ctr, nc * sizeof(uint32_t)) != hipSuccess) {
+            hipMalloc((void **)&d_ctr, 2 * nc * sizeof(uint32_t)) != hipSuccess ||
+            hipHostMalloc((void **)&h_stat, 2 * nc * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
             err = "workspace split groups";
             return PBN_ENOMEM;
         }
+        d_stat = d_ctr;
         cap_grp = nc;
     }
     if (xch_words > cap_xch) {
@@ -168,13 +166,40 @@ int Workspace::ensure_rows(size_t words, std::string &err)
     return PBN_OK;
 }
 
+namespace {
+std::atomic<uint64_t> g_split_fallbacks{0};
+}  // namespace
+
+uint64_t split_fallbacks() { return g_split_fallbacks.load(); }
+
 int Workspace::check_split(std::string &err)
 {
     if (!split_used) return PBN_OK;
-    split_used = false;
-    if (h_err && *h_err) {
-        *h_err = 0;
-        err = "node-split step: a block gave up waiting for its group (the launch did not fit on the device)";
+    const size_t ng = split_used;
+    split_used = 0;
+    std::vector<StepItem> redo;
+    for (size_t q = 0; q < ng && q < split_items.size(); ++q)
+        if (h_stat[2 * q + 1] == 1u) redo.push_back(split_items[q]);
+    const size_t nq = redo_queries, nb = redo_bsum;
+    redo_queries = redo_bsum = 0;
+    if (redo.empty()) return PBN_OK;
+    // the groups that gave up left their state as the launch found it and
+    // wrote only indicator words that the re-run writes again unchanged
+    g_split_fallbacks += redo.size();
+    hipStream_t stream = split_stream;
+    int rc = launch_items(redo, *this, stream, err, false, false);
+    if (rc) return rc;
+    if (nq) {
+        if ((rc = launch_reduce(d_queries, (uint32_t)nq, d_win, d_bsum, stream, err))) return rc;
+        if (hipMemcpyAsync(h_win, d_win, nq * sizeof(WindowResult), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+            (nb && hipMemcpyAsync(h_bsum, d_bsum, nb * sizeof(int32_t), hipMemcpyDeviceToHost, stream) !=
+                       hipSuccess)) {
+            err = "result download";
+            return PBN_EDEVICE;
+        }
+    }
+    if (hipStreamSynchronize(stream) != hipSuccess) {
+        err = "node-split re-run";
         return PBN_EDEVICE;
     }
     return PBN_OK;
@@ -189,13 +214,13 @@ void Workspace::release()
     if (h_grp) (void)hipHostFree(h_grp);
     if (d_ctr) (void)hipFree(d_ctr);
     if (d_xch) (void)hipFree(d_xch);
-    if (d_err) (void)hipFree(d_err);
-    if (h_err) (void)hipHostFree(h_err);
+    if (h_stat) (void)hipHostFree(h_stat);
     d_grp = h_grp = nullptr;
     d_xch = nullptr;
-    d_ctr = d_err = h_err = nullptr;
+    d_ctr = d_stat = h_stat = nullptr;
     cap_grp = cap_xch = 0;
-    split_used = false;
+    split_used = 0;
+    split_items.clear();
     if (ev_items) (void)hipEventSynchronize(ev_items), (void)hipEventDestroy(ev_items);
     if (ev_queries) (void)hipEventSynchronize(ev_queries), (void)hipEventDestroy(ev_queries);
     ev_items = ev_queries = nullptr;
@@ -889,12 +914,22 @@ int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, 
     std::vector<uint32_t> parts(items.size(), 1);
     {
         std::vector<size_t> cand;
+        // forced: every group that still keeps the launch within one block
+        // per CU (the parts of a group must all be resident at once)
+        size_t blocks = items.size();
         for (size_t i = 0; i < items.size(); ++i) {
             const StepItem &it = items[i];
             if (it.kernel == 0 || !it.owner || it.nchains == 0) continue;
             const uint32_t nblk = ((const pbn_sim *)it.owner)->net.nblk;
-            if (g_split_mode >= 2) parts[i] = std::min(std::min(g_split_mode.load(), kSplitMaxParts), nblk);
-            else cand.push_back(i);
+            if (g_split_mode >= 2) {
+                const uint32_t P = std::min(std::min(g_split_mode.load(), kSplitMaxParts), nblk);
+                if (P >= 2 && blocks + P - 1 <= kCus) {
+                    parts[i] = P;
+                    blocks += P - 1;
+                }
+            } else {
+                cand.push_back(i);
+            }
         }
         bool hinted = false;
         for (size_t i : cand)
@@ -956,6 +991,7 @@ int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, 
     if (plan.empty()) return PBN_OK;
     int rc = ws.ensure_split(plan.size(), xwords, err);
     if (rc) return rc;
+    ws.split_items.clear();
     std::vector<StepItem> out;
     out.reserve(items.size() + extra);
     std::vector<int> which(items.size(), -1);
@@ -972,13 +1008,20 @@ int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, 
         SplitGroup &g = ws.h_grp[q];
         g.tab = p.tab.d_tab;
         g.xch = ws.d_xch + xoff;
-        g.ctr = ws.d_ctr + q;
-        g.err = ws.d_err;
+        g.ctr = ws.d_ctr + 2 * q;
+        g.stat = ws.d_ctr + 2 * q + 1;
         g.nparts = p.P;
         g.groups = p.tab.groups;
         g.spins = g_split_spins;
         g.pad_ = 0;
         xoff += 2 * (size_t)sim->net.n + 2 * (size_t)p.P;
+        // the whole group in its one-block latency shape, should it give up
+        StepItem whole = items[i];
+        choose_kernel(sim->net, whole, true);
+        whole.part = 0;
+        whole.grp = nullptr;
+        whole.parts_hint = 0;
+        ws.split_items.push_back(whole);
         for (uint32_t r = 0; r < p.P; ++r) {
             StepItem s = items[i];
             s.part = r;
@@ -1035,7 +1078,9 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
             g.maxW = std::max(g.maxW, (it.nodes + 31) / 32);
             g.cost += keys[i].cost * it.nchains;
         }
-        if (g.kernel != 0 && b - a >= 2 * kXcds) {
+        // (not for node-split parts: in launch order, block i on XCD i mod 8,
+        // a launch of at most 256 blocks has a CU for every part at once)
+        if (g.kernel != 0 && (g.cls >> 16) != 2 && b - a >= 2 * kXcds) {
             // XCD-aware placement: block i of a launch runs on XCD i mod 8, so
             // all blocks of one network go to one XCD (its records then live in
             // one L2), networks spread over the XCDs by cost; short lists are
@@ -1109,8 +1154,7 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
     if (nsplit) {
         if (hipMemcpyAsync(ws.d_grp, ws.h_grp, nsplit * sizeof(SplitGroup), hipMemcpyHostToDevice, stream) !=
                 hipSuccess ||
-            hipMemsetAsync(ws.d_ctr, 0, nsplit * sizeof(uint32_t), stream) != hipSuccess ||
-            hipMemsetAsync(ws.d_err, 0, sizeof(uint32_t), stream) != hipSuccess) {
+            hipMemsetAsync(ws.d_ctr, 0, 2 * nsplit * sizeof(uint32_t), stream) != hipSuccess) {
             err = "node-split group upload";
             return PBN_EDEVICE;
         }
@@ -1162,11 +1206,14 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
         }
     }
     if (!rc && nsplit) {
-        if (hipMemcpyAsync(ws.h_err, ws.d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, stream) != hipSuccess) {
-            err = "node-split flag download";
+        if (hipMemcpyAsync(ws.h_stat, ws.d_ctr, 2 * nsplit * sizeof(uint32_t), hipMemcpyDeviceToHost, stream) !=
+            hipSuccess) {
+            err = "node-split status download";
             return PBN_EDEVICE;
         }
-        ws.split_used = true;
+        ws.split_used = nsplit;
+        ws.split_stream = stream;
+        ws.redo_queries = ws.redo_bsum = 0;
     }
     return rc;
 }
@@ -1175,6 +1222,7 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
 
 namespace {
 struct ProfState {
+    uint64_t fallback_base = 0;       // node-split re-runs before the last reset
     std::mutex mu;                    // launches on several threads record marks
     std::atomic<bool> on{false};
     std::vector<ProfileMark> pending;
@@ -1237,7 +1285,10 @@ int profile_collect(pbn_profile *out, std::string &err)
         p.pool.push_back(m.stop);
     }
     p.pending.clear();
-    if (out) *out = p.acc;
+    if (out) {
+        *out = p.acc;
+        out->split_fallbacks = split_fallbacks() - p.fallback_base;
+    }
     return PBN_OK;
 }
 
@@ -1250,6 +1301,7 @@ void profile_clear()
     ProfState &p = prof();
     std::lock_guard<std::mutex> hold(p.mu);
     p.acc = pbn_profile{};
+    p.fallback_base = split_fallbacks();
 }
 
 // ------------------------------------------------------------ rounds
@@ -1426,6 +1478,11 @@ int round_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, 
         hipSuccess) { err = "query upload"; return PBN_EDEVICE; }
     if ((rc = ws.after_copy(ws.ev_queries, ws.queries_in_flight, stream, err))) return rc;
     if ((rc = launch_reduce(ws.d_queries, (uint32_t)qs.size(), ws.d_win, ws.d_bsum, stream, err))) return rc;
+    if (ws.split_used) {
+        // a node-split group re-run after a give-up repeats this reduction
+        ws.redo_queries = qs.size();
+        ws.redo_bsum = bsum_total;
+    }
     if (hipMemcpyAsync(ws.h_win, ws.d_win, qs.size() * sizeof(WindowResult), hipMemcpyDeviceToHost, stream) !=
         hipSuccess) { err = "result download"; return PBN_EDEVICE; }
     if (bsum_total && hipMemcpyAsync(ws.h_bsum, ws.d_bsum, bsum_total * sizeof(int32_t), hipMemcpyDeviceToHost,

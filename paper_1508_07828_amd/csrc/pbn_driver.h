@@ -36,19 +36,27 @@ struct Workspace {
     int after_copy(hipEvent_t &ev, bool &in_flight, hipStream_t stream, std::string &err);
     int ensure_stage(size_t count, std::string &err);
     // node-split form: group descriptors (pinned staging, device), exchange
-    // area, arrival counters and the error word of the last launch
+    // area, arrival counters and the groups' status words of the last launch
     SplitGroup *d_grp = nullptr, *h_grp = nullptr;
     uint64_t *d_xch = nullptr;
-    uint32_t *d_ctr = nullptr, *d_err = nullptr, *h_err = nullptr;
+    uint32_t *d_ctr = nullptr, *d_stat = nullptr, *h_stat = nullptr;
     size_t cap_grp = 0, cap_xch = 0;
+    // the last launch's node-split groups as whole 64-chain items (one-block
+    // shapes) and its stream, for the re-run of a group that gave up; the
+    // reduction that followed it in the same round (queries, batch sums)
+    std::vector<StepItem> split_items;
+    hipStream_t split_stream = nullptr;
+    size_t redo_queries = 0, redo_bsum = 0;
     // lane-per-chain state rows of networks too large for LDS
     uint32_t *d_rows = nullptr;
     size_t cap_rows = 0;
     int ensure_rows(size_t words, std::string &err);
-    bool split_used = false;      // the last launch had node-split groups
+    size_t split_used = 0;        // node-split groups in the last launch
     int ensure_split(size_t groups, size_t xch_words, std::string &err);
-    // after the stream reached the last launch: PBN_EDEVICE if a node-split
-    // group gave up waiting
+    // After the stream reached the last launch: every node-split group that
+    // gave up waiting (its state unchanged) is re-run in the one-block form on
+    // the same stream, then the round's reduction is repeated, and the stream
+    // is synchronised again.
     int check_split(std::string &err);
     void release();
     ~Workspace() { release(); }
@@ -233,6 +241,8 @@ void set_kernel_mode(int mode, uint32_t waves);
 void set_split_mode(uint32_t parts);
 // Polls a node-split part makes before it gives up (0 = the default).
 void set_split_spins(uint32_t polls);
+// Node-split groups re-run in the one-block form after a give-up (process-wide).
+uint64_t split_fallbacks();
 
 // Launch step items for several sims (sorted by cost) on stream.  allow_split:
 // the launch owns the device (nothing else runs beside it that could hold the

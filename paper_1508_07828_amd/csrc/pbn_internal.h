@@ -97,12 +97,14 @@ struct DevSim {
 //   xch: u64 [2][n] next-state words as published by their owners, then
 //        [2][P] perturbed-chain words, by transition parity
 //   ctr: arrivals, one per part and transition, zero at launch
-//   err: set to 1 when a barrier wait times out (the launch then ends early)
+//   stat: 0 at launch; 1 once a block's barrier wait timed out (the group then
+//         ends early and leaves its state unchanged), 2 once block 0 completed
+//         the last transition (it then writes the state back)
 struct SplitGroup {
     const uint32_t *tab;
     uint64_t *xch;
     uint32_t *ctr;
-    uint32_t *err;
+    uint32_t *stat;
     uint32_t nparts, groups;
     uint32_t spins, pad_;        // polls of the counter before a part gives up
 };

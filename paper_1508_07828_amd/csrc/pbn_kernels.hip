@@ -12,7 +12,6 @@
 #include "pbn_device.h"
 
 #include <mutex>
-#include <set>
 #include <utility>
 
 namespace pbn {
@@ -288,16 +287,16 @@ __device__ __forceinline__ uint32_t range_mask(uint64_t wi, uint64_t lo, uint64_
     return upto & ~((1u << a) - 1u);
 }
 
-__device__ __forceinline__ int64_t block_sum(int64_t v, int64_t *scratch)
+__device__ __forceinline__ int64_t block_sum(int64_t v, int64_t *part)
 {
     // wave64 reduction then across the waves of the block
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) scratch[wave] = v;
+    if (lane == 0) part[wave] = v;
     __syncthreads();
     int64_t tot = 0;
     if (threadIdx.x == 0)
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += scratch[w];
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += part[w];
     __syncthreads();
     return tot;
 }
@@ -306,7 +305,7 @@ __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t *scratch)
 __global__ void __launch_bounds__(256) k_reduce(const Query *__restrict__ qs, WindowResult *__restrict__ win,
                                                 int32_t *__restrict__ bsum)
 {
-    __shared__ int64_t scratch[8];
+    __shared__ int64_t part[8];
     const Query qy = load_query(qs, blockIdx.x);
     const View v = load_view(qy.sim);
     const uint32_t omega = v.omega;
@@ -332,11 +331,11 @@ __global__ void __launch_bounds__(256) k_reduce(const Query *__restrict__ qs, Wi
             T1 += S;
             T2 += S * S;
         }
-        T1 = block_sum(T1, scratch);
-        T2 = block_sum(T2, scratch);
-        n01 = block_sum(n01, scratch);
-        n10 = block_sum(n10, scratch);
-        n11 = block_sum(n11, scratch);
+        T1 = block_sum(T1, part);
+        T2 = block_sum(T2, part);
+        n01 = block_sum(n01, part);
+        n10 = block_sum(n10, part);
+        n11 = block_sum(n11, part);
         if (threadIdx.x == 0) {
             const int64_t pairs = hi > lo ? (int64_t)(hi - lo - 1) * omega : 0;
             WindowResult r;
@@ -388,18 +387,23 @@ int launch_setup(const DevSim *d_staging, DevSim *const *d_dst, uint32_t count, 
 // kernel, so it must not sit on the launch path.
 int allow_full_lds(const void *fn, std::string &err)
 {
+    // (kernel, device) pairs already raised, in a fixed table: no allocation
+    // here, so that launch paths which must not allocate can use it
+    constexpr int kSlots = 256;
     static std::mutex mu;
-    static std::set<std::pair<const void *, int>> done;
+    static std::pair<const void *, int> done[kSlots];
+    static int used = 0;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
         err = "hipGetDevice";
         return PBN_EDEVICE;
     }
     std::lock_guard<std::mutex> lock(mu);
-    if (done.count({fn, dev})) return PBN_OK;
+    for (int i = 0; i < used; ++i)
+        if (done[i].first == fn && done[i].second == dev) return PBN_OK;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return check(e, "LDS attribute", err);
-    done.insert({fn, dev});
+    if (used < kSlots) done[used++] = {fn, dev};
     return PBN_OK;
 }
 

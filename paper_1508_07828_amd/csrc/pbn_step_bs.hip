@@ -555,10 +555,19 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
 //      group has arrived at this transition on the group's counter, then read
 //      them all: node i of part q becomes h_i, except in the chains perturbed
 //      by another part only, which keep S_i.
-// The wait is bounded: a block that waits about a second gives up, sets the
-// group's error word and ends; the host then reports the failure.  Block 0 of
-// the group records the indicators (state set q by its wave q mod G) and
-// writes the state back.
+// Ordering: every wave's stores complete and the block synchronises before
+// its first thread arrives with a release read-modify-write of the counter at
+// agent scope; the poll reads it with acquire loads (the last block to arrive
+// acquires through its own read-modify-write), and the block synchronises
+// again before any thread reads the others' words.
+// The wait is bounded: a block that waits about a second gives up.  The group's
+// status word then decides, once, between the two ends of the launch: a block
+// that gives up moves it from 0 to 1 (aborted), block 0 moves it from 0 to 2
+// (complete) after the last transition.  An aborted group never writes its
+// state back, so the host re-runs it in the one-block form from the state it
+// started from; a block that gives up after its group completed ends quietly.
+// Block 0 records the indicators (state set q by its wave q mod G) and writes
+// the state back.
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) k_step_split(const StepItem *__restrict__ items)
 {
     const StepItem it = load_item(items, blockIdx.x);
@@ -569,7 +578,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     const cu32 tab = (cu32)sg->tab;
     PBN_GAS uint64_t *xch = (PBN_GAS uint64_t *)sg->xch;
     PBN_GAS uint32_t *ctr = (PBN_GAS uint32_t *)sg->ctr;
-    PBN_GAS uint32_t *errw = (PBN_GAS uint32_t *)sg->err;
+    PBN_GAS uint32_t *gstat = (PBN_GAS uint32_t *)sg->stat;
     const uint32_t n = v.n, W = v.W, omega = v.omega;
     const uint32_t G = blockDim.x >> 6;
     const uint32_t lane = threadIdx.x & 63u;
@@ -715,29 +724,38 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             __hip_atomic_store(&X[i_lo + k], h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (threadIdx.x == 0) __hip_atomic_store(&XP[r], Pr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // every wave's stores complete before the block arrives
+        // every wave's stores complete before the block arrives; the release
+        // below orders them (through the barrier) before the arrival
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __builtin_amdgcn_s_waitcnt(0);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __syncthreads();
         if (threadIdx.x == 0) {
             const uint32_t target = P * (s + 1);
-            // the last block to arrive need not poll
-            const uint32_t seen = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+            // the last block to arrive need not poll: its read-modify-write
+            // acquires every earlier arrival's release
+            const uint32_t seen = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
             uint32_t spins = 0;
-            while (seen < target && __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                if (++spins >= max_spins) {
+            while (seen < target && __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                // another block of the group gave up: no one will arrive
+                if (__hip_atomic_load(gstat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1u) {
                     *abort_flag = 1u;
+                    break;
+                }
+                if (++spins >= max_spins) {
+                    uint32_t expect = 0u;
+                    __hip_atomic_compare_exchange_strong(gstat, &expect, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                    // 2: the group completed after all (this was its last
+                    // transition), and this block's part is done
+                    *abort_flag = expect == 2u ? 2u : 1u;
                     break;
                 }
                 __builtin_amdgcn_s_sleep(2);
             }
         }
         __syncthreads();
-        if (*abort_flag) {
-            if (threadIdx.x == 0) __hip_atomic_store(errw, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return;
-        }
+        if (*abort_flag) return;
         // node i of part q: h_i, except S_i in the chains perturbed outside q.
         // Every thread issues its first eight node words, the first P threads
         // the parts' perturbed-chain words (into LDS), before any is used.
@@ -793,6 +811,17 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
         ++pos;
     }
     if (!recorder) return;
+    // the group completed unless a block gave up first: then the state stays
+    // as the launch found it, for the host's one-block re-run
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t expect = 0u;
+        __hip_atomic_compare_exchange_strong(gstat, &expect, 2u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        *abort_flag = expect == 1u ? 1u : 0u;
+    }
+    __syncthreads();
+    if (*abort_flag) return;
     if (active && it.nrec > 0 && (pos & 31)) {
         gu32 bits = (gu32)v.d->bits;
         for (uint32_t q = wave; q < nprops; q += G)
@@ -811,6 +840,25 @@ static int check_bs(hipError_t e, const char *what, std::string &err)
 {
     if (e == hipSuccess) return PBN_OK;
     err = std::string(what) + ": " + hipGetErrorString(e);
+    return PBN_EDEVICE;
+}
+
+// An error left by an earlier runtime call would otherwise be reported as the
+// launch's own.
+static int no_stale_error(const char *what, std::string &err)
+{
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) return PBN_OK;
+    err = std::string("before ") + what + ", an earlier HIP call failed: " + hipGetErrorString(e);
+    return PBN_EDEVICE;
+}
+
+static int check_launch(const char *what, uint32_t nitems, uint32_t G, size_t lds, std::string &err)
+{
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) return PBN_OK;
+    err = std::string(what) + " (" + std::to_string(nitems) + " blocks of " + std::to_string(64 * G) +
+          " threads, " + std::to_string(lds) + " bytes of LDS): " + hipGetErrorString(e);
     return PBN_EDEVICE;
 }
 
@@ -841,8 +889,9 @@ int launch_step_split(const StepItem *d_items, uint32_t nitems, uint32_t G, size
         int rc = allow_full_lds((const void *)k_step_split, err);
         if (rc) return rc;
     }
+    if (int rc = no_stale_error("k_step_split launch", err)) return rc;
     hipLaunchKernelGGL(k_step_split, dim3(nitems), dim3(64 * G), lds, (hipStream_t)stream, d_items);
-    return check_bs(hipGetLastError(), "k_step_split launch", err);
+    return check_launch("k_step_split launch", nitems, G, lds, err);
 }
 
 int launch_step_bs(const StepItem *d_items, uint32_t nitems, uint32_t G, bool small, size_t lds, void *stream,
@@ -862,11 +911,12 @@ int launch_step_bs(const StepItem *d_items, uint32_t nitems, uint32_t G, bool sm
         int rc = allow_full_lds(fn, err);
         if (rc) return rc;
     }
+    if (int rc = no_stale_error("k_step_bs launch", err)) return rc;
     if (small)
         hipLaunchKernelGGL(k_step_bs<true>, dim3(nitems), dim3(64 * G), lds, (hipStream_t)stream, d_items);
     else
         hipLaunchKernelGGL(k_step_bs<false>, dim3(nitems), dim3(64 * G), lds, (hipStream_t)stream, d_items);
-    return check_bs(hipGetLastError(), "k_step_bs launch", err);
+    return check_launch(small ? "k_step_bs<small> launch" : "k_step_bs launch", nitems, G, lds, err);
 }
 
 }  // namespace pbn

@@ -182,34 +182,85 @@ def test_split_burn_in_and_thinning(split):
 
 def test_split_gives_up_cleanly():
     """With a one-poll limit a part that reaches a transition's barrier before
-    its group gives up at once: the launch ends early (no hang), the call
-    reports the failure, and a reset restores a simulation that matches the
-    oracle again."""
+    its group gives up at once: the group ends early (no hang), leaves its
+    state as the launch found it, and the call re-runs it in the one-block
+    form, so it succeeds and the chains still equal the oracle's."""
     net, omega, pats = CASES["n300_l4"]()
     text = ps.to_text(net)
     say("split failure path: 5 parts, one poll")
     sim = pkg.Simulation(pkg.Network(text), omega, 7828, max_props=1, max_len=4096)
-    failed = False
+    ch = oracle.Chains(oracle.Net(text), omega, 7828, pats)
     pkg.set_split(5)
     pkg.set_split_polls(1)
+    pkg.profile_reset()
     try:
-        for attempt in range(5):
-            sim.reset(pats)
-            try:
-                sim.run(300)
-            except pkg.PbnError as e:
-                assert e.code == pkg.PBN_EDEVICE and "gave up" in str(e), e
-                failed = True
-                break
+        sim.reset(pats)
+        for steps in (300, 45, 301):
+            sim.run(steps)
+            ch.extend(steps)
+            assert np.array_equal(sim.read_state(), ch.states), steps
+        fallbacks = pkg.profile_read()["split_fallbacks"]
     finally:
         pkg.set_split_polls(0)
         pkg.set_split(0)
-    assert failed
-    sim.reset(pats)
-    ch = oracle.Chains(oracle.Net(text), omega, 7828, pats)
-    sim.run(37)
-    ch.extend(37)
-    assert np.array_equal(sim.read_state(), ch.states)
+    assert fallbacks > 0
+    assert np.array_equal(sim.read_bits(0, 0, ch.length), ch.bits[0])
+
+
+def test_split_give_up_in_estimates_and_server():
+    """The same failure path inside rounds that reduce what they extended: a
+    one-network estimate and a server round re-run the groups that gave up and
+    repeat the round's reductions, and every result equals the oracle's."""
+    job = ps.medium()
+    text = ps.to_text(job.net)
+    want = drivers.solve(text, job.chains, job.seed, job.patterns, job.r, job.confidence, job.psrf_max, cap=CAP)
+    reqs = [(c, ps.to_text(CASES[c]()[0]), CASES[c]()[2][:1]) for c in ("n300_l4", "ragged_l6_k5", "medium")]
+    pkg.set_split(3)
+    pkg.set_split_polls(1)
+    pkg.profile_reset()
+    try:
+        say("split give-up: estimate on medium, 3 parts, one poll")
+        sim = pkg.Simulation(pkg.Network(text), job.chains, job.seed, max_props=1, max_len=CAP)
+        got = sim.estimate(job.patterns, job.r, job.confidence, psrf_max=job.psrf_max)
+        say("split give-up: server with three requests")
+        srv = pkg.Server(256 << 20)
+        ids = {c: srv.submit(pkg.Network(t), 64, 90 + i, p, 0.02, max_len=CAP, psrf_max=1.1)
+               for i, (c, t, p) in enumerate(reqs)}
+        rounds = 0
+        while srv.step()[2] < len(reqs):
+            rounds += 1
+            assert rounds < 10000
+        fallbacks = pkg.profile_read()["split_fallbacks"]
+    finally:
+        pkg.set_split_polls(0)
+        pkg.set_split(0)
+    assert fallbacks > 0
+    assert_same_result(got[0], want[0], "medium estimate")
+    for i, (c, t, p) in enumerate(reqs):
+        w = drivers.solve(t, 64, 90 + i, p, 0.02, 0.95, 1.1, cap=CAP)[0]
+        assert_same_result(srv.poll(ids[c])[0], w, c)
+
+
+def test_server_bad_requests_refused_at_submit():
+    """A state set naming a node beyond n, or more terms than the limit, is
+    refused when submitted, so a server with good requests beside it runs on."""
+    net, _, pats = CASES["ragged_k6_p05"]()
+    text = ps.to_text(net)
+    nw = pkg.Network(text)
+    srv = pkg.Server(64 << 20)
+    good = srv.submit(nw, 64, 3, pats[:1], 0.02, max_len=CAP, psrf_max=1.1)
+    with pytest.raises(pkg.PbnError) as e:
+        srv.submit(nw, 64, 4, [((net.n, 1),)], 0.02, max_len=CAP)
+    assert e.value.code == pkg.PBN_EINVAL
+    with pytest.raises(pkg.PbnError) as e:
+        srv.submit(nw, 64, 5, [tuple((i % net.n, 1) for i in range(65))], 0.02, max_len=CAP)
+    assert e.value.code == pkg.PBN_ELIMIT
+    rounds = 0
+    while srv.step()[2] < 1:
+        rounds += 1
+        assert rounds < 10000
+    want = drivers.solve(text, 64, 3, pats[:1], 0.02, 0.95, 1.1, cap=CAP)[0]
+    assert_same_result(srv.poll(good)[0], want, "good request")
 
 
 def test_split_estimate_equals_oracle():
