@@ -105,6 +105,10 @@ typedef struct {
                                      the Skart methods stop below 2^31 positions (32-bit
                                      batch sums), and Gelman-Rubin where omega psi^2 would
                                      exceed its exact 63-bit sum of squares            */
+    uint32_t thin;                /* transitions per recorded position; 0 or 1 -> every
+                                     state (the paper's methods); k > 1 records every k-th
+                                     state, so the procedures run on the thinned chains  */
+    uint32_t reserved;
 } pbn_opts;
 
 /* Result per state set.  prob is the estimate (two-state: ones in the final
@@ -112,7 +116,8 @@ typedef struct {
  * psi_gr: psi returned by Alg. 3; psi: final window start (after Alg. 4's
  * burn-in re-runs); n: window length per chain; N, M: Alg. 1's sample size and
  * burn-in of the last pass; kappa, batches: Skart batch size and count;
- * chain_len: positions this state set needed; status: PBN_OK or PBN_ENOTCONV
+ * chain_len: positions this state set needed (recorded positions: thin transitions
+ * each); status: PBN_OK or PBN_ENOTCONV
  * (prob then holds NaN or the last estimate), or for a server request that
  * could not run, the error that ended it (prob NaN). */
 typedef struct {
@@ -120,6 +125,9 @@ typedef struct {
     uint64_t psi_gr, psi, n, N, M, kappa, batches, chain_len;
     int status;
     int reserved;
+    uint64_t sample_size;         /* observations behind prob: omega n (two-state, Skart),
+                                     N (Alg. 1), kappa p' (Alg. 2); 0 when not converged */
+    uint64_t rounds;              /* window or batch results this state set consumed    */
 } pbn_result;
 
 typedef struct {
@@ -144,6 +152,9 @@ typedef struct {
  * 1 <= k <= 16, parents distinct and < n, truth table fits 2^k bits.
  * Host only (no device call).  On success *out owns the network. */
 int pbn_load(const char *text, size_t len, pbn_net **out);
+/* The same from a file holding the canonical text.  Errors as pbn_load, and
+ * PBN_EINVAL when the file cannot be read. */
+int pbn_load_file(const char *path, pbn_net **out);
 void pbn_free(pbn_net *net);
 int pbn_net_get_info(const pbn_net *net, pbn_net_info *out);
 /* Thresholds T_1..T_l of node i (for tests); returns l or -1. */
@@ -284,6 +295,14 @@ typedef struct {
 } pbn_profile;
 
 int pbn_profile_enable(int on);
+/* The kernel and node-split choices of one simulation's launches, instead of
+ * the process-wide ones below (so that threads with their own simulations
+ * need not share them): mode and waves as in pbn_set_kernel, parts as in
+ * pbn_set_split; mode -1 or parts -1 return to the process-wide setting.
+ * Results do not depend on the choice. */
+int pbn_sim_set_kernel(pbn_sim *sim, int mode, uint32_t waves);
+int pbn_sim_set_split(pbn_sim *sim, int parts);
+
 /* Trajectory-kernel selection for subsequent launches: mode 0 = automatic
  * (bit-sliced kernel when every predictor has at most 6 parents and the
  * bit-sliced state fits in LDS, else lane-per-chain), 1 = lane-per-chain only,

@@ -146,22 +146,25 @@ def _props_csr(patterns):
 class Chains:
     """omega oracle chains with their recorded indicator streams.
 
-    Position l (1-based) of a chain is the state after transition l-1 (the
-    initial state s(0) is not recorded).  ``bits[q][c][l-1]`` is the indicator
-    of property q at position l of chain c.
+    Position l (1-based) of a chain is the state after transition l*thin - 1
+    (0-based transitions; thin = 1: after transition l-1; the initial state
+    s(0) is not recorded).  ``bits[q][c][l-1]`` is the indicator of property q
+    at position l of chain c.
     """
 
     def __init__(self, net: Net, omega: int, seed: int, patterns, chain0: int = 0,
-                 threads: int | None = None):
+                 threads: int | None = None, thin: int = 1):
         self.net = net
         self.omega = int(omega)
         self.seed = int(seed)
         self.chain0 = int(chain0)
+        self.thin = int(thin)
         self.patterns = [tuple(p) for p in patterns]
         self.threads = threads or default_threads()
         self.states = np.zeros((self.omega, net.n), np.uint8)
         lib().orc_init(net._h, self.seed, self.chain0, self.omega, self.states.ctypes.data)
         self.length = 0
+        self.transitions = 0
         self._cap = 0
         self._bits = np.zeros((len(self.patterns), self.omega, 0), np.uint8)
         self._csr = _props_csr(self.patterns)
@@ -180,16 +183,19 @@ class Chains:
             nb = np.zeros((len(self.patterns), self.omega, cap), np.uint8)
             nb[:, :, : self.length] = self._bits[:, :, : self.length]
             self._bits, self._cap = nb, cap
-        out = np.zeros((len(self.patterns), self.omega, k), np.uint8)
+        steps = k * self.thin
+        out = np.zeros((len(self.patterns), self.omega, steps), np.uint8)
         offs, nodes, vals = self._csr
         rc = lib().orc_run(self.net._h, self.seed, self.chain0, self.omega, self.states.ctypes.data,
-                           self.length, k, len(self.patterns), offs.ctypes.data, nodes.ctypes.data,
+                           self.transitions, steps, len(self.patterns), offs.ctypes.data, nodes.ctypes.data,
                            vals.ctypes.data, out.ctypes.data if len(self.patterns) else None,
                            self.threads)
         if rc != 0:
             raise RuntimeError(lib().orc_error().decode())
-        self._bits[:, :, self.length: need] = out
+        # every thin-th state is a recorded position
+        self._bits[:, :, self.length: need] = out[:, :, self.thin - 1:: self.thin]
         self.length = need
+        self.transitions += steps
 
     def extend_to(self, length: int) -> None:
         if length > self.length:

@@ -304,13 +304,14 @@ def estimate_ci(ch: Chains, q: int, H_star: float, s: float, cap: int) -> Dict:
 
 def solve(text: str, omega: int, seed: int, patterns, r: float, s: float, psrf_max: float,
           method: str = "two_state", psi0: int = 256, eps: float = 1e-10, cap: int = 1 << 26,
-          threads: int | None = None) -> List[Dict]:
+          threads: int | None = None, thin: int = 1) -> List[Dict]:
     """Solve every property alone (fresh chains, same seed); the per-property
-    results equal those of a shared-chain run."""
+    results equal those of a shared-chain run.  thin > 1: the procedures run on
+    every thin-th state of the chains."""
     net = Net(text)
     out = []
     for q in range(len(patterns)):
-        ch = Chains(net, omega, seed, [patterns[q]], threads=threads)
+        ch = Chains(net, omega, seed, [patterns[q]], threads=threads, thin=thin)
         if method == "two_state":
             out.append(estimate_probability_in_parallel(ch, 0, psi0, psrf_max, eps, r, s, cap))
         elif method == "skart":

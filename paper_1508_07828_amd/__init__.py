@@ -28,7 +28,8 @@ EXPORTS = (
     "pbn_batch_run", "pbn_batch_estimate", "pbn_server_create", "pbn_server_free", "pbn_server_submit",
     "pbn_server_step", "pbn_server_poll", "pbn_server_memory", "pbn_normal_quantile", "pbn_t_quantile",
     "pbn_last_error", "pbn_profile_enable", "pbn_profile_read", "pbn_profile_reset", "pbn_set_kernel", "pbn_set_split", "pbn_set_split_polls",
-    "pbn_autotune", "pbn_autotune_reset", "pbn_skart_batch_stats",
+    "pbn_autotune", "pbn_autotune_reset", "pbn_skart_batch_stats", "pbn_load_file",
+    "pbn_sim_set_kernel", "pbn_sim_set_split",
 )
 
 
@@ -45,7 +46,8 @@ class Pattern(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("psi0", ctypes.c_uint64), ("psrf_max", ctypes.c_double),
-                ("eps", ctypes.c_double), ("max_len", ctypes.c_uint64)]
+                ("eps", ctypes.c_double), ("max_len", ctypes.c_uint64), ("thin", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class Result(ctypes.Structure):
@@ -53,7 +55,8 @@ class Result(ctypes.Structure):
                 ("rhat", ctypes.c_double), ("psi_gr", ctypes.c_uint64), ("psi", ctypes.c_uint64),
                 ("n", ctypes.c_uint64), ("N", ctypes.c_uint64), ("M", ctypes.c_uint64),
                 ("kappa", ctypes.c_uint64), ("batches", ctypes.c_uint64), ("chain_len", ctypes.c_uint64),
-                ("status", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("status", ctypes.c_int), ("reserved", ctypes.c_int), ("sample_size", ctypes.c_uint64),
+                ("rounds", ctypes.c_uint64)]
 
     def as_dict(self) -> Dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -99,6 +102,9 @@ def lib():
                                   ctypes.c_double, ctypes.c_size_t)
     sig = {
         "pbn_load": (i32, [ctypes.c_char_p, sz, ctypes.POINTER(vp)]),
+        "pbn_load_file": (i32, [ctypes.c_char_p, ctypes.POINTER(vp)]),
+        "pbn_sim_set_kernel": (i32, [vp, i32, u32]),
+        "pbn_sim_set_split": (i32, [vp, i32]),
         "pbn_free": (None, [vp]),
         "pbn_net_get_info": (i32, [vp, ctypes.POINTER(NetInfo)]),
         "pbn_net_thresholds": (i32, [vp, u32, vp, u32]),
@@ -240,10 +246,10 @@ class _Patterns:
 
 
 def make_opts(method: str = "two_state", psi0: int = 256, psrf_max: float = 1.1, eps: float = 1e-10,
-              max_len: int = 0) -> Opts:
+              max_len: int = 0, thin: int = 1) -> Opts:
     code = {"two_state": TWO_STATE, "skart": SKART, "sequential": SEQ_TWO_STATE,
             "sequential_skart": SEQ_SKART}[method]
-    return Opts(code, psi0, psrf_max, eps, max_len)
+    return Opts(code, psi0, psrf_max, eps, max_len, thin, 0)
 
 
 # ------------------------------------------------------------ objects
@@ -251,10 +257,13 @@ def make_opts(method: str = "two_state", psi0: int = 256, psrf_max: float = 1.1,
 class Network:
     """A parsed and compiled network (host memory)."""
 
-    def __init__(self, text: str):
+    def __init__(self, text: str = None, path: str = None):
         h = ctypes.c_void_p()
-        b = text.encode()
-        _check(lib().pbn_load(b, len(b), ctypes.byref(h)))
+        if path is not None:
+            _check(lib().pbn_load_file(os.fsencode(path), ctypes.byref(h)))
+        else:
+            b = text.encode()
+            _check(lib().pbn_load(b, len(b), ctypes.byref(h)))
         self._h = h
         info = NetInfo()
         _check(lib().pbn_net_get_info(h, ctypes.byref(info)))
@@ -314,6 +323,15 @@ class Simulation:
 
     def run(self, steps: int, burn_in: int = 0, thin: int = 1) -> None:
         _check(lib().run_chains(self._h, burn_in, steps, thin))
+
+    def set_kernel(self, mode: str = "global", waves: int = 0) -> None:
+        """This simulation's kernel choice ("global": the process-wide one)."""
+        code = {"global": -1, "auto": 0, "lane": 1, "bitsliced": 2}[mode]
+        _check(lib().pbn_sim_set_kernel(self._h, code, waves))
+
+    def set_split(self, parts: int = -1) -> None:
+        """This simulation's node-split parts (-1: the process-wide setting)."""
+        _check(lib().pbn_sim_set_split(self._h, parts))
 
     def sync(self) -> None:
         _check(lib().pbn_sim_sync(self._h))

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -104,6 +105,21 @@ int pbn_load(const char *text, size_t len, pbn_net **out)
     if (rc) return fail(rc, err);
     *out = net.release();
     return PBN_OK;
+}
+
+int pbn_load_file(const char *path, pbn_net **out)
+{
+    if (!path || !out) return fail(PBN_EINVAL, "null argument");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(PBN_EINVAL, std::string("cannot open ") + path);
+    std::string text;
+    char buf[1 << 16];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+    const bool bad = std::ferror(f) != 0;
+    std::fclose(f);
+    if (bad) return fail(PBN_EINVAL, std::string("cannot read ") + path);
+    return pbn_load(text.data(), text.size(), out);
 }
 
 void pbn_free(pbn_net *net) { delete net; }
@@ -349,6 +365,7 @@ int pbn_batch_estimate(pbn_sim *const *sims, uint32_t count, const pbn_pattern *
     if (rc0) return fail(rc0, err);
     for (uint32_t i = 0; i < count; ++i) {
         runs[i].sim = sims[i];
+        sims[i]->thin = opts && opts->thin > 1 ? opts->thin : 1;
         const pbn::MachineParams P = pbn::make_params(sims[i], opts, r[i], conf[i]);
         for (uint32_t q = 0; q < nprops[i]; ++q) runs[i].machines.emplace_back(P, q);
     }
@@ -548,6 +565,7 @@ int pbn_server_step(pbn_server *srv, uint32_t *active, uint32_t *waiting, uint32
             retire(rq, rc);
             continue;
         }
+        rq->sim->thin = rq->opts.thin > 1 ? rq->opts.thin : 1;
         admitted.push_back(rq);
     }
     srv->queue.swap(still);
@@ -643,6 +661,23 @@ int pbn_set_kernel(int mode, uint32_t waves)
 int pbn_set_split(uint32_t parts)
 {
     pbn::set_split_mode(parts);
+    return PBN_OK;
+}
+
+int pbn_sim_set_kernel(pbn_sim *sim, int mode, uint32_t waves)
+{
+    if (!sim || mode < -1 || mode > 2 ||
+        (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 16))
+        return fail(PBN_EINVAL, "mode must be -1..2 and waves 0, 1, 2, 4, 8 or 16");
+    sim->kmode = mode;
+    sim->kwaves = mode < 0 ? 0 : waves;
+    return PBN_OK;
+}
+
+int pbn_sim_set_split(pbn_sim *sim, int parts)
+{
+    if (!sim || parts < -1) return fail(PBN_EINVAL, "parts must be -1 or more");
+    sim->split = parts;
     return PBN_OK;
 }
 

@@ -120,10 +120,9 @@ int Workspace::ensure_split(size_t groups, size_t xch_words, std::string &err)
         if (d_grp) (void)hipFree(d_grp);
         if (h_grp) (void)hipHostFree(h_grp);
         if (d_ctr) (void)hipFree(d_ctr);
-        if (d_stat) (void)hipFree(d_stat);
         if (h_stat) (void)hipHostFree(h_stat);
         d_grp = h_grp = nullptr;
-        d_ctr = d_stat = h_stat = nullptr;
+        d_ctr = h_stat = nullptr;
         cap_grp = 0;
         // group q: arrival counter at word 2q, status word at 2q + 1 (one
         // clear and one download per launch)
@@ -134,7 +133,6 @@ int Workspace::ensure_split(size_t groups, size_t xch_words, std::string &err)
             err = "workspace split groups";
             return PBN_ENOMEM;
         }
-        d_stat = d_ctr;
         cap_grp = nc;
     }
     if (xch_words > cap_xch) {
@@ -217,7 +215,7 @@ void Workspace::release()
     if (h_stat) (void)hipHostFree(h_stat);
     d_grp = h_grp = nullptr;
     d_xch = nullptr;
-    d_ctr = d_stat = h_stat = nullptr;
+    d_ctr = h_stat = nullptr;
     cap_grp = cap_xch = 0;
     split_used = 0;
     split_items.clear();
@@ -365,6 +363,7 @@ void Machine::not_converged(uint64_t chain_len)
 void Machine::feed_window(const WindowResult &w, uint64_t chain_len)
 {
     const uint32_t omega = P_.omega;
+    ++res_.rounds;
     switch (st_) {
     case kGR: {
         bool defined;
@@ -483,6 +482,7 @@ void Machine::feed_window(const WindowResult &w, uint64_t chain_len)
         res_.M = M_;
         res_.n = N_;
         res_.N = N_;
+        res_.sample_size = N_;
         res_.prob = (double)w.T1 / (double)N_;
         res_.chain_len = l_;
         done_ = true;
@@ -495,6 +495,7 @@ void Machine::feed_window(const WindowResult &w, uint64_t chain_len)
 void Machine::feed_batch(const int32_t *bsum, uint64_t chain_len)
 {
     const uint32_t omega = P_.omega;
+    ++res_.rounds;
     const uint64_t m = p_ / omega;
     if (st_ == kSkartRandomness) {
         if (randomness_passes(batch_moments(bsum, omega, m)) || tries_ >= 10) {
@@ -564,6 +565,7 @@ void Machine::skart_ci(const int32_t *bsum, uint64_t chain_len)
     res_.kappa = kappa_;
     res_.batches = p_;
     res_.n = kappa_ * m;
+    res_.sample_size = kappa_ * p_;
     res_.chain_len = base_ + res_.n;
     res_.psi = base_;
     done_ = true;
@@ -583,6 +585,7 @@ void Machine::finish_two_state(int64_t T1)
     res_.psi = psi_;
     res_.n = n_;
     res_.N = N_;
+    res_.sample_size = (uint64_t)P_.omega * n_;
     res_.prob = (double)T1 / (double)((uint64_t)P_.omega * n_);
     res_.chain_len = psi_ + n_;
     done_ = true;
@@ -621,6 +624,7 @@ int sim_setup(pbn_sim *sim, const Net &net, uint32_t omega, uint64_t seed, uint3
     sim->dbuf = (uint8_t *)dev_buf;
     sim->dbytes = dev_bytes;
     sim->stream = stream;
+    if (hipGetDevice(&sim->device) != hipSuccess) { err = "hipGetDevice"; return PBN_EDEVICE; }
     uint8_t *p = sim->dbuf;
     sim->d_desc = (DevSim *)p;
     p += a256(sizeof(DevSim));
@@ -763,7 +767,7 @@ void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t t
         it.ops_per_step = (float)sim->net.ops_per_step;
         it.philox_per_step = (float)sim->net.philox_per_step;
         it.owner = sim;
-        choose_kernel(sim->net, it, latency);
+        choose_kernel(sim, it, latency);
         items.push_back(it);
     }
     sim->t_done += burn_in + steps * thin;
@@ -800,7 +804,7 @@ void set_split_spins(uint32_t polls) { g_split_spins = polls ? polls : kSplitSpi
 uint64_t latency_waves(const pbn_sim *sim)
 {
     StepItem probe{};
-    choose_kernel(sim->net, probe, true);
+    choose_kernel(sim, probe, true);
     return (uint64_t)((sim->omega + 63) / 64) * (probe.kernel ? probe.kernel : 1);
 }
 
@@ -812,17 +816,22 @@ uint32_t waves_for(uint32_t n, bool latency)
     return n < 40 ? 2 : n < 900 ? 4 : 8;
 }
 
-void choose_kernel(const Net &net, StepItem &it, bool latency)
+int kernel_mode_of(const pbn_sim *sim) { return sim && sim->kmode >= 0 ? sim->kmode : g_kernel_mode.load(); }
+uint32_t waves_override_of(const pbn_sim *sim) { return sim && sim->kmode >= 0 ? sim->kwaves : g_waves_override.load(); }
+uint32_t split_mode_of(const pbn_sim *sim) { return sim && sim->split >= 0 ? (uint32_t)sim->split : g_split_mode.load(); }
+
+void choose_kernel(const pbn_sim *sim, StepItem &it, bool latency)
 {
+    const Net &net = sim->net;
     it.kernel = 0;
     it.lds = 0;
     it.small = 0;
-    if (g_kernel_mode == 1 || !net.bitsliced) return;
-    const uint32_t forced = g_waves_override.load();
+    if (kernel_mode_of(sim) == 1 || !net.bitsliced) return;
+    const uint32_t forced = waves_override_of(sim);
     uint32_t G = forced ? forced : waves_for(net.n, latency);
     size_t lds = bs_lds_bytes(net.n, net.msel_total, G);
     // a shape whose LDS does not fit falls back to fewer waves
-    while (lds > 160 * 1024 && G > 1 && !g_waves_override) {
+    while (lds > 160 * 1024 && G > 1 && !forced) {
         G /= 2;
         lds = bs_lds_bytes(net.n, net.msel_total, G);
     }
@@ -920,9 +929,11 @@ int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, 
         for (size_t i = 0; i < items.size(); ++i) {
             const StepItem &it = items[i];
             if (it.kernel == 0 || !it.owner || it.nchains == 0) continue;
-            const uint32_t nblk = ((const pbn_sim *)it.owner)->net.nblk;
-            if (g_split_mode >= 2) {
-                const uint32_t P = std::min(std::min(g_split_mode.load(), kSplitMaxParts), nblk);
+            const pbn_sim *owner = (const pbn_sim *)it.owner;
+            const uint32_t nblk = owner->net.nblk, mode = split_mode_of(owner);
+            if (mode == 1) continue;
+            if (mode >= 2) {
+                const uint32_t P = std::min(std::min(mode, kSplitMaxParts), nblk);
                 if (P >= 2 && blocks + P - 1 <= kCus) {
                     parts[i] = P;
                     blocks += P - 1;
@@ -937,7 +948,7 @@ int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, 
                 parts[i] = std::min(items[i].parts_hint, kSplitMaxParts);
                 hinted = true;
             }
-        if (g_split_mode == 0 && !hinted && items.size() < kCus && !cand.empty()) {
+        if (!hinted && items.size() < kCus && !cand.empty()) {
             auto work = [&](size_t i) {
                 const StepItem &it = items[i];
                 return (double)it.nodes * (double)(it.nburn + (uint64_t)it.nrec * it.thin) / (double)parts[i];
@@ -974,12 +985,13 @@ int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, 
         const uint32_t per = (nblk + P - 1) / P;
         uint32_t G = 16;
         while (G > 1 && G > per) G /= 2;
-        if (g_waves_override) G = g_waves_override;
+        const uint32_t forced = waves_override_of(sim);
+        if (forced) G = forced;
         pbn_sim::SplitTab tab;
         int rc = split_table(sim, P, tab, err);
         if (rc) return rc;
         size_t lds = split_lds_bytes(sim->net.n, tab.n_own, tab.m_own, G);
-        while (lds > 160 * 1024 && G > 1 && !g_waves_override) {
+        while (lds > 160 * 1024 && G > 1 && !forced) {
             G /= 2;
             lds = split_lds_bytes(sim->net.n, tab.n_own, tab.m_own, G);
         }
@@ -1017,7 +1029,7 @@ int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, 
         xoff += 2 * (size_t)sim->net.n + 2 * (size_t)p.P;
         // the whole group in its one-block latency shape, should it give up
         StepItem whole = items[i];
-        choose_kernel(sim->net, whole, true);
+        choose_kernel(sim, whole, true);
         whole.part = 0;
         whole.grp = nullptr;
         whole.parts_hint = 0;
@@ -1046,7 +1058,7 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
     int rc = ws.before_write(ws.ev_items, ws.items_in_flight, err);
     if (rc) return rc;
     size_t nsplit = 0;
-    if (allow_split && g_split_mode != 1 && (rc = split_expand(items, ws, err, nsplit))) return rc;
+    if (allow_split && (rc = split_expand(items, ws, err, nsplit))) return rc;
     // groups of equal kernel form; inside a group the longest
     // items first, since the hardware dispatches blocks roughly in order
     struct Key { uint32_t kernel, cls; double cost; size_t idx; };
@@ -1338,11 +1350,11 @@ MachineParams make_params(const pbn_sim *sim, const pbn_opts *opts, double r, do
 // single-block timings: about 2.5 us plus 0.17 us per node and wave (0.25 us
 // with 16 waves, whose barriers cost more); about 1 us per node for the
 // lane-per-chain kernel.
-double step_latency_us(const Net &net, bool latency)
+double step_latency_us(const pbn_sim *sim, bool latency)
 {
     StepItem probe{};
-    choose_kernel(net, probe, latency);
-    const double n = net.n;
+    choose_kernel(sim, probe, latency);
+    const double n = sim->net.n;
     const double per = probe.kernel == 16 ? 0.25 : 0.17;
     return probe.kernel ? 2.5 + per * n / probe.kernel : 1.0 + 1.0 * n;
 }
@@ -1361,6 +1373,7 @@ static void plan_parts(const std::vector<std::pair<pbn_sim *, uint64_t>> &ext, s
     uint64_t spare = kCus - used;
     auto cap = [&](size_t k) {
         const Net &net = ext[k].first->net;
+        if (split_mode_of(ext[k].first) != 0) return 1u;
         return net.bitsliced ? std::min<uint32_t>(kSplitMaxParts, net.nblk / 8) : 1u;
     };
     auto work = [&](size_t k) { return (double)ext[k].first->net.n * (double)ext[k].second / parts[k]; };
@@ -1384,9 +1397,11 @@ static void plan_parts(const std::vector<std::pair<pbn_sim *, uint64_t>> &ext, s
 // about 6 us of exchange plus the one-block time over the parts.
 uint64_t slice_len(const pbn_sim *sim, double tick_us, bool latency, uint32_t parts)
 {
-    double us = step_latency_us(sim->net, latency);
-    if (g_split_mode >= 2) parts = std::min(std::min(g_split_mode.load(), kSplitMaxParts), sim->net.nblk);
-    if (latency && parts >= 2 && g_split_mode != 1 && sim->net.bitsliced) us = std::min(us, 6.0 + us / parts);
+    double us = step_latency_us(sim, latency);
+    const uint32_t mode = split_mode_of(sim);
+    if (mode >= 2) parts = std::min(std::min(mode, kSplitMaxParts), sim->net.nblk);
+    if (latency && parts >= 2 && mode != 1 && sim->net.bitsliced) us = std::min(us, 6.0 + us / parts);
+    us *= sim->thin;                  // a slice counts recorded positions, each thin transitions long
     const double q = std::floor(tick_us / us / 32.0) * 32.0;
     return (uint64_t)std::max(32.0, q);
 }
@@ -1418,20 +1433,23 @@ int round_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, 
         }
         if (!ready) {
             if (target > sim->max_len) { err = "request beyond the bit-stream capacity"; return PBN_ELIMIT; }
-            if (sim->t_done + (target - sim->len) >= (1ull << 32)) { err = "transition index limit"; return PBN_ELIMIT; }
+            if (target - sim->len > ((1ull << 32) - 1 - sim->t_done) / sim->thin) {
+                err = "transition index limit";
+                return PBN_ELIMIT;
+            }
             ext.push_back({sim, target - sim->len});
         }
     }
     // node-split parts per simulation (time-sliced rounds that own the device),
     // decided before slicing so that each slice is about tick_us long
     std::vector<uint32_t> parts(ext.size(), 1);
-    if (tick_us > 0.0 && allow_fork && latency && g_split_mode == 0) plan_parts(ext, parts);
+    if (tick_us > 0.0 && allow_fork && latency) plan_parts(ext, parts);
     for (size_t k = 0; k < ext.size(); ++k) {
         pbn_sim *sim = ext[k].first;
         uint64_t e = ext[k].second;
         if (tick_us > 0.0) e = std::min(e, slice_len(sim, tick_us, latency != 0, allow_fork ? parts[k] : 1));
         const size_t first = items.size();
-        sim_extend_items(sim, 0, e, 1, items, latency != 0);
+        sim_extend_items(sim, 0, e, sim->thin, items, latency != 0);
         for (size_t i = first; i < items.size(); ++i) items[i].parts_hint = parts[k];
     }
     int rc = launch_items(items, ws, stream, err, allow_fork, allow_fork);
@@ -1616,7 +1634,7 @@ int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
         }
         for (SimRun *r : order) {
             const uint64_t first = r->machines.empty() ? 0 : r->machines[0].request().need_len;
-            const double serial = (double)first * step_latency_us(r->sim->net, false);
+            const double serial = (double)first * step_latency_us(r->sim, false);
             if (serial > 0.25 * bulk_us) crit.push_back({serial, r});
         }
         std::stable_sort(crit.begin(), crit.end(),
@@ -1635,7 +1653,7 @@ int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
     }
     for (SimRun *r : order) {
         StepItem probe{};
-        choose_kernel(r->sim->net, probe, false);
+        choose_kernel(r->sim, probe, false);
         const int k = probe.kernel == 8 ? 0 : probe.kernel == 4 ? 1 : 2;
         P.lane[k]->runs.push_back(r);
     }

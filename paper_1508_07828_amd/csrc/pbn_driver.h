@@ -36,10 +36,11 @@ struct Workspace {
     int after_copy(hipEvent_t &ev, bool &in_flight, hipStream_t stream, std::string &err);
     int ensure_stage(size_t count, std::string &err);
     // node-split form: group descriptors (pinned staging, device), exchange
-    // area, arrival counters and the groups' status words of the last launch
+    // area, and per group an arrival counter and a status word (d_ctr[2q],
+    // d_ctr[2q + 1]; the last launch's copied to h_stat)
     SplitGroup *d_grp = nullptr, *h_grp = nullptr;
     uint64_t *d_xch = nullptr;
-    uint32_t *d_ctr = nullptr, *d_stat = nullptr, *h_stat = nullptr;
+    uint32_t *d_ctr = nullptr, *h_stat = nullptr;
     size_t cap_grp = 0, cap_xch = 0;
     // the last launch's node-split groups as whole 64-chain items (one-block
     // shapes) and its stream, for the re-run of a group that gave up; the
@@ -131,6 +132,12 @@ struct pbn_sim {
     uint8_t *dbuf = nullptr;
     size_t dbytes = 0;
     hipStream_t stream = nullptr;
+    int device = -1;              // the device current when the simulation was created
+    // kernel and node-split choice of this simulation's launches (-1: the
+    // process-wide setting), and the transitions per recorded position of its
+    // estimates
+    int kmode = -1, split = -1;
+    uint32_t kwaves = 0, thin = 1;
     pbn::DevSim desc{};
     pbn::DevSim *d_desc = nullptr;
     uint64_t len = 0, t_done = 0;
@@ -228,8 +235,9 @@ int profile_collect(pbn_profile *out, std::string &err);
 void profile_set(bool on);
 void profile_clear();
 
-// Kernel selection for a step item (see pbn_driver.cpp) and its override.
-void choose_kernel(const Net &net, StepItem &it, bool latency);
+// Kernel selection for a step item of sim (see pbn_driver.cpp): the
+// simulation's own setting, else the process-wide one.
+void choose_kernel(const pbn_sim *sim, StepItem &it, bool latency);
 // Autotuner (pbn_tune.cpp): measured shapes per size bucket, if measured.
 bool tuned_waves(uint32_t n, bool latency, uint32_t *G);
 int autotune(hipStream_t stream, pbn_tune_row *rows, uint32_t cap, uint32_t *count, std::string &err);

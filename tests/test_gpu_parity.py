@@ -689,3 +689,82 @@ def test_rejects_bad_arguments():
     with pytest.raises(pkg.PbnError) as e:
         pkg.Server(64 << 20).submit(net, (1 << 24) + 1, 1, [((0, 1),)], 0.02)
     assert e.value.code == pkg.PBN_ELIMIT
+
+
+@pytest.mark.parametrize("method", ["two_state", "skart"])
+def test_estimate_with_thinning(method):
+    """pbn_opts.thin = 3: the procedures run on every third state of the
+    chains; every result equals the oracle's on its thinned chains, and the
+    sample size is omega n."""
+    net, omega, pats = CASES["ragged_k6_p05"]()
+    text = ps.to_text(net)
+    say("estimate with thin 3, " + method)
+    sim = pkg.Simulation(pkg.Network(text), omega, 313, max_props=2, max_len=CAP)
+    got = sim.estimate(pats[:2], 0.02, 0.95, method=method, psrf_max=1.1, thin=3)
+    want = drivers.solve(text, omega, 313, pats[:2], 0.02, 0.95, 1.1, method=method, cap=CAP, thin=3)
+    for q in range(2):
+        assert_same_result(got[q], want[q], (method, q))
+        assert got[q]["sample_size"] == omega * want[q]["n"] and got[q]["rounds"] >= 2
+    # the chains made three transitions per recorded position
+    L, T = sim.position()
+    assert T == 3 * L
+
+
+def test_kernel_choice_per_simulation():
+    """Per-simulation kernel and node-split choices override the process-wide
+    ones for that simulation only; results equal the oracle's either way."""
+    net, omega, pats = CASES["n300_l4"]()
+    text = ps.to_text(net)
+    nw = pkg.Network(text)
+    a = pkg.Simulation(nw, omega, 21, max_props=1, max_len=4096)
+    b = pkg.Simulation(nw, omega, 21, max_props=1, max_len=4096)
+    a.set_kernel("lane")
+    b.set_split(3)
+    pkg.set_kernel("bitsliced", 2)
+    pkg.profile_reset()
+    pkg.profile_enable(True)
+    try:
+        say("per-simulation kernel choice: lane-per-chain beside 3 parts")
+        for s in (a, b):
+            s.reset(pats)
+            s.run(150)
+        prof = pkg.profile_read()
+    finally:
+        pkg.profile_enable(False)
+        pkg.set_kernel("auto", 0)
+    ch = oracle.Chains(oracle.Net(text), omega, 21, pats)
+    ch.extend(150)
+    for s in (a, b):
+        assert np.array_equal(s.read_state(), ch.states)
+        assert np.array_equal(s.read_bits(0, 0, 150), ch.bits[0])
+    assert prof["split_launches"] >= 1
+    a.set_kernel("global")
+    b.set_split(-1)
+    with pytest.raises(pkg.PbnError):
+        a.set_kernel("bitsliced", 3)
+
+
+def test_split_workspace_grows():
+    """Launches whose node-split groups outnumber the previous launch's make
+    the workspace grow its group tables; later launches still run and every
+    chain equals the oracle's (a regression test: the growth once freed one
+    buffer twice, and the next launch failed)."""
+    cases = ["n300_l4", "ragged_l6_k5", "medium"]
+    nets = [CASES[c]() for c in cases]
+    texts = [ps.to_text(n) for n, _, _ in nets]
+    sims = [pkg.Simulation(pkg.Network(t), 64, 500 + i, max_props=1, max_len=1024) for i, t in enumerate(texts)]
+    for s, (_, _, p) in zip(sims, nets):
+        s.reset(p[:1])
+    pkg.set_split(2)
+    try:
+        say("split workspace growth: 1 group, then 3, then 3 again")
+        pkg.batch_run(sims[:1], [40])
+        pkg.batch_run(sims, [40, 80, 80])
+        pkg.batch_run(sims, [20, 20, 20])
+    finally:
+        pkg.set_split(0)
+    for i, (s, t, (_, _, p)) in enumerate(zip(sims, texts, nets)):
+        ch = oracle.Chains(oracle.Net(t), 64, 500 + i, p[:1])
+        ch.extend(s.position()[0])
+        assert np.array_equal(s.read_state(), ch.states), cases[i]
+        assert np.array_equal(s.read_bits(0, 0, ch.length), ch.bits[0]), cases[i]

@@ -32,7 +32,7 @@ def test_exports_match_header():
     hdr = open(os.path.join(ROOT, "include", "pbnssa.h")).read()
     hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
     names = set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", hdr)) - {"sizeof", "if", "for", "while"}
-    names = {n for n in names if n.startswith("pbn_") or n in ("run_chains", "psrf", "estimate_prob")}
+    names = {n for n in names if n.startswith("pbn_") or n.startswith("run_chains") or n in ("psrf", "estimate_prob")}
     assert len(names) >= 25
     L = pkg.lib()
     for n in sorted(names):
@@ -201,3 +201,19 @@ def test_skart_stats_rejects():
     with pytest.raises(pkg.PbnError) as e:
         pkg.skart_batch_stats(b, 1 << 34, 0.95)
     assert e.value.code == pkg.PBN_ELIMIT
+
+
+def test_load_file(tmp_path):
+    """Loading from a file gives the network loading its text gives; an
+    unreadable path is PBN_EINVAL."""
+    text = ps.to_text(ps.medium().net)
+    f = tmp_path / "medium.pbn"
+    f.write_text(text)
+    a, b = pkg.Network(text), pkg.Network(path=str(f))
+    assert (a.n, a.W, a.info.nfun, a.info.p_thr, a.info.blob_bytes) == (b.n, b.W, b.info.nfun, b.info.p_thr,
+                                                                        b.info.blob_bytes)
+    for i in range(a.n):
+        assert a.thresholds(i) == b.thresholds(i)
+    with pytest.raises(pkg.PbnError) as e:
+        pkg.Network(path=str(tmp_path / "missing.pbn"))
+    assert e.value.code == pkg.PBN_EINVAL
