@@ -189,6 +189,22 @@ int pbn_sim_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops);
  * the bit-stream capacity or the 2^32 transition limit would be exceeded. */
 int run_chains(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): run_chains with the same
+ * arguments, results and errors, making no allocation of any kind.  Its launch
+ * table (one entry per 64-chain group) lives in a fixed device array of the
+ * library (PBN_NOALLOC_MAX_CHAINS / 64 entries, 384 KiB per device, held until
+ * the process ends) and is written on the device, so no host-to-device copy is
+ * made either.  Asynchronous on the simulation's stream; the simulation's
+ * device must be current.  Limits: at most PBN_NOALLOC_MAX_CHAINS chains
+ * (PBN_ELIMIT beyond); networks whose lane-per-chain rows exceed LDS (more
+ * than 10240 nodes with a predictor of more than 6 parents) are PBN_ELIMIT;
+ * the node-split form is not used.  Every call on one device shares that
+ * device's array: calls that overlap on one device (other streams or threads)
+ * race, so the caller serialises them. */
+#define PBN_NOALLOC_MAX_CHAINS (1u << 18)
+int run_chains_noalloc(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin);
+
 /* Gelman-Rubin R (Alg. 3) of state set `prop` over the last psi recorded
  * positions of every chain (positions len-psi+1..len).  Synchronises.
  * *rhat = +inf when the within-chain variance W is 0. */

@@ -28,7 +28,7 @@ EXPORTS = (
     "pbn_batch_run", "pbn_batch_estimate", "pbn_server_create", "pbn_server_free", "pbn_server_submit",
     "pbn_server_step", "pbn_server_poll", "pbn_server_memory", "pbn_normal_quantile", "pbn_t_quantile",
     "pbn_last_error", "pbn_profile_enable", "pbn_profile_read", "pbn_profile_reset", "pbn_set_kernel", "pbn_set_split", "pbn_set_split_polls",
-    "pbn_autotune", "pbn_autotune_reset", "pbn_skart_batch_stats", "pbn_load_file",
+    "pbn_autotune", "pbn_autotune_reset", "pbn_skart_batch_stats", "run_chains_noalloc", "pbn_load_file",
     "pbn_sim_set_kernel", "pbn_sim_set_split",
 )
 
@@ -113,6 +113,7 @@ def lib():
         "pbn_sim_free": (None, [vp]),
         "pbn_sim_reset": (i32, [vp, ctypes.POINTER(Pattern), u32]),
         "run_chains": (i32, [vp, u64, u64, u32]),
+        "run_chains_noalloc": (i32, [vp, u64, u64, u32]),
         "psrf": (i32, [vp, u32, u64, ctypes.POINTER(dbl)]),
         "pbn_window_counts": (i32, [vp, u32, u64, u64, ctypes.POINTER(Counts)]),
         "pbn_batch_sums": (i32, [vp, u32, u64, u64, u64, vp]),
@@ -332,6 +333,10 @@ class Simulation:
     def set_split(self, parts: int = -1) -> None:
         """This simulation's node-split parts (-1: the process-wide setting)."""
         _check(lib().pbn_sim_set_split(self._h, parts))
+
+    def run_noalloc(self, steps: int, burn_in: int = 0, thin: int = 1) -> None:
+        """run_chains_noalloc: the same extension, with no allocation."""
+        _check(lib().run_chains_noalloc(self._h, burn_in, steps, thin))
 
     def sync(self) -> None:
         _check(lib().pbn_sim_sync(self._h))

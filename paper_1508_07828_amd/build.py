@@ -9,8 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpbnssa.so")
-SOURCES = ["pbn_kernels.hip", "pbn_step_bs.hip", "pbn_net.cpp", "pbn_stats.cpp", "pbn_driver.cpp", "pbn_api.cpp",
-           "pbn_tune.cpp"]
+SOURCES = ["pbn_kernels.hip", "pbn_step_bs.hip", "pbn_noalloc.hip", "pbn_net.cpp", "pbn_stats.cpp", "pbn_driver.cpp",
+           "pbn_api.cpp", "pbn_tune.cpp"]
 ARCH = os.environ.get("PBN_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

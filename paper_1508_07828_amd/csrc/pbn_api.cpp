@@ -199,6 +199,17 @@ int run_chains(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin)
     return rc ? fail(rc, err) : PBN_OK;
 }
 
+int run_chains_noalloc(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin)
+{
+    if (!sim || thin < 1) return fail(PBN_EINVAL, "bad argument");
+    if (!fits(sim->len, steps, 1, position_cap(sim))) return fail(PBN_ELIMIT, "bit-stream capacity exceeded");
+    if (!fits(sim->t_done, burn_in, 1, kMaxTransition) || !fits(sim->t_done + burn_in, steps, thin, kMaxTransition))
+        return fail(PBN_ELIMIT, "transition index limit (2^32)");
+    std::string err;
+    const int rc = pbn::run_chains_noalloc_impl(sim, burn_in, steps, thin, err);
+    return rc ? fail(rc, err) : PBN_OK;
+}
+
 int psrf(pbn_sim *sim, uint32_t prop, uint64_t psi, double *rhat)
 {
     if (!sim || !rhat || psi < 2 || psi > sim->len || sim->omega < 2) return fail(PBN_EINVAL, "bad argument");

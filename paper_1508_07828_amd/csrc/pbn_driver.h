@@ -252,6 +252,11 @@ void set_split_spins(uint32_t polls);
 // Node-split groups re-run in the one-block form after a give-up (process-wide).
 uint64_t split_fallbacks();
 
+// run_chains without allocation (pbn_noalloc.hip): the launch table lives in
+// a fixed device array; at most PBN_NOALLOC_MAX_CHAINS chains, no node-split
+// form, no device scratch rows.
+int run_chains_noalloc_impl(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin, std::string &err);
+
 // Launch step items for several sims (sorted by cost) on stream.  allow_split:
 // the launch owns the device (nothing else runs beside it that could hold the
 // CUs its node-split groups wait for), so latency-bound 64-chain groups may
