@@ -61,11 +61,12 @@ def node_updates_of(sims, jobs):
     return float(sum(s.position()[1] * j.chains * j.net.n for s, j in zip(sims, jobs)))
 
 
-def run_serving(pkg, torch, seconds, rate, arena_bytes, serial_budget_s=20.0):
-    jobs = ps.serving(duration_s=seconds, rate=rate)
+def run_serving(pkg, torch, seconds, rate, arena_bytes, serial_budget_s=20.0, sched=None):
+    jobs = ps.serving(duration_s=seconds, rate=rate, workers=cpu_threads())
     log("serving: {} requests over {:.1f} s".format(len(jobs), seconds))
-    nets = [pkg.Network(ps.to_text(j.net)) for j in jobs]
+    nets = [pkg.Network(j.text) for j in jobs]
     srv = pkg.Server(arena_bytes)
+    srv.configure(**(sched or {}))
     t0 = time.perf_counter()
     nxt, ids, finish = 0, {}, {}
     pkg.profile_enable(True)
@@ -95,6 +96,7 @@ def run_serving(pkg, torch, seconds, rate, arena_bytes, serial_budget_s=20.0):
     wall = time.perf_counter() - t0
     prof = pkg.profile_read()
     pkg.profile_enable(False)
+    long_moved, long_rounds = srv.lane_stats()
     lat = np.array([finish[i] - jobs[i].arrival for i in range(len(jobs))])
     results = [srv.poll(ids[i]) for i in range(len(jobs))]
     _, peak_mem = srv.memory()
@@ -122,11 +124,50 @@ def run_serving(pkg, torch, seconds, rate, arena_bytes, serial_budget_s=20.0):
         requests=len(jobs), arrival_rate_per_s=rate, arrival_seconds=seconds, wall_s=wall, rounds=rounds,
         p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
         queries_per_s=len(jobs) / wall, node_updates_per_s=prof["node_updates"] / wall,
+        # the trajectory kernels' algorithmic operations over the serving wall time
+        roofline={"bound": "alu", "achieved": prof["alg_ops"] / wall / 1e12, "peak": PEAK_INT32_OPS / 1e12,
+                  "unit": "Tops/s", "frac": prof["alg_ops"] / wall / PEAK_INT32_OPS,
+                  "kernel_frac": prof["alg_ops"] / max(prof["kernel_ms"] / 1e3, 1e-12) / PEAK_INT32_OPS,
+                  "launches": int(prof["launches"]), "split_launches": int(prof["split_launches"])},
         not_converged=int(sum(r[0]["status"] != 0 for r in results)),
+        long_lane_requests=long_moved, long_lane_rounds=long_rounds,
+        split_fallbacks=int(prof["split_fallbacks"]),
         arena_bytes=arena_bytes, arena_peak_bytes=peak_mem,
-        serial_first_k=k, serial_p50_ms=float(np.percentile(serial_lat, 50) * 1e3),
-        serial_p99_ms=float(np.percentile(serial_lat, 99) * 1e3),
+        serial_first_k=k,
+        serial_p50_ms=float(np.percentile(serial_lat, 50) * 1e3) if k else None,
+        serial_p99_ms=float(np.percentile(serial_lat, 99) * 1e3) if k else None,
     )
+
+
+def run_saturated(pkg, count, arena_bytes):
+    """Capacity: the first `count` requests of the serving trace all queued at
+    once, the server stepped until every one is answered; queries/s and
+    node-updates/s over that wall time."""
+    jobs = ps.serving(duration_s=1e9, rate=200.0, limit=count, workers=cpu_threads())
+    nets = [pkg.Network(j.text) for j in jobs]
+    srv = pkg.Server(arena_bytes)
+    pkg.profile_enable(True)
+    pkg.profile_reset()
+    t0 = time.perf_counter()
+    ids = [srv.submit(nt, j.chains, j.seed, j.patterns, j.r, j.confidence, max_len=MAX_LEN, psrf_max=1.1)
+           for nt, j in zip(nets, jobs)]
+    rounds = 0
+    while True:
+        active, waiting, done = srv.step()
+        rounds += 1
+        if rounds % 100 == 0:
+            log("  saturated round {}: active {} waiting {} done {}".format(rounds, active, waiting, done))
+        if done == len(jobs):
+            break
+    wall = time.perf_counter() - t0
+    prof = pkg.profile_read()
+    pkg.profile_enable(False)
+    nconv = sum(srv.poll(i)[0]["status"] != 0 for i in ids)
+    _, peak_mem = srv.memory()
+    return dict(requests=len(jobs), wall_s=wall, rounds=rounds, queries_per_s=len(jobs) / wall,
+                node_updates_per_s=prof["node_updates"] / wall,
+                roofline_frac=prof["alg_ops"] / wall / PEAK_INT32_OPS, not_converged=int(nconv),
+                arena_peak_bytes=peak_mem)
 
 
 def single_workload(pkg, torch, name: str, steps: int, warmup: int, cpu_s: float, no_cpu: bool) -> dict:
@@ -342,12 +383,21 @@ def roofline_of(prof: dict, total_t: float, batched: bool = True) -> dict:
     return roofline
 
 
+def cpu_threads() -> int:
+    """Host threads for the oracle: every core this process may run on, within
+    the host's stated thread budget (OMP_NUM_THREADS, the CPU share of one GPU
+    on a shared host) when one is set."""
+    cores = len(os.sched_getaffinity(0))
+    budget = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(cores, int(budget))) if budget.isdigit() else max(1, cores)
+
+
 def cpu_baseline(jobs, budget_s: float, label: str = "the batched workload"):
     """The oracle's simulator on the host cores: 256-step extensions of every
     chain of each job in turn until the time budget is spent (a single job is
     extended repeatedly)."""
     import oracle
-    threads = min(os.cpu_count() or 1, 16)
+    threads = cpu_threads()
     done_nu, t_used, used, chunks = 0.0, 0.0, 0, 0
     steps = 256
     for j in jobs:
@@ -364,6 +414,7 @@ def cpu_baseline(jobs, budget_s: float, label: str = "the batched workload"):
             if len(jobs) > 1 or t_used >= budget_s or chunks >= 64:
                 break
     return dict(value=done_nu / t_used, unit="node-updates/s", cores=threads, kind="oracle",
+                nproc=os.cpu_count(), affinity=len(os.sched_getaffinity(0)),
                 sample="{} network(s) of {}, all their chains, {} extension(s) of {} recorded steps "
                        "(CPU simulator with indicator recording, {} threads over chains, {:.1f} s)".format(
                            used, label, chunks, steps, threads, t_used))
@@ -375,8 +426,16 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--count", type=int, default=512)
-    ap.add_argument("--plain-sample", type=int, default=48)
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--plain-sample", type=int, default=0, help="networks of the plain leg (0 = all)")
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--long-lane-us", type=float, default=0.0,
+                    help="server long-request lane threshold in us of kernel time (0 = no long lane)")
+    ap.add_argument("--ahead-us", type=float, default=0.0,
+                    help="server ahead slice in us of kernel time (0 = none)")
+    ap.add_argument("--long-lane-quarters", type=int, default=0,
+                    help="CU share of the server's long-request lane in quarters (0 = default)")
+    ap.add_argument("--saturate", type=int, default=1000,
+                    help="requests of the serving trace queued at once for the capacity figure (0 = skip)")
     ap.add_argument("--serial-seconds", type=float, default=20.0,
                     help="time budget of the serving leg's serial-solve baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -391,11 +450,16 @@ def main() -> int:
                                                          "isolated"],
                     help="batched (default, the headline) or one plain configuration")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter scale)")
+    ap.add_argument("--trace-union", nargs=4, metavar=("TRACE_CSV", "KERNEL", "SOLVES", "OUT"),
+                    help="busy time of a kernel's dispatches in a rocprofv3 kernel trace, per solve")
     ap.add_argument("--traffic-from", nargs=5, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE", "OUT"),
                     help="turn rocprofv3 FETCH_SIZE/WRITE_SIZE runs into bytes per k_step_bs launch")
     args = ap.parse_args()
     if args.traffic_from:
         return traffic_from(*args.traffic_from)
+    if args.trace_union:
+        f, k, n, o = args.trace_union
+        return trace_union(f, k, int(n), o)
     if args.copy_probe:
         return copy_probe()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -472,11 +536,14 @@ def main() -> int:
 
     plain = None
     if not args.no_plain:
-        idx = np.random.default_rng(1).choice(len(jobs), size=min(args.plain_sample, len(jobs)), replace=False)
+        n_plain = len(jobs) if args.plain_sample <= 0 else min(args.plain_sample, len(jobs))
+        idx = np.random.default_rng(1).choice(len(jobs), size=n_plain, replace=False)
         sub = [jobs[i] for i in sorted(idx)]
         _, psims = make_sims(pkg, sub)
-        for s, j in zip(psims, sub):                          # warm each once
-            pass
+        # warm every simulation (its workspace, kernels, tables) with one
+        # untimed estimate; each estimate restarts the chains from s(0)
+        for s, j in zip(psims, sub):
+            s.estimate(j.patterns, j.r, j.confidence, psrf_max=1.1)
         torch.cuda.synchronize()
         a = time.perf_counter()
         for s, j in zip(psims, sub):
@@ -485,15 +552,22 @@ def main() -> int:
         tp = time.perf_counter() - a
         nu = node_updates_of(psims, sub)
         plain = {"value": nu / tp, "unit": "node-updates/s", "networks": len(sub), "seconds": tp,
-                 "note": "one estimate per network, its own launches and synchronisations per round"}
+                 "note": "one estimate per network, its own launches and synchronisations per round; "
+                         "each simulation warmed by one untimed estimate"}
         del psims
         log("plain: {:.3e} node-updates/s over {} networks".format(plain["value"], len(sub)))
 
     serving = None
     if not args.no_serve:
         log("serving")
-        serving = run_serving(pkg, torch, args.serve_seconds, 200.0, 16 << 30, args.serial_seconds)
+        sched = dict(ahead_us=args.ahead_us, long_lane_us=args.long_lane_us, long_quarters=args.long_lane_quarters)
+        serving = run_serving(pkg, torch, args.serve_seconds, 200.0, 16 << 30, args.serial_seconds, sched)
+        serving["schedule"] = sched
         log("serving: p50 {:.1f} ms p99 {:.1f} ms".format(serving["p50_ms"], serving["p99_ms"]))
+        if args.saturate > 0:
+            log("serving, saturated: {} requests at once".format(args.saturate))
+            serving["saturated"] = run_saturated(pkg, args.saturate, 16 << 30)
+            log("saturated: {:.1f} queries/s".format(serving["saturated"]["queries_per_s"]))
 
     cpu = None if args.no_cpu else cpu_baseline(jobs, args.cpu_seconds)
 
@@ -538,6 +612,37 @@ def copy_probe(mib: int = 1024, reps: int = 4) -> int:
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_per_launch": mib << 20, "launches": reps}))
+    return 0
+
+
+def trace_union(trace_csv: str, kernel: str, solves: int, out: str) -> int:
+    """From a rocprofv3 kernel-trace CSV of a run of `solves` batched solves
+    (warm-up and timed; no other legs): the wall time with at least one
+    `kernel` dispatch in flight, and the summed dispatch time, in all and per
+    solve.  Their ratio is the mean number of dispatches in flight (the lanes'
+    launches overlap), and the union per solve against the solve's algorithmic
+    operations gives the chip-wide fraction of the ALU peak."""
+    import csv
+    spans = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+                   for r in csv.DictReader(open(trace_csv)) if kernel in r["Kernel_Name"])
+    union_ns, cur_a, cur_b = 0, None, None
+    for a, b in spans:
+        if cur_b is not None and a <= cur_b:
+            cur_b = max(cur_b, b)
+            continue
+        if cur_b is not None:
+            union_ns += cur_b - cur_a
+        cur_a, cur_b = a, b
+    if cur_b is not None:
+        union_ns += cur_b - cur_a
+    summed_ns = sum(b - a for a, b in spans)
+    info = {"kernel": kernel, "dispatches": len(spans), "solves": solves,
+            "union_ms": union_ns / 1e6, "summed_dispatch_ms": summed_ns / 1e6,
+            "union_ms_per_solve": union_ns / 1e6 / solves, "summed_ms_per_solve": summed_ns / 1e6 / solves,
+            "mean_in_flight": summed_ns / max(union_ns, 1)}
+    with open(out, "w") as fh:
+        json.dump(info, fh, indent=1)
+    print(json.dumps(info))
     return 0
 
 

@@ -253,7 +253,9 @@ int pbn_batch_estimate(pbn_sim *const *sims, uint32_t count, const pbn_pattern *
 
 /* ---------------------------------------------------------------- serving */
 
-/* A server owns a caller-provided device arena of arena_bytes.  Requests are
+/* A server owns a caller-provided device arena of arena_bytes and streams of
+ * its own (non-blocking; the work queued on hip_stream before the call, e.g.
+ * the arena's allocation, comes first).  Requests are
  * admitted when their footprint (pbn_sim_bytes) fits in the free arena; their
  * chains stay on the device across extension rounds; each call to
  * pbn_server_step runs one round for every active request (one batched
@@ -272,6 +274,35 @@ void pbn_server_free(pbn_server *srv);
 int pbn_server_submit(pbn_server *srv, const pbn_net *net, uint32_t omega, uint64_t seed,
                       const pbn_pattern *props, uint32_t nprops, double r, double confidence,
                       const pbn_opts *opts, uint64_t max_len, uint64_t *id);
+/* How a server schedules its rounds (all times are kernel time in
+ * microseconds, as predicted by the library's per-transition model).
+ *   slice_us      extension per request and round (0: 1500); a round lasts
+ *                 about its longest slice, so short requests see rounds of
+ *                 about this length
+ *   ahead_us      behind each round, one more slice of this length for the
+ *                 requests still more than 3000 us short of their requirement,
+ *                 so that the device works while the host takes the round's
+ *                 decisions (0: none, the default)
+ *   long_lane_us  a request whose pending extension exceeds this moves to a
+ *                 lane of its own: a stream restricted to long_quarters
+ *                 quarters of every XCD's CUs (0: 3), whose rounds extend its
+ *                 requests in slices of long_slice_us (0: 20000) and are
+ *                 collected at later steps without holding the other rounds;
+ *                 while it has requests, the other rounds keep to the other
+ *                 CUs (0: no long lane, the default)
+ * Results do not depend on any of these.  The CU share is fixed once the
+ * server has stepped; the lane cannot be turned off while it has requests;
+ * negative values are PBN_EINVAL.  On the serving workload (Poisson 200/s,
+ * n up to 5000) neither ahead slices nor the long lane shortened the tail:
+ * both are off by default. */
+typedef struct {
+    double slice_us, ahead_us, long_lane_us, long_slice_us;
+    uint32_t long_quarters;
+    uint32_t reserved;
+} pbn_server_opts;
+int pbn_server_configure(pbn_server *srv, const pbn_server_opts *opts);
+/* Requests moved to the long lane so far, and the rounds that lane began. */
+int pbn_server_lane_stats(const pbn_server *srv, uint64_t *long_requests, uint64_t *long_rounds);
 /* One round.  *active / *waiting / *done receive the counts after the round.
  * A request that cannot be admitted (its device set-up fails) ends at once,
  * and a failed round ends every request that was in it: such a request is

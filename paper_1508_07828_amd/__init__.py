@@ -29,7 +29,8 @@ EXPORTS = (
     "pbn_server_step", "pbn_server_poll", "pbn_server_memory", "pbn_normal_quantile", "pbn_t_quantile",
     "pbn_last_error", "pbn_profile_enable", "pbn_profile_read", "pbn_profile_reset", "pbn_set_kernel", "pbn_set_split", "pbn_set_split_polls",
     "pbn_autotune", "pbn_autotune_reset", "pbn_skart_batch_stats", "run_chains_noalloc", "pbn_load_file",
-    "pbn_sim_set_kernel", "pbn_sim_set_split",
+    "pbn_sim_set_kernel", "pbn_sim_set_split", "pbn_server_configure",
+    "pbn_server_lane_stats",
 )
 
 
@@ -81,6 +82,11 @@ class Counts(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("T1", "T2", "n00", "n01", "n10", "n11")]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("slice_us", ctypes.c_double), ("ahead_us", ctypes.c_double), ("long_lane_us", ctypes.c_double),
+                ("long_slice_us", ctypes.c_double), ("long_quarters", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
 class SkartStats(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_double), ("ci_lo", ctypes.c_double), ("ci_hi", ctypes.c_double),
                 ("H", ctypes.c_double), ("vn_C", ctypes.c_double), ("vn_limit", ctypes.c_double),
@@ -97,6 +103,11 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError("libpbnssa.so not built: run paper_1508_07828_amd/build.py")
+    # torch first: its HIP runtime is then the one the library binds to (same
+    # soname).  Loaded the other way round, torch would bring a second HIP
+    # runtime into the process, whose device memory and streams the library's
+    # runtime does not know, and the library's first HIP call fails.
+    _torch()
     L = ctypes.CDLL(LIB_PATH)
     vp, u32, u64, i32, dbl, sz = (ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int,
                                   ctypes.c_double, ctypes.c_size_t)
@@ -132,6 +143,8 @@ def lib():
                                     ctypes.POINTER(Opts), u64, ctypes.POINTER(u64)]),
         "pbn_server_step": (i32, [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32)]),
         "pbn_server_poll": (i32, [vp, u64, ctypes.POINTER(i32), ctypes.POINTER(Result)]),
+        "pbn_server_configure": (i32, [vp, ctypes.POINTER(ServerOpts)]),
+        "pbn_server_lane_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]),
         "pbn_server_memory": (i32, [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]),
         "pbn_normal_quantile": (dbl, [dbl]),
         "pbn_t_quantile": (dbl, [dbl, dbl]),
@@ -443,6 +456,19 @@ class Server:
                                        ctypes.byref(o), max_len, ctypes.byref(rid)))
         self._nprops[rid.value] = P.count
         return int(rid.value)
+
+    def configure(self, slice_us: float = 0.0, ahead_us: float = 0.0, long_lane_us: float = 0.0,
+                  long_slice_us: float = 0.0, long_quarters: int = 0) -> None:
+        """Round scheduling (see pbn_server_configure; 0 keeps a default)."""
+        o = ServerOpts(float(slice_us), float(ahead_us), float(long_lane_us), float(long_slice_us),
+                       int(long_quarters), 0)
+        _check(lib().pbn_server_configure(self._h, ctypes.byref(o)))
+
+    def lane_stats(self) -> Tuple[int, int]:
+        """(requests moved to the long lane, rounds it began)."""
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().pbn_server_lane_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
 
     def step(self) -> Tuple[int, int, int]:
         a, w, d = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()

@@ -455,28 +455,128 @@ struct ServeReq {
 
 }  // namespace
 
+// Long-request lane of the server.  A request whose pending extension would
+// take more than kLongUs of kernel time moves to a lane of its own: a stream
+// restricted to a share of the CUs (kLongQuarters quarters of every XCD's),
+// whose rounds run in slices of kLongTickUs beside the short requests' rounds
+// and are collected when they complete, without holding those rounds.  While
+// it has requests, the short requests' launches keep to the other CUs (a
+// masked stream pool), so each lane's node-split groups have their CUs to
+// themselves.  The long requests are few but carry most of the work (on the
+// serving trace 7% of the requests, 74% of the node-updates), hence three
+// quarters of the CUs by default.
+constexpr double kLongTickUs = 20000.0;
+constexpr uint32_t kLongQuarters = 3;
+// Ahead slices (off by default): behind each round, the requests still more
+// than kAheadLeftUs of kernel time short of their requirement get one more
+// slice.
+constexpr double kAheadLeftUs = 3000.0;
+
 struct pbn_server {
     uint8_t *arena_base = nullptr;
     Arena arena;
+    // the server's own non-blocking stream (ordered after the caller's stream
+    // at creation): work on the legacy default stream would wait for the
+    // long lane's slices, which run on blocking (CU-masked) streams
     hipStream_t stream = nullptr;
     pbn::Workspace ws;
     uint64_t next_id = 1;
     std::deque<ServeReq *> queue;
-    std::vector<ServeReq *> active;
+    std::vector<ServeReq *> active;          // the short requests' lane
     std::map<uint64_t, std::unique_ptr<ServeReq>> all;
     uint32_t done = 0;
+    // long lane (lanes: 0 not yet set up, 1 ready, -1 unavailable or off)
+    int lanes = 0;
+    double long_us = INFINITY, long_tick_us = kLongTickUs;
+    uint32_t long_quarters = kLongQuarters;
+    double slice_us = pbn::kServeTickUs, ahead_us = 0.0;
+    pbn::Workspace ahead_ws;
+    hipEvent_t ahead_ev = nullptr;
+    bool ahead_pending = false;
+    uint64_t long_moved = 0, long_rounds = 0;
+    uint32_t cus = 0, long_cus = 0;
+    hipStream_t long_stream = nullptr, main_masked = nullptr;
+    hipEvent_t admit_ev = nullptr;
+    pbn::StreamPool main_pool;
+    pbn::Workspace long_ws;
+    pbn::RoundCtx long_ctx;
+    std::vector<ServeReq *> long_active;
+    ~pbn_server()
+    {
+        if (stream) {
+            (void)hipStreamSynchronize(stream);
+            (void)hipStreamDestroy(stream);
+        }
+        if (long_stream) {
+            (void)hipStreamSynchronize(long_stream);
+            (void)hipStreamDestroy(long_stream);
+        }
+        if (main_masked) {
+            (void)hipStreamSynchronize(main_masked);
+            (void)hipStreamDestroy(main_masked);
+        }
+        if (admit_ev) (void)hipEventDestroy(admit_ev);
+        if (ahead_ev) (void)hipEventDestroy(ahead_ev);
+        if (long_ctx.done) (void)hipEventDestroy(long_ctx.done);
+    }
 };
+
+namespace {
+
+// CU masks of the two lanes: CU bit i goes to the long lane when (i / 8) % 4 <
+// long_quarters, the same share of every XCD's CUs whether the mask's bits run
+// XCD by XCD or interleave the XCDs.
+int setup_lanes(pbn_server *srv, std::string &err)
+{
+    if (srv->lanes) return srv->lanes > 0 ? PBN_OK : PBN_OK;
+    srv->lanes = -1;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        err = "device attributes";
+        return PBN_EDEVICE;
+    }
+    if (cus < 128) return PBN_OK;                 // too few CUs to give a lane its own
+    std::vector<uint32_t> lm((cus + 31) / 32, 0u), mm((cus + 31) / 32, 0u);
+    uint32_t nl = 0;
+    for (int i = 0; i < cus; ++i) {
+        const bool lng = (uint32_t)(i / 8) % 4 < srv->long_quarters;
+        (lng ? lm : mm)[i / 32] |= 1u << (i % 32);
+        nl += lng;
+    }
+    if (hipExtStreamCreateWithCUMask(&srv->long_stream, (uint32_t)lm.size(), lm.data()) != hipSuccess ||
+        hipExtStreamCreateWithCUMask(&srv->main_masked, (uint32_t)mm.size(), mm.data()) != hipSuccess ||
+        hipEventCreateWithFlags(&srv->admit_ev, hipEventDisableTiming) != hipSuccess) {
+        err = "CU-masked server streams";
+        return PBN_EDEVICE;
+    }
+    srv->main_pool.cu_mask = mm;
+    srv->cus = (uint32_t)cus;
+    srv->long_cus = nl;
+    srv->lanes = 1;
+    return PBN_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
 int pbn_server_create(void *dev_arena, size_t arena_bytes, void *hip_stream, pbn_server **out)
 {
     if (!dev_arena || !out) return fail(PBN_EINVAL, "null argument");
-    pbn_server *s = new pbn_server();
+    std::unique_ptr<pbn_server> s(new pbn_server());
     s->arena_base = (uint8_t *)dev_arena;
     s->arena.init(arena_bytes);
-    s->stream = (hipStream_t)hip_stream;
-    *out = s;
+    hipEvent_t ready = nullptr;
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(ready, (hipStream_t)hip_stream) != hipSuccess ||
+        hipStreamWaitEvent(s->stream, ready, 0) != hipSuccess) {
+        if (ready) (void)hipEventDestroy(ready);
+        return fail(PBN_EDEVICE, "server stream");
+    }
+    (void)hipEventDestroy(ready);
+    *out = s.release();
     return PBN_OK;
 }
 
@@ -607,12 +707,110 @@ int pbn_server_step(pbn_server *srv, uint32_t *active, uint32_t *waiting, uint32
             srv->active.push_back(rq);
         }
     }
+    // retire finished requests and free their memory for the next admission
+    auto retire_finished = [&](std::vector<ServeReq *> &lane) {
+        bool waited = false;
+        for (auto it = lane.begin(); it != lane.end();) {
+            ServeReq *rq = *it;
+            if (!rq->run.finished()) { ++it; continue; }
+            // an ahead slice queued behind the round may still extend it: its
+            // memory is freed once that slice has run
+            if (!waited && srv->ahead_pending) {
+                (void)hipEventSynchronize(srv->ahead_ev);
+                waited = true;
+            }
+            for (auto &m : rq->run.machines) rq->results.push_back(m.result());
+            rq->run.machines.clear();
+            rq->sim.reset();
+            srv->arena.release(rq->off, rq->bytes);
+            rq->state = 2;
+            ++srv->done;
+            it = lane.erase(it);
+        }
+    };
+    auto fail_lane = [&](std::vector<ServeReq *> &lane, hipStream_t s, int rc) {
+        // the lane's chains are in an unknown state: every request in it ends
+        // with the error, and the queued ones are admitted later
+        (void)hipStreamSynchronize(s);
+        note(rc);
+        for (ServeReq *rq : lane) retire(rq, rc);
+        lane.clear();
+    };
+    // the long lane's round, once it has completed
+    if (srv->long_ctx.pending) {
+        const hipError_t e = hipEventQuery(srv->long_ctx.done);
+        if (e == hipSuccess) {
+            int rc = srv->long_ws.check_split(err);
+            if (rc) {
+                srv->long_ctx.pending = false;
+                fail_lane(srv->long_active, srv->long_stream, rc);
+            } else {
+                pbn::round_end(srv->long_ws, srv->long_ctx);
+                retire_finished(srv->long_active);
+            }
+        } else if (e != hipErrorNotReady) {
+            err = std::string("long lane: ") + hipGetErrorString(e);
+            srv->long_ctx.pending = false;
+            fail_lane(srv->long_active, srv->long_stream, PBN_EDEVICE);
+        }
+    }
+    const bool long_busy = !srv->long_active.empty();
     std::vector<pbn::SimRun *> runs;
     for (ServeReq *rq : srv->active) runs.push_back(&rq->run);
     if (!runs.empty()) {
         // time-sliced: a request that needs a long extension does not hold the
-        // others (or the next admissions) for its whole length
-        int rc = pbn::run_round(runs, srv->ws, srv->stream, err, pbn::kServeTickUs);
+        // others (or the next admissions) for its whole length.  Beside a busy
+        // long lane the round keeps to the other CUs, after the admissions'
+        // set-up on the server's stream.
+        hipStream_t ms = srv->stream;
+        pbn::LaunchCfg cfg;
+        int rc = PBN_OK;
+        if (long_busy) {
+            ms = srv->main_masked;
+            cfg.cus = srv->cus - srv->long_cus;
+            cfg.pool = &srv->main_pool;
+            if (hipEventRecord(srv->admit_ev, srv->stream) != hipSuccess ||
+                hipStreamWaitEvent(ms, srv->admit_ev, 0) != hipSuccess) {
+                err = "lane event";
+                rc = PBN_EDEVICE;
+            }
+        }
+        // the previous step's ahead slice has run (it was queued behind that
+        // step's round); a node-split group of it that gave up is re-run first
+        if (!rc && srv->ahead_pending) {
+            srv->ahead_pending = false;
+            if (hipEventSynchronize(srv->ahead_ev) != hipSuccess) {
+                err = "ahead slice";
+                rc = PBN_EDEVICE;
+            } else {
+                rc = srv->ahead_ws.check_split(err);
+            }
+        }
+        pbn::RoundCtx ctx;
+        if (!rc) rc = pbn::round_begin(runs, srv->ws, ms, ctx, err, cfg, srv->slice_us);
+        if (!rc && srv->ahead_us > 0.0) {
+            bool launched = false;
+            rc = pbn::ahead_begin(runs, srv->ahead_ws, ms, cfg, srv->ahead_us, kAheadLeftUs, &launched, err);
+            if (!rc && launched) {
+                if ((!srv->ahead_ev && hipEventCreateWithFlags(&srv->ahead_ev, hipEventDisableTiming) != hipSuccess) ||
+                    hipEventRecord(srv->ahead_ev, ms) != hipSuccess) {
+                    err = "ahead event";
+                    rc = PBN_EDEVICE;
+                } else {
+                    srv->ahead_pending = true;
+                }
+            }
+        }
+        if (!rc && ctx.pending) {
+            const hipError_t e = hipEventSynchronize(ctx.done);
+            if (e != hipSuccess) {
+                err = std::string("round sync: ") + hipGetErrorString(e);
+                rc = PBN_EDEVICE;
+            } else if (!(rc = srv->ws.check_split(err))) {
+                pbn::round_end(srv->ws, ctx);
+            }
+        }
+        if (ctx.done) (void)hipEventDestroy(ctx.done);
         // the next admission rewrites the pinned descriptor staging: this
         // round's copy of it has completed once the stream is idle
         if (!admitted.empty() && hipStreamSynchronize(srv->stream) != hipSuccess && !rc) {
@@ -620,33 +818,88 @@ int pbn_server_step(pbn_server *srv, uint32_t *active, uint32_t *waiting, uint32
             rc = PBN_EDEVICE;
         }
         if (rc) {
-            // the round's chains are in an unknown state: every request in it
-            // ends with the error, and the queued ones are admitted later
-            (void)hipStreamSynchronize(srv->stream);
-            note(rc);
-            for (ServeReq *rq : srv->active) retire(rq, rc);
-            srv->active.clear();
+            srv->ahead_pending = false;
+            fail_lane(srv->active, ms, rc);
         }
     }
-    // retire finished requests and free their memory for the next admission
-    for (auto it = srv->active.begin(); it != srv->active.end();) {
-        ServeReq *rq = *it;
-        if (!rq->run.finished()) { ++it; continue; }
-        for (auto &m : rq->run.machines) rq->results.push_back(m.result());
-        rq->run.machines.clear();
-        rq->sim.reset();
-        srv->arena.release(rq->off, rq->bytes);
-        rq->state = 2;
-        ++srv->done;
-        it = srv->active.erase(it);
+    retire_finished(srv->active);
+    // requests whose pending extension is long move to the long lane
+    if (srv->lanes == 0) {
+        int rc = setup_lanes(srv, err);
+        if (rc) note(rc);
     }
-    if (active) *active = (uint32_t)srv->active.size();
+    if (srv->lanes > 0) {
+        for (auto it = srv->active.begin(); it != srv->active.end();) {
+            ServeReq *rq = *it;
+            uint64_t need = UINT64_MAX;
+            for (auto &m : rq->run.machines)
+                if (!m.done()) need = std::min(need, m.request().need_len);
+            const pbn_sim *sim = rq->sim.get();
+            const uint32_t groups = (sim->omega + 63) / 64;
+            const uint32_t parts = std::max<uint32_t>(1, std::min<uint32_t>(16, srv->long_cus / groups));
+            if (need != UINT64_MAX && need > sim->len && groups <= srv->long_cus &&
+                pbn::extension_us(sim, need - sim->len, parts) > srv->long_us) {
+                srv->long_active.push_back(rq);
+                ++srv->long_moved;
+                it = srv->active.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        if (!srv->long_ctx.pending && !srv->long_active.empty()) {
+            // the long lane's next slice, after everything queued on the
+            // server's stream (the moved requests' earlier rounds)
+            std::vector<pbn::SimRun *> lr;
+            for (ServeReq *rq : srv->long_active) lr.push_back(&rq->run);
+            const pbn::LaunchCfg lcfg{false, true, srv->long_cus, nullptr};
+            int rc = PBN_OK;
+            if (hipEventRecord(srv->admit_ev, srv->stream) != hipSuccess ||
+                hipStreamWaitEvent(srv->long_stream, srv->admit_ev, 0) != hipSuccess) {
+                err = "lane event";
+                rc = PBN_EDEVICE;
+            }
+            if (!rc)
+                rc = pbn::round_begin(lr, srv->long_ws, srv->long_stream, srv->long_ctx, err, lcfg, srv->long_tick_us, 1);
+            if (!rc) ++srv->long_rounds;
+            if (rc) {
+                srv->long_ctx.pending = false;
+                fail_lane(srv->long_active, srv->long_stream, rc);
+            }
+        }
+    }
+    if (active) *active = (uint32_t)(srv->active.size() + srv->long_active.size());
     if (waiting) *waiting = (uint32_t)srv->queue.size();
     if (done) *done = srv->done;
     if (first_rc) {
         err = first_err;
         return fail(first_rc, err);
     }
+    return PBN_OK;
+}
+
+int pbn_server_configure(pbn_server *srv, const pbn_server_opts *o)
+{
+    if (!srv || !o || o->long_quarters > 3) return fail(PBN_EINVAL, "bad argument");
+    if (!(o->slice_us >= 0.0) || !(o->long_slice_us >= 0.0) || !(o->ahead_us >= 0.0) || !(o->long_lane_us >= 0.0))
+        return fail(PBN_EINVAL, "bad argument");
+    const uint32_t q = o->long_quarters ? o->long_quarters : kLongQuarters;
+    if (q != srv->long_quarters && srv->lanes != 0)
+        return fail(PBN_EINVAL, "the lanes' CU shares are fixed once the server has stepped");
+    const double long_us = o->long_lane_us > 0.0 ? o->long_lane_us : INFINITY;
+    if (std::isinf(long_us) && !srv->long_active.empty()) return fail(PBN_EINVAL, "the long lane has requests");
+    srv->long_quarters = q;
+    srv->long_us = long_us;
+    srv->long_tick_us = o->long_slice_us > 0.0 ? o->long_slice_us : kLongTickUs;
+    srv->slice_us = o->slice_us > 0.0 ? o->slice_us : pbn::kServeTickUs;
+    srv->ahead_us = o->ahead_us > 0.0 ? o->ahead_us : 0.0;
+    return PBN_OK;
+}
+
+int pbn_server_lane_stats(const pbn_server *srv, uint64_t *long_requests, uint64_t *long_rounds)
+{
+    if (!srv) return fail(PBN_EINVAL, "null argument");
+    if (long_requests) *long_requests = srv->long_moved;
+    if (long_rounds) *long_rounds = srv->long_rounds;
     return PBN_OK;
 }
 

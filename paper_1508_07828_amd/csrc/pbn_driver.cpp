@@ -119,17 +119,16 @@ int Workspace::ensure_split(size_t groups, size_t xch_words, std::string &err)
         const size_t nc = std::max(groups, 2 * cap_grp);
         if (d_grp) (void)hipFree(d_grp);
         if (h_grp) (void)hipHostFree(h_grp);
-        if (d_ctr) (void)hipFree(d_ctr);
+        if (d_stat) (void)hipFree(d_stat);
         if (h_stat) (void)hipHostFree(h_stat);
         d_grp = h_grp = nullptr;
-        d_ctr = h_stat = nullptr;
+        d_stat = h_stat = nullptr;
         cap_grp = 0;
-        // group q: arrival counter at word 2q, status word at 2q + 1 (one
-        // clear and one download per launch)
+        // one status word per group (one clear and one download per launch)
         if (hipMalloc((void **)&d_grp, nc * sizeof(SplitGroup)) != hipSuccess ||
             hipHostMalloc((void **)&h_grp, nc * sizeof(SplitGroup), hipHostMallocDefault) != hipSuccess ||
-            hipMalloc((void **)&d_ctr, 2 * nc * sizeof(uint32_t)) != hipSuccess ||
-            hipHostMalloc((void **)&h_stat, 2 * nc * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+            hipMalloc((void **)&d_stat, nc * sizeof(uint32_t)) != hipSuccess ||
+            hipHostMalloc((void **)&h_stat, nc * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
             err = "workspace split groups";
             return PBN_ENOMEM;
         }
@@ -177,7 +176,7 @@ int Workspace::check_split(std::string &err)
     split_used = 0;
     std::vector<StepItem> redo;
     for (size_t q = 0; q < ng && q < split_items.size(); ++q)
-        if (h_stat[2 * q + 1] == 1u) redo.push_back(split_items[q]);
+        if (h_stat[q] == 1u) redo.push_back(split_items[q]);
     const size_t nq = redo_queries, nb = redo_bsum;
     redo_queries = redo_bsum = 0;
     if (redo.empty()) return PBN_OK;
@@ -210,12 +209,12 @@ void Workspace::release()
     cap_rows = 0;
     if (d_grp) (void)hipFree(d_grp);
     if (h_grp) (void)hipHostFree(h_grp);
-    if (d_ctr) (void)hipFree(d_ctr);
+    if (d_stat) (void)hipFree(d_stat);
     if (d_xch) (void)hipFree(d_xch);
     if (h_stat) (void)hipHostFree(h_stat);
     d_grp = h_grp = nullptr;
     d_xch = nullptr;
-    d_ctr = h_stat = nullptr;
+    d_stat = h_stat = nullptr;
     cap_grp = cap_xch = 0;
     split_used = 0;
     split_items.clear();
@@ -843,34 +842,43 @@ void choose_kernel(const pbn_sim *sim, StepItem &it, bool latency)
 
 namespace {
 
-// Streams for concurrent launch groups (default priority, non-blocking).
-// One caller at a time: the fork and join events are shared.
-struct StreamPool {
-    static constexpr int kN = 4;
-    hipStream_t s[kN] = {};
-    hipEvent_t fork = nullptr, join[kN] = {};
-    bool ready = false;
-    std::mutex mu;
-    int init(std::string &err)
-    {
-        if (ready) return PBN_OK;
-        for (int i = 0; i < kN; ++i) {
-            if (hipStreamCreateWithFlags(&s[i], hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&join[i], hipEventDisableTiming) != hipSuccess) {
-                err = "stream pool";
-                return PBN_EDEVICE;
-            }
-        }
-        if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) { err = "stream pool"; return PBN_EDEVICE; }
-        ready = true;
-        return PBN_OK;
-    }
-};
 StreamPool &stream_pool()
 {
     static StreamPool p;
     return p;
 }
+}  // namespace
+
+int StreamPool::init(std::string &err)
+{
+    if (ready) return PBN_OK;
+    for (int i = 0; i < kN; ++i) {
+        const hipError_t e = cu_mask.empty()
+                                 ? hipStreamCreateWithFlags(&s[i], hipStreamNonBlocking)
+                                 : hipExtStreamCreateWithCUMask(&s[i], (uint32_t)cu_mask.size(), cu_mask.data());
+        if (e != hipSuccess || hipEventCreateWithFlags(&join[i], hipEventDisableTiming) != hipSuccess) {
+            err = "stream pool";
+            return PBN_EDEVICE;
+        }
+    }
+    if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) { err = "stream pool"; return PBN_EDEVICE; }
+    ready = true;
+    return PBN_OK;
+}
+
+void StreamPool::release()
+{
+    if (!ready) return;
+    for (int i = 0; i < kN; ++i) {
+        (void)hipStreamSynchronize(s[i]);
+        (void)hipStreamDestroy(s[i]);
+        (void)hipEventDestroy(join[i]);
+    }
+    (void)hipEventDestroy(fork);
+    ready = false;
+}
+
+namespace {
 
 
 
@@ -916,10 +924,9 @@ int split_table(pbn_sim *sim, uint32_t P, pbn_sim::SplitTab &out, std::string &e
 // so a group's parts are resident together.  Forced: P parts for every
 // bit-sliced group (at most one per node block).  The parts of a node-split
 // group are marked small = 2.
-int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, size_t &ngroups)
+int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, size_t &ngroups, size_t kCus)
 {
     ngroups = 0;
-    constexpr size_t kCus = 256;
     std::vector<uint32_t> parts(items.size(), 1);
     {
         std::vector<size_t> cand;
@@ -997,7 +1004,7 @@ int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, 
         }
         if (lds > 160 * 1024) continue;
         plan.push_back(Plan{i, P, G, (uint32_t)lds, tab});
-        xwords += 2 * (size_t)sim->net.n + 2 * (size_t)P;
+        xwords += split_xch_words(sim->net.n, P);
         extra += P - 1;
     }
     if (plan.empty()) return PBN_OK;
@@ -1020,13 +1027,12 @@ int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, 
         SplitGroup &g = ws.h_grp[q];
         g.tab = p.tab.d_tab;
         g.xch = ws.d_xch + xoff;
-        g.ctr = ws.d_ctr + 2 * q;
-        g.stat = ws.d_ctr + 2 * q + 1;
+        g.stat = ws.d_stat + q;
         g.nparts = p.P;
         g.groups = p.tab.groups;
         g.spins = g_split_spins;
         g.pad_ = 0;
-        xoff += 2 * (size_t)sim->net.n + 2 * (size_t)p.P;
+        xoff += split_xch_words(sim->net.n, p.P);
         // the whole group in its one-block latency shape, should it give up
         StepItem whole = items[i];
         choose_kernel(sim, whole, true);
@@ -1046,19 +1052,20 @@ int split_expand(std::vector<StepItem> &items, Workspace &ws, std::string &err, 
     }
     items.swap(out);
     ngroups = plan.size();
+    ws.xch_used = xoff;
     return PBN_OK;
 }
 
 }  // namespace
 
 int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream, std::string &err,
-                 bool allow_fork, bool allow_split)
+                 bool allow_fork, bool allow_split, uint32_t cus, StreamPool *pool)
 {
     if (items.empty()) return PBN_OK;
     int rc = ws.before_write(ws.ev_items, ws.items_in_flight, err);
     if (rc) return rc;
     size_t nsplit = 0;
-    if (allow_split && (rc = split_expand(items, ws, err, nsplit))) return rc;
+    if (allow_split && (rc = split_expand(items, ws, err, nsplit, cus))) return rc;
     // groups of equal kernel form; inside a group the longest
     // items first, since the hardware dispatches blocks roughly in order
     struct Key { uint32_t kernel, cls; double cost; size_t idx; };
@@ -1166,7 +1173,8 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
     if (nsplit) {
         if (hipMemcpyAsync(ws.d_grp, ws.h_grp, nsplit * sizeof(SplitGroup), hipMemcpyHostToDevice, stream) !=
                 hipSuccess ||
-            hipMemsetAsync(ws.d_ctr, 0, 2 * nsplit * sizeof(uint32_t), stream) != hipSuccess) {
+            hipMemsetAsync(ws.d_stat, 0, nsplit * sizeof(uint32_t), stream) != hipSuccess ||
+            hipMemsetAsync(ws.d_xch, 0, ws.xch_used * sizeof(uint64_t), stream) != hipSuccess) {
             err = "node-split group upload";
             return PBN_EDEVICE;
         }
@@ -1201,7 +1209,7 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
     } else {
         // largest groups first, spread over the pool's streams, joined back
         std::sort(groups.begin(), groups.end(), [](const Group &a, const Group &b) { return a.cost > b.cost; });
-        StreamPool &P = stream_pool();
+        StreamPool &P = pool ? *pool : stream_pool();
         std::lock_guard<std::mutex> hold(P.mu);
         if ((rc = P.init(err))) return rc;
         if (hipEventRecord(P.fork, stream) != hipSuccess) { err = "fork event"; return PBN_EDEVICE; }
@@ -1218,7 +1226,7 @@ int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream
         }
     }
     if (!rc && nsplit) {
-        if (hipMemcpyAsync(ws.h_stat, ws.d_ctr, 2 * nsplit * sizeof(uint32_t), hipMemcpyDeviceToHost, stream) !=
+        if (hipMemcpyAsync(ws.h_stat, ws.d_stat, nsplit * sizeof(uint32_t), hipMemcpyDeviceToHost, stream) !=
             hipSuccess) {
             err = "node-split status download";
             return PBN_EDEVICE;
@@ -1364,9 +1372,9 @@ double step_latency_us(const pbn_sim *sim, bool latency)
 // per part (n x transitions / parts); one more part costs one CU per 64-chain
 // group of that simulation.  At most kSplitMaxParts parts of at least 8 node
 // blocks, bit-sliced networks only.
-static void plan_parts(const std::vector<std::pair<pbn_sim *, uint64_t>> &ext, std::vector<uint32_t> &parts)
+static void plan_parts(const std::vector<std::pair<pbn_sim *, uint64_t>> &ext, std::vector<uint32_t> &parts,
+                       uint64_t kCus)
 {
-    constexpr uint64_t kCus = 256;
     uint64_t used = 0;
     for (const auto &e : ext) used += (e.first->omega + 63) / 64;
     if (used >= kCus) return;
@@ -1392,6 +1400,13 @@ static void plan_parts(const std::vector<std::pair<pbn_sim *, uint64_t>> &ext, s
     }
 }
 
+double extension_us(const pbn_sim *sim, uint64_t positions, uint32_t parts)
+{
+    double us = step_latency_us(sim, true);
+    if (parts >= 2 && sim->net.bitsliced && split_mode_of(sim) != 1) us = std::min(us, 6.0 + us / parts);
+    return us * (double)sim->thin * (double)positions;
+}
+
 // parts: the network's 64-chain groups are spread over that many CUs in the
 // node-split form (forced part counts included); a transition then costs
 // about 6 us of exchange plus the one-block time over the parts.
@@ -1407,7 +1422,7 @@ uint64_t slice_len(const pbn_sim *sim, double tick_us, bool latency, uint32_t pa
 }
 
 int round_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, RoundCtx &ctx, std::string &err,
-                bool allow_fork, double tick_us, int latency)
+                const LaunchCfg &cfg, double tick_us, int latency)
 {
     ctx.owners.clear();
     ctx.kinds.clear();
@@ -1443,16 +1458,16 @@ int round_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, 
     // node-split parts per simulation (time-sliced rounds that own the device),
     // decided before slicing so that each slice is about tick_us long
     std::vector<uint32_t> parts(ext.size(), 1);
-    if (tick_us > 0.0 && allow_fork && latency) plan_parts(ext, parts);
+    if (tick_us > 0.0 && cfg.split && latency) plan_parts(ext, parts, cfg.cus);
     for (size_t k = 0; k < ext.size(); ++k) {
         pbn_sim *sim = ext[k].first;
         uint64_t e = ext[k].second;
-        if (tick_us > 0.0) e = std::min(e, slice_len(sim, tick_us, latency != 0, allow_fork ? parts[k] : 1));
+        if (tick_us > 0.0) e = std::min(e, slice_len(sim, tick_us, latency != 0, cfg.split ? parts[k] : 1));
         const size_t first = items.size();
         sim_extend_items(sim, 0, e, sim->thin, items, latency != 0);
         for (size_t i = first; i < items.size(); ++i) items[i].parts_hint = parts[k];
     }
-    int rc = launch_items(items, ws, stream, err, allow_fork, allow_fork);
+    int rc = launch_items(items, ws, stream, err, cfg.fork, cfg.split, cfg.cus, cfg.pool);
     if (rc) return rc;
     // 2. queries for every ready request
     std::vector<Query> qs;
@@ -1514,6 +1529,42 @@ int round_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, 
     return PBN_OK;
 }
 
+int ahead_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, const LaunchCfg &cfg,
+                double tick_us, double min_left_us, bool *launched, std::string &err)
+{
+    *launched = false;
+    // runs still short of their pending requirement by more than min_left_us
+    // of kernel time, after the round queued before
+    std::vector<std::pair<pbn_sim *, uint64_t>> ext;
+    uint64_t waves = 0;
+    for (SimRun *run : runs) {
+        if (run->finished()) continue;
+        pbn_sim *sim = run->sim;
+        uint64_t target = UINT64_MAX;
+        for (auto &m : run->machines)
+            if (!m.done()) target = std::min(target, m.request().need_len);
+        if (target == UINT64_MAX || target <= sim->len || target > sim->max_len) continue;
+        if (target - sim->len > ((1ull << 32) - 1 - sim->t_done) / sim->thin) continue;
+        if (extension_us(sim, target - sim->len, kSplitMaxParts) < min_left_us) continue;
+        ext.push_back({sim, target - sim->len});
+        waves += latency_waves(sim);
+    }
+    if (ext.empty() || waves > kLatencyWaves) return PBN_OK;
+    std::vector<uint32_t> parts(ext.size(), 1);
+    if (cfg.split) plan_parts(ext, parts, cfg.cus);
+    std::vector<StepItem> items;
+    for (size_t k = 0; k < ext.size(); ++k) {
+        pbn_sim *sim = ext[k].first;
+        const uint64_t e = std::min(ext[k].second, slice_len(sim, tick_us, true, cfg.split ? parts[k] : 1));
+        const size_t first = items.size();
+        sim_extend_items(sim, 0, e, sim->thin, items, true);
+        for (size_t i = first; i < items.size(); ++i) items[i].parts_hint = parts[k];
+    }
+    const int rc = launch_items(items, ws, stream, err, cfg.fork, cfg.split, cfg.cus, cfg.pool);
+    if (!rc) *launched = true;
+    return rc;
+}
+
 void round_end(Workspace &ws, RoundCtx &ctx)
 {
     for (size_t i = 0; i < ctx.owners.size(); ++i) {
@@ -1527,10 +1578,11 @@ void round_end(Workspace &ws, RoundCtx &ctx)
     ctx.pending = false;
 }
 
-int run_round(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err, double tick_us)
+int run_round(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err, double tick_us,
+              const LaunchCfg &cfg)
 {
     RoundCtx ctx;
-    int rc = round_begin(runs, ws, stream, ctx, err, true, tick_us);
+    int rc = round_begin(runs, ws, stream, ctx, err, cfg, tick_us);
     if (!rc && ctx.pending) {
         hipError_t e = hipEventSynchronize(ctx.done);
         if (e != hipSuccess) { err = std::string("round sync: ") + hipGetErrorString(e); rc = PBN_EDEVICE; }
@@ -1697,7 +1749,9 @@ int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
             all_done = false;
             // the express lane takes whole extensions
             const double tick = k < nl ? kTickUs : 0.0;
-            if ((rc = round_begin(L.runs, L.ws, L.stream, L.ctx, err, false, tick, k < nl ? latency : xlatency))) break;
+            const LaunchCfg lane_cfg{false, false, 256, nullptr};
+            if ((rc = round_begin(L.runs, L.ws, L.stream, L.ctx, err, lane_cfg, tick, k < nl ? latency : xlatency)))
+                break;
             if (L.ctx.pending) any_pending = true;
         }
         if (rc || all_done) break;

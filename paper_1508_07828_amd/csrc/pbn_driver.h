@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -36,12 +37,12 @@ struct Workspace {
     int after_copy(hipEvent_t &ev, bool &in_flight, hipStream_t stream, std::string &err);
     int ensure_stage(size_t count, std::string &err);
     // node-split form: group descriptors (pinned staging, device), exchange
-    // area, and per group an arrival counter and a status word (d_ctr[2q],
-    // d_ctr[2q + 1]; the last launch's copied to h_stat)
+    // area (the last launch's first xch_used words), and a status word per
+    // group (the last launch's copied to h_stat)
     SplitGroup *d_grp = nullptr, *h_grp = nullptr;
     uint64_t *d_xch = nullptr;
-    uint32_t *d_ctr = nullptr, *h_stat = nullptr;
-    size_t cap_grp = 0, cap_xch = 0;
+    uint32_t *d_stat = nullptr, *h_stat = nullptr;
+    size_t cap_grp = 0, cap_xch = 0, xch_used = 0;
     // the last launch's node-split groups as whole 64-chain items (one-block
     // shapes) and its stream, for the re-run of a group that gave up; the
     // reduction that followed it in the same round (queries, batch sums)
@@ -175,6 +176,10 @@ void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t t
 constexpr uint64_t kLatencyWaves = 256 * 24;
 // Waves that the blocks of sim need in latency shapes.
 uint64_t latency_waves(const pbn_sim *sim);
+// Kernel time (us) of extending sim by `positions` recorded positions in its
+// latency shape, its 64-chain groups in `parts` node-split parts each (a
+// model fitted to single-group timings).
+double extension_us(const pbn_sim *sim, uint64_t positions, uint32_t parts);
 // Kernel time per extension slice of a time-sliced round (microseconds).
 constexpr double kTickUs = 5000.0;
 // Server rounds: shorter slices, since a request's result waits for the end of
@@ -197,6 +202,31 @@ struct SimRun {
 
 MachineParams make_params(const pbn_sim *sim, const pbn_opts *opts, double r, double conf);
 
+// Streams for concurrent launch groups (default priority, non-blocking),
+// restricted to the CUs of cu_mask when it is set (hipExtStreamCreateWithCUMask
+// words); one caller at a time.
+struct StreamPool {
+    static constexpr int kN = 4;
+    hipStream_t s[kN] = {};
+    hipEvent_t fork = nullptr, join[kN] = {};
+    bool ready = false;
+    std::mutex mu;
+    std::vector<uint32_t> cu_mask;
+    int init(std::string &err);
+    void release();
+    ~StreamPool() { release(); }
+};
+
+// How a round's step launches run: fork spreads its kernel groups over a
+// stream pool (pool, or the library's shared one); split allows node-split
+// parts, which needs the launch to own `cus` CUs while it runs (nothing else
+// on them).
+struct LaunchCfg {
+    bool fork = true, split = true;
+    uint32_t cus = 256;
+    StreamPool *pool = nullptr;
+};
+
 // One round over all runs: extension launch for the runs that wait for
 // positions, reduction launch for every ready request, one synchronisation.
 // round_begin enqueues a round and records ctx.done; round_end feeds the
@@ -211,11 +241,19 @@ struct RoundCtx {
 // tick_us > 0 limits each extension to a slice of about that much kernel time;
 // latency 1/0 forces the kernel shapes, -1 decides from the runs' chain groups.
 int round_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, RoundCtx &ctx, std::string &err,
-                bool allow_fork = true, double tick_us = 0.0, int latency = -1);
+                const LaunchCfg &cfg = LaunchCfg{}, double tick_us = 0.0, int latency = -1);
 void round_end(Workspace &ws, RoundCtx &ctx);
+// Queue, behind a round, one more slice of about tick_us of kernel time for
+// every run whose pending requirement is still more than min_left_us of
+// kernel time away (its next round would extend it anyway): the device works
+// through the host's decisions for the round.  Only while those runs' groups
+// fit on the chip in latency shapes.  *launched tells whether anything was
+// queued (ws.check_split then applies once the stream has passed it).
+int ahead_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, const LaunchCfg &cfg,
+                double tick_us, double min_left_us, bool *launched, std::string &err);
 // One synchronous round; tick_us > 0 time-slices its extensions.
 int run_round(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err,
-              double tick_us = 0.0);
+              double tick_us = 0.0, const LaunchCfg &cfg = LaunchCfg{});
 // Many simulations: lanes by step-kernel class, each with its own stream and
 // asynchronous, time-sliced round loop (run_to_completion for one simulation).
 int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, std::string &err);
@@ -262,6 +300,6 @@ int run_chains_noalloc_impl(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint
 // CUs its node-split groups wait for), so latency-bound 64-chain groups may
 // be spread over several CUs; ws.check_split then tells whether they finished.
 int launch_items(std::vector<StepItem> &items, Workspace &ws, hipStream_t stream, std::string &err,
-                 bool allow_fork = true, bool allow_split = false);
+                 bool allow_fork = true, bool allow_split = false, uint32_t cus = 256, StreamPool *pool = nullptr);
 
 }  // namespace pbn

@@ -89,27 +89,29 @@ struct DevSim {
 // group, block r owning a contiguous range of 16-node blocks and the predictor
 // slots of those nodes.  Each transition every block publishes, for its own
 // nodes, the perturbation flips and the function values, plus its chains'
-// perturbed flags, and reads everyone's after a counter barrier.
+// perturbed flags, and reads everyone's as they arrive.
 //   tab: u32 [0, P]  first 16-node block of part r (tab[P] = nblk)
 //            [P + 1, 2P + 1]  first 64-slot group of part r (tab[2P + 1] = groups)
 //            at split_head(P): K of every slot group, then (16-byte aligned) the
 //            slot records, 8 words each, as in DevSim::fs_rec
-//   xch: u64 [2][n] next-state words as published by their owners, then
-//        [2][P] perturbed-chain words, by transition parity
-//   ctr: arrivals, one per part and transition, zero at launch
-//   stat: 0 at launch; 1 once a block's barrier wait timed out (the group then
-//         ends early and leaves its state unchanged), 2 once block 0 completed
-//         the last transition (it then writes the state back)
+//   xch: u64 [2][n][2] next-state words as published by their owners, then
+//        [2][P][2] perturbed-chain words, by transition parity; each u64 holds
+//        a 32-bit half of a mask under a 32-bit tag (launch transition + 1);
+//        zero at launch
+//   stat: 0 at launch; 1 once a block's wait timed out (the group then ends
+//         early and leaves its state unchanged), 2 once block 0 completed the
+//         last transition (it then writes the state back)
 struct SplitGroup {
     const uint32_t *tab;
     uint64_t *xch;
-    uint32_t *ctr;
     uint32_t *stat;
     uint32_t nparts, groups;
-    uint32_t spins, pad_;        // polls of the counter before a part gives up
+    uint32_t spins, pad_;        // polls of a word before a part gives up
 };
-// Polls of a block's counter wait before it gives up (each poll reads the
-// counter from memory and sleeps, together well over 100 ns); tests of the
+// Exchange-area words of one group.
+constexpr size_t split_xch_words(uint32_t n, uint32_t P) { return (size_t)4 * n + (size_t)4 * P; }
+// Polls of one exchange word before a block gives up (each poll reads the
+// word from memory and sleeps, together well over 100 ns); tests of the
 // failure path lower it.
 constexpr uint32_t kSplitSpins = 1u << 20;
 // Parts of one node-split group, at most.

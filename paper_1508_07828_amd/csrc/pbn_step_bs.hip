@@ -551,23 +551,18 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
 //   -- barrier
 //   X  with Pr the chains this block perturbed, publish for every own node
 //      h_i = Pr & (S_i ^ flips_i) | ~Pr & f_i and the word Pr to the group's
-//      exchange area (agent-coherent stores), wait until every block of the
-//      group has arrived at this transition on the group's counter, then read
-//      them all: node i of part q becomes h_i, except in the chains perturbed
-//      by another part only, which keep S_i.
-// Ordering: every wave's stores complete and the block synchronises before
-// its first thread arrives with a release read-modify-write of the counter at
-// agent scope; the poll reads it with acquire loads (the last block to arrive
-// acquires through its own read-modify-write), and the block synchronises
-// again before any thread reads the others' words.
-// The wait is bounded: a block that waits about a second gives up.  The group's
-// status word then decides, once, between the two ends of the launch: a block
-// that gives up moves it from 0 to 1 (aborted), block 0 moves it from 0 to 2
-// (complete) after the last transition.  An aborted group never writes its
-// state back, so the host re-runs it in the one-block form from the state it
-// started from; a block that gives up after its group completed ends quietly.
-// Block 0 records the indicators (state set q by its wave q mod G) and writes
-// the state back.
+//      exchange area, each 64-bit word a 32-bit half tagged with the
+//      transition, then read every other part's words, polling each until it
+//      carries this transition's tag: node i of part q becomes h_i, except in
+//      the chains perturbed by another part only, which keep S_i.
+// The wait is bounded: a block that polls about a second gives up.  The
+// group's status word then decides, once, between the two ends of the
+// launch: a block that gives up moves it from 0 to 1 (aborted), block 0 moves
+// it from 0 to 2 (complete) after the last transition.  An aborted group never
+// writes its state back, so the host re-runs it in the one-block form from the
+// state it started from; the other blocks of an aborted group see the word
+// and stop polling.  Block 0 records the indicators (state set q by its wave
+// q mod G) and writes the state back.
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) k_step_split(const StepItem *__restrict__ items)
 {
     const StepItem it = load_item(items, blockIdx.x);
@@ -577,7 +572,6 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     const uint32_t P = sg->nparts, r = it.part, groups = sg->groups, max_spins = sg->spins;
     const cu32 tab = (cu32)sg->tab;
     PBN_GAS uint64_t *xch = (PBN_GAS uint64_t *)sg->xch;
-    PBN_GAS uint32_t *ctr = (PBN_GAS uint32_t *)sg->ctr;
     PBN_GAS uint32_t *gstat = (PBN_GAS uint32_t *)sg->stat;
     const uint32_t n = v.n, W = v.W, omega = v.omega;
     const uint32_t G = blockDim.x >> 6;
@@ -714,60 +708,72 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
         // block's perturbed chains: exact for the chains this block perturbed
         // and for the unperturbed ones; the chains perturbed only in other
         // parts keep S_i, which every reader restores from its own S.
-        PBN_GAS uint64_t *X = xch + (size_t)(s & 1) * n;
-        PBN_GAS uint64_t *XP = xch + (size_t)2 * n + (size_t)(s & 1) * P;
+        // Every published 64-bit word is (tag << 32) | one 32-bit half of a
+        // mask, tag = s + 1, stored and loaded whole (single-copy atomic), so
+        // a reader polls the data itself until each word carries this
+        // transition's tag: no counter, no wait for the stores to complete.
+        // The area is zero at launch; the word a reader sees before the
+        // owner's store is two transitions old (parity) or zero, never this
+        // tag.  A reader that polls too long gives up (bounded wait).
+        PBN_GAS uint64_t *X = xch + (size_t)(s & 1) * 2 * n;
+        PBN_GAS uint64_t *XP = xch + (size_t)4 * n + (size_t)(s & 1) * 2 * P;
+        const uint64_t tag = (uint64_t)(s + 1) << 32;
         uint64_t Pr = 0;
         for (uint32_t w = 0; w < G; ++w) Pr |= Pt[w];
         for (uint32_t k = threadIdx.x; k < n_own; k += 64 * G) {
             const uint64_t h = (Pr & (S[i_lo + k] ^ Gm[k])) | (~Pr & Fm[k]);
             Fm[k] = h;
-            __hip_atomic_store(&X[i_lo + k], h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&X[2 * (i_lo + k)], tag | (uint32_t)h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&X[2 * (i_lo + k) + 1], tag | (uint32_t)(h >> 32), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
-        if (threadIdx.x == 0) __hip_atomic_store(&XP[r], Pr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // every wave's stores complete before the block arrives; the release
-        // below orders them (through the barrier) before the arrival
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        __builtin_amdgcn_s_waitcnt(0);
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        __syncthreads();
         if (threadIdx.x == 0) {
-            const uint32_t target = P * (s + 1);
-            // the last block to arrive need not poll: its read-modify-write
-            // acquires every earlier arrival's release
-            const uint32_t seen = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
-            uint32_t spins = 0;
-            while (seen < target && __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                // another block of the group gave up: no one will arrive
-                if (__hip_atomic_load(gstat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1u) {
-                    *abort_flag = 1u;
-                    break;
-                }
-                if (++spins >= max_spins) {
-                    uint32_t expect = 0u;
-                    __hip_atomic_compare_exchange_strong(gstat, &expect, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-                    // 2: the group completed after all (this was its last
-                    // transition), and this block's part is done
-                    *abort_flag = expect == 2u ? 2u : 1u;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
+            __hip_atomic_store(&XP[2 * r], tag | (uint32_t)Pr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&XP[2 * r + 1], tag | (uint32_t)(Pr >> 32), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
-        __syncthreads();
-        if (*abort_flag) return;
+        // poll two words (the halves of one mask) until both carry the tag
+        bool gave_up = false;
+        auto fetch = [&](PBN_GAS uint64_t *w2, uint64_t &out) {
+            uint64_t a0 = __hip_atomic_load(&w2[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t a1 = __hip_atomic_load(&w2[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t spins = 0;
+            while (((a0 ^ tag) >> 32) | ((a1 ^ tag) >> 32)) {
+                // another block of the group gave up: its words will not come
+                if ((spins & 63u) == 63u &&
+                    __hip_atomic_load(gstat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1u)
+                    gave_up = true;
+                if (gave_up || ++spins >= max_spins) {
+                    gave_up = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                a0 = __hip_atomic_load(&w2[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                a1 = __hip_atomic_load(&w2[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            out = (a1 << 32) | (uint32_t)a0;
+        };
         // node i of part q: h_i, except S_i in the chains perturbed outside q.
-        // Every thread issues its first eight node words, the first P threads
-        // the parts' perturbed-chain words (into LDS), before any is used.
-        constexpr uint32_t U = 8;
+        // Every thread issues its first four nodes' loads, the first P
+        // threads the parts' perturbed-chain words (into LDS), before any
+        // result is used; a batch whose words are not all there yet polls.
+        constexpr uint32_t U = 4;
         uint64_t h[U];
         auto load_batch = [&](uint32_t i0) {
+            uint64_t a[2 * U];
 #pragma unroll
             for (uint32_t u = 0; u < U; ++u) {
                 const uint32_t i = i0 + u * 64 * G;
-                h[u] = 0ull;
-                if (i < n && (i < i_lo || i >= i_hi))
-                    h[u] = __hip_atomic_load(&X[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const bool other = i < n && (i < i_lo || i >= i_hi);
+                a[2 * u] = other ? __hip_atomic_load(&X[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : tag;
+                a[2 * u + 1] =
+                    other ? __hip_atomic_load(&X[2 * i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : tag;
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t i = i0 + u * 64 * G;
+                h[u] = (a[2 * u + 1] << 32) | (uint32_t)a[2 * u];
+                if (((a[2 * u] ^ tag) >> 32) | ((a[2 * u + 1] ^ tag) >> 32)) fetch(&X[2 * i], h[u]);
             }
         };
         auto apply_batch = [&](uint32_t i0, uint64_t Pall) {
@@ -788,17 +794,39 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
                 }
             }
         };
+        // own words (Fm) complete before any thread applies them
+        __syncthreads();
         uint64_t Pall = 0;
         // every thread runs the first pass (and its barrier), whatever n is
         for (uint32_t i0 = threadIdx.x, first = 1; first || i0 < n; i0 += 64 * G * U, first = 0) {
             load_batch(i0);
             if (first) {
-                if (threadIdx.x < P)
-                    xpl[threadIdx.x] = __hip_atomic_load(&XP[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (threadIdx.x < P) {
+                    uint64_t pw;
+                    fetch(&XP[2 * threadIdx.x], pw);
+                    xpl[threadIdx.x] = pw;
+                }
+                if (gave_up) *abort_flag = 1u;
                 __syncthreads();
+                if (*abort_flag) break;
                 for (uint32_t q = 0; q < P; ++q) Pall |= xpl[q];
             }
+            if (gave_up) {
+                *abort_flag = 1u;
+                break;
+            }
             apply_batch(i0, Pall);
+        }
+        __syncthreads();
+        if (*abort_flag) {
+            // the group ends: the status word records it unless the group
+            // already completed
+            if (threadIdx.x == 0) {
+                uint32_t expect = 0u;
+                __hip_atomic_compare_exchange_strong(gstat, &expect, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+            }
+            return;
         }
         if (s >= it.nburn && ++since == it.thin) {
             since = 0;

@@ -126,6 +126,7 @@ class Job:
     psrf_max: float
     method: str = "two_state"          # or "skart"
     arrival: float = 0.0               # seconds (serving trace only)
+    text: str = ""                     # the network's canonical text, when drawn with it
 
 
 def tiny() -> Job:
@@ -162,23 +163,44 @@ def batched(count: int = 512) -> List[Job]:
     return jobs
 
 
+def _serving_request(args) -> Job:
+    """Request b of the serving trace: its own generator, seeded by (trace seed,
+    b), so that requests can be drawn in any order or in parallel."""
+    b, t, chains = args
+    rng = np.random.default_rng([STRUCT_SEED_BASE + 4, b])
+    n = int(round(math.exp(rng.uniform(math.log(50), math.log(5000)))))
+    net = random_network(rng, n, (1, 3), (1, 5), 0.001)
+    r = 0.01 if rng.integers(0, 2) == 0 else 0.005
+    pat = random_pattern(rng, n, int(rng.integers(1, 5)))
+    return Job("serving[{}]".format(b), net, chains, (SIM_SEED << 24) + b, [pat], r, 0.95, 1.1, arrival=t,
+               text=to_text(net))
+
+
+def serving_request(b: int, chains: int = 256) -> Job:
+    """Request b of the serving trace alone (its arrival time left at 0)."""
+    return _serving_request((b, 0.0, chains))
+
+
 def serving(duration_s: float = 60.0, rate: float = 200.0, chains: int = 256,
-            limit: int | None = None) -> List[Job]:
+            limit: int | None = None, workers: int = 0) -> List[Job]:
+    """Poisson arrivals at `rate` per second for duration_s (at most `limit`
+    requests); each request's network, precision and state set are drawn from
+    a generator of its own.  workers > 1 draws the requests in that many
+    processes (the result does not depend on it)."""
     rng = np.random.default_rng(STRUCT_SEED_BASE + 4)
-    jobs = []
+    times = []
     t = 0.0
     while True:
         t += float(rng.exponential(1.0 / rate))
-        if t > duration_s or (limit is not None and len(jobs) >= limit):
+        if t > duration_s or (limit is not None and len(times) >= limit):
             break
-        n = int(round(math.exp(rng.uniform(math.log(50), math.log(5000)))))
-        net = random_network(rng, n, (1, 3), (1, 5), 0.001)
-        r = 0.01 if rng.integers(0, 2) == 0 else 0.005
-        pat = random_pattern(rng, n, int(rng.integers(1, 5)))
-        b = len(jobs)
-        jobs.append(Job("serving[{}]".format(b), net, chains, (SIM_SEED << 24) + b,
-                        [pat], r, 0.95, 1.1, arrival=t))
-    return jobs
+        times.append(t)
+    args = [(b, tb, chains) for b, tb in enumerate(times)]
+    if workers > 1 and len(args) > 64:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(workers) as pool:
+            return pool.map(_serving_request, args, chunksize=16)
+    return [_serving_request(a) for a in args]
 
 
 def multiprop(chains: int = 16384, r: float = 1e-4) -> Job:

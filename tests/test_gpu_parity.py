@@ -7,6 +7,7 @@ length, status).  Floating point (R, the estimates, the Skart CI): within
 1e-12 relative, the tolerance stated for this path.
 """
 import dataclasses
+import os
 import sys
 
 import numpy as np
@@ -22,6 +23,7 @@ pytestmark = pytest.mark.gpu
 INT_KEYS = ("status", "psi_gr", "psi", "n", "N", "M", "kappa", "batches", "chain_len")
 FP_KEYS = ("prob", "rhat", "ci_lo", "ci_hi")
 CAP = 1 << 15
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def say(msg):
@@ -768,3 +770,63 @@ def test_split_workspace_grows():
         ch.extend(s.position()[0])
         assert np.array_equal(s.read_state(), ch.states), cases[i]
         assert np.array_equal(s.read_bits(0, 0, ch.length), ch.bits[0]), cases[i]
+
+
+def test_library_loaded_before_torch():
+    """A process that loads the library before it touches torch (a network
+    compiled first) still runs on the one HIP runtime torch uses: a regression
+    test, since the library once bound to a second runtime there and its first
+    device call failed."""
+    import subprocess
+    script = (
+        "import sys; sys.path.insert(0, {root!r})\n"
+        "import numpy as np\n"
+        "import paper_1508_07828_amd as pkg, pbnsynth as ps\n"
+        "net = pkg.Network(ps.to_text(ps.medium().net))\n"
+        "srv = pkg.Server(64 << 20)\n"
+        "rid = srv.submit(net, 64, 3, ps.medium().patterns, 0.02, max_len=1 << 15, psrf_max=1.1)\n"
+        "while srv.step()[2] < 1: pass\n"
+        "print('status', srv.poll(rid)[0]['status'])\n").format(root=ROOT)
+    say("library loaded before torch, in a child process")
+    out = subprocess.run([sys.executable, "-c", script], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert "status 0" in out.stdout, out.stdout
+
+
+# requests of the serving trace with n >= 2000 at r = 0.005 (trace index: chain
+# length, n): 1262: 512, 2109; 484: 512, 3056; 441: 682, 2013; 1307: 684, 2613;
+# 1285: 923, 2016; 588: 795, 3149; 356: 1715, 2172
+SERVE_BIG = (1262, 484, 441, 1307, 1285, 588, 356)
+
+
+def test_server_large_requests_and_long_lane():
+    """The top of the serving trace (n >= 2000, r = 0.005) in one server with
+    smaller requests, node-split parts planned per round: with a low threshold
+    the longer ones move to the long-request lane (a CU-masked stream of its
+    own, slices collected asynchronously) while the others keep to the
+    remaining CUs.  Every result equals the oracle's solo run."""
+    jobs = [ps.serving_request(i) for i in SERVE_BIG] + sorted(ps.serving(limit=60), key=lambda j: j.net.n)[:6]
+    srv = pkg.Server(2 << 30)
+    srv.configure(long_lane_us=2000.0, long_slice_us=3000.0, ahead_us=500.0)
+    say("server: {} requests, n = {}".format(len(jobs), [j.net.n for j in jobs]))
+    ids = [srv.submit(pkg.Network(ps.to_text(j.net)), j.chains, j.seed, j.patterns, j.r, j.confidence,
+                      max_len=CAP, psrf_max=j.psrf_max) for j in jobs]
+    pkg.profile_reset()
+    pkg.profile_enable(True)
+    rounds = 0
+    try:
+        while srv.step()[2] < len(jobs):
+            rounds += 1
+            assert rounds < 100000
+        prof = pkg.profile_read()
+    finally:
+        pkg.profile_enable(False)
+    assert prof["split_launches"] > 0
+    moved, long_rounds = srv.lane_stats()
+    say("long lane: {} requests, {} rounds".format(moved, long_rounds))
+    assert moved >= 2 and long_rounds >= 2
+    for rid, j in zip(ids, jobs):
+        say("oracle: trace request n={} r={}".format(j.net.n, j.r))
+        want = drivers.solve(ps.to_text(j.net), j.chains, j.seed, j.patterns, j.r, j.confidence, j.psrf_max,
+                             cap=CAP)
+        assert_same_result(srv.poll(rid)[0], want[0], j.name)
