@@ -617,29 +617,45 @@ def copy_probe(mib: int = 1024, reps: int = 4) -> int:
 
 def trace_union(trace_csv: str, kernel: str, solves: int, out: str) -> int:
     """From a rocprofv3 kernel-trace CSV of a run of `solves` batched solves
-    (warm-up and timed; no other legs): the wall time with at least one
-    `kernel` dispatch in flight, and the summed dispatch time, in all and per
-    solve.  Their ratio is the mean number of dispatches in flight (the lanes'
-    launches overlap), and the union per solve against the solve's algorithmic
-    operations gives the chip-wide fraction of the ALU peak."""
+    (one warm-up, then the timed ones; no other legs): the wall time with at
+    least one `kernel` dispatch in flight, and the summed dispatch time.  The
+    solves run one after another with host work between them, so the merged
+    busy intervals split into solves at their `solves` - 1 widest gaps; the
+    union per timed solve (the warm-up left out) against a solve's algorithmic
+    operations gives the chip-wide fraction of the ALU peak, and the summed
+    dispatch time over the union the mean number of dispatches in flight (the
+    lanes' launches overlap)."""
     import csv
     spans = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
                    for r in csv.DictReader(open(trace_csv)) if kernel in r["Kernel_Name"])
-    union_ns, cur_a, cur_b = 0, None, None
+    merged = []
     for a, b in spans:
-        if cur_b is not None and a <= cur_b:
-            cur_b = max(cur_b, b)
-            continue
-        if cur_b is not None:
-            union_ns += cur_b - cur_a
-        cur_a, cur_b = a, b
-    if cur_b is not None:
-        union_ns += cur_b - cur_a
+        if merged and a <= merged[-1][1]:
+            merged[-1][1] = max(merged[-1][1], b)
+        else:
+            merged.append([a, b])
+    solves = max(1, min(solves, len(merged)))
+    gaps = sorted(range(len(merged) - 1), key=lambda i: merged[i + 1][0] - merged[i][1], reverse=True)
+    cuts = sorted(gaps[: solves - 1]) + [len(merged) - 1]
+    per_solve, lo = [], 0
+    for c in cuts:
+        group = merged[lo: c + 1]
+        g_lo, g_hi = group[0][0], group[-1][1]
+        busy = sum(b - a for a, b in group)
+        summed = sum(min(b, g_hi) - max(a, g_lo) for a, b in spans if a < g_hi and b > g_lo)
+        per_solve.append({"union_ms": busy / 1e6, "first_to_last_ms": (g_hi - g_lo) / 1e6,
+                          "summed_dispatch_ms": summed / 1e6})
+        lo = c + 1
+    timed = per_solve[1:] or per_solve
+    union_ns = sum(b - a for a, b in merged)
     summed_ns = sum(b - a for a, b in spans)
+    t_union = sum(p["union_ms"] for p in timed) / len(timed)
+    t_summed = sum(p["summed_dispatch_ms"] for p in timed) / len(timed)
     info = {"kernel": kernel, "dispatches": len(spans), "solves": solves,
             "union_ms": union_ns / 1e6, "summed_dispatch_ms": summed_ns / 1e6,
-            "union_ms_per_solve": union_ns / 1e6 / solves, "summed_ms_per_solve": summed_ns / 1e6 / solves,
-            "mean_in_flight": summed_ns / max(union_ns, 1)}
+            "per_solve": per_solve,
+            "timed_union_ms_per_solve": t_union, "timed_summed_ms_per_solve": t_summed,
+            "timed_mean_in_flight": t_summed / max(t_union, 1e-9)}
     with open(out, "w") as fh:
         json.dump(info, fh, indent=1)
     print(json.dumps(info))
@@ -663,8 +679,9 @@ def traffic_from(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy_write
     dispatch), each scaled so that the plain copy reads and writes its size."""
     f_k, n_kf = _counter_sum(fetch_dir, "k_step_bs", "FETCH_SIZE")
     w_k, n_kw = _counter_sum(write_dir, "k_step_bs", "WRITE_SIZE")
-    f_c, n_cf = _counter_sum(copy_fetch_dir, "", "FETCH_SIZE")
-    w_c, n_cw = _counter_sum(copy_write_dir, "", "WRITE_SIZE")
+    # the probe's copies only: the fill that makes its source reads nothing
+    f_c, n_cf = _counter_sum(copy_fetch_dir, "copyBuffer", "FETCH_SIZE")
+    w_c, n_cw = _counter_sum(copy_write_dir, "copyBuffer", "WRITE_SIZE")
     copy_bytes = float(1024 << 20)
     f_scale = copy_bytes / (f_c / n_cf * 1024.0)
     w_scale = copy_bytes / (w_c / n_cw * 1024.0)
