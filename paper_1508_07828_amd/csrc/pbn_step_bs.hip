@@ -594,8 +594,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     uint32_t *Q = (uint32_t *)(Pw + 2 * G) + wave * 3 * kQCap;
     uint32_t *acc = (uint32_t *)(Pw + 2 * G) + G * 3 * kQCap + lane;
     uint32_t *abort_flag = (uint32_t *)(Pw + 2 * G) + G * 3 * kQCap + 64 * kMaxProps;
-    uint64_t *xpl = (uint64_t *)(abort_flag + 2);          // the parts' perturbed-chain words
-    uint8_t *owner = (uint8_t *)(xpl + kSplitMaxParts);    // part of each 16-node block
+    uint64_t *xpl = (uint64_t *)(abort_flag + 2);          // the parts' perturbed-chain words, a row per wave
+    uint8_t *owner = (uint8_t *)(xpl + kSplitMaxParts * G); // part of each 16-node block
     const uint64_t words_cap = v.d->words_cap;
     const bool recorder = r == 0;
 
@@ -655,10 +655,12 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             }
         }
     };
-    for (uint32_t s = 0; s < total; ++s) {
+    // ---- A: own blocks, lane = chain.  A draws only from the stream (t,
+    // chain, node): it reads no state, so transition s + 1's draws run while
+    // this part waits for the other parts' words of transition s.
+    auto phase_a = [&](uint32_t s) {
         const uint32_t t = it.t0 + s;
         uint64_t *Pt = Pw + (s & 1) * G;
-        // ---- A: own blocks, lane = chain
         uint64_t P_acc = 0;
         uint32_t qlen = 0;
         if (lane == 0) Pt[wave] = 0ull;
@@ -672,7 +674,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             draw_block(v, t, c, lane, b, v.blk_sel[b], thr8, thr8x4, Gm, i_lo, M, m_lo, Q, qlen, P_acc);
         }
         if (P_acc && lane == 0) lds_or(&Pt[wave], P_acc);
-        __syncthreads();
+    };
+    if (total > 0) phase_a(0);
+    __syncthreads();
+    for (uint32_t s = 0; s < total; ++s) {
+        const uint64_t *Pt = Pw + (s & 1) * G;
 
         // ---- C: own slots, lane = slot
         if (pending && recorder) {
@@ -714,7 +720,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
         // transition's tag: no counter, no wait for the stores to complete.
         // The area is zero at launch; the word a reader sees before the
         // owner's store is two transitions old (parity) or zero, never this
-        // tag.  A reader that polls too long gives up (bounded wait).
+        // tag.  A reader that polls too long gives up (bounded wait).  A part
+        // publishes transition s + 1 only after it has read every word of
+        // transition s, so no word of parity s & 1 is overwritten while a
+        // reader still needs it.
         PBN_GAS uint64_t *X = xch + (size_t)(s & 1) * 2 * n;
         PBN_GAS uint64_t *XP = xch + (size_t)4 * n + (size_t)(s & 1) * 2 * P;
         const uint64_t tag = (uint64_t)(s + 1) << 32;
@@ -722,7 +731,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
         for (uint32_t w = 0; w < G; ++w) Pr |= Pt[w];
         for (uint32_t k = threadIdx.x; k < n_own; k += 64 * G) {
             const uint64_t h = (Pr & (S[i_lo + k] ^ Gm[k])) | (~Pr & Fm[k]);
+            // h waits in Fm for this block's readers; the flips are consumed
             Fm[k] = h;
+            Gm[k] = 0ull;
             __hip_atomic_store(&X[2 * (i_lo + k)], tag | (uint32_t)h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&X[2 * (i_lo + k) + 1], tag | (uint32_t)(h >> 32), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
@@ -732,6 +743,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             __hip_atomic_store(&XP[2 * r + 1], tag | (uint32_t)(Pr >> 32), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
+        // own words (Fm) complete and the flips cleared before the next draws
+        // and before any thread applies them
+        __syncthreads();
+        if (s + 1 < total) phase_a(s + 1);
+
         // poll two words (the halves of one mask) until both carry the tag
         bool gave_up = false;
         auto fetch = [&](PBN_GAS uint64_t *w2, uint64_t &out) {
@@ -753,30 +769,44 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             }
             out = (a1 << 32) | (uint32_t)a0;
         };
+        // every wave reads the parts' perturbed-chain words itself (lane q:
+        // part q's, kept in the wave's own LDS row), so no barrier separates
+        // them from the node words
+        uint64_t xw = 0;
+        if (lane < P) fetch(&XP[2 * lane], xw);
+        uint64_t *xplw = xpl + (size_t)wave * kSplitMaxParts;
+        if (lane < P) xplw[lane] = xw;
+        uint64_t Pall = 0;
+        for (uint32_t q = 0; q < P; ++q) Pall |= xplw[q];
         // node i of part q: h_i, except S_i in the chains perturbed outside q.
-        // Every thread issues its first four nodes' loads, the first P
-        // threads the parts' perturbed-chain words (into LDS), before any
-        // result is used; a batch whose words are not all there yet polls.
+        // Every thread issues its next four nodes' loads before any result is
+        // used; a batch whose words are not all there yet polls.  The loop is
+        // uniform over the wave (lanes past n load nothing).
         constexpr uint32_t U = 4;
-        uint64_t h[U];
-        auto load_batch = [&](uint32_t i0) {
-            uint64_t a[2 * U];
+        bool quit = __ballot(gave_up) != 0;
+        for (uint32_t i0 = threadIdx.x; !quit && i0 - lane < n; i0 += 64 * G * U) {
+            uint64_t h[U];
+            {
+                uint64_t a[2 * U];
 #pragma unroll
-            for (uint32_t u = 0; u < U; ++u) {
-                const uint32_t i = i0 + u * 64 * G;
-                const bool other = i < n && (i < i_lo || i >= i_hi);
-                a[2 * u] = other ? __hip_atomic_load(&X[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : tag;
-                a[2 * u + 1] =
-                    other ? __hip_atomic_load(&X[2 * i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : tag;
-            }
+                for (uint32_t u = 0; u < U; ++u) {
+                    const uint32_t i = i0 + u * 64 * G;
+                    const bool other = i < n && (i < i_lo || i >= i_hi);
+                    a[2 * u] = other ? __hip_atomic_load(&X[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : tag;
+                    a[2 * u + 1] =
+                        other ? __hip_atomic_load(&X[2 * i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : tag;
+                }
 #pragma unroll
-            for (uint32_t u = 0; u < U; ++u) {
-                const uint32_t i = i0 + u * 64 * G;
-                h[u] = (a[2 * u + 1] << 32) | (uint32_t)a[2 * u];
-                if (((a[2 * u] ^ tag) >> 32) | ((a[2 * u + 1] ^ tag) >> 32)) fetch(&X[2 * i], h[u]);
+                for (uint32_t u = 0; u < U; ++u) {
+                    const uint32_t i = i0 + u * 64 * G;
+                    h[u] = (a[2 * u + 1] << 32) | (uint32_t)a[2 * u];
+                    if (((a[2 * u] ^ tag) >> 32) | ((a[2 * u + 1] ^ tag) >> 32)) fetch(&X[2 * i], h[u]);
+                }
             }
-        };
-        auto apply_batch = [&](uint32_t i0, uint64_t Pall) {
+            if (__ballot(gave_up)) {
+                quit = true;
+                break;
+            }
 #pragma unroll
             for (uint32_t u = 0; u < U; ++u) {
                 const uint32_t i = i0 + u * 64 * G;
@@ -784,55 +814,31 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
                     const uint32_t q = owner[i >> 4];
                     uint64_t hv = h[u];
                     if (q == r) {
-                        // own node: h from LDS, and the next transition's words cleared
-                        // by the thread that read them
+                        // own node: h from LDS, cleared for the next C by the
+                        // thread that read it (the next flips are already in Gm)
                         hv = Fm[i - i_lo];
-                        Gm[i - i_lo] = Fm[i - i_lo] = 0ull;
+                        Fm[i - i_lo] = 0ull;
                     }
-                    const uint64_t keep = Pall & ~xpl[q];
+                    const uint64_t keep = Pall & ~xplw[q];
                     S[i] = (hv & ~keep) | (S[i] & keep);
                 }
             }
-        };
-        // own words (Fm) complete before any thread applies them
-        __syncthreads();
-        uint64_t Pall = 0;
-        // every thread runs the first pass (and its barrier), whatever n is
-        for (uint32_t i0 = threadIdx.x, first = 1; first || i0 < n; i0 += 64 * G * U, first = 0) {
-            load_batch(i0);
-            if (first) {
-                if (threadIdx.x < P) {
-                    uint64_t pw;
-                    fetch(&XP[2 * threadIdx.x], pw);
-                    xpl[threadIdx.x] = pw;
-                }
-                if (gave_up) *abort_flag = 1u;
-                __syncthreads();
-                if (*abort_flag) break;
-                for (uint32_t q = 0; q < P; ++q) Pall |= xpl[q];
-            }
-            if (gave_up) {
-                *abort_flag = 1u;
-                break;
-            }
-            apply_batch(i0, Pall);
         }
-        __syncthreads();
-        if (*abort_flag) {
-            // the group ends: the status word records it unless the group
-            // already completed
-            if (threadIdx.x == 0) {
-                uint32_t expect = 0u;
-                __hip_atomic_compare_exchange_strong(gstat, &expect, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-            }
-            return;
+        if (quit && lane == 0) {
+            // the group ends: the status word records it (at once, so that
+            // the other parts stop polling) unless the group already completed
+            *abort_flag = 1u;
+            uint32_t expect = 0u;
+            __hip_atomic_compare_exchange_strong(gstat, &expect, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
         }
+        // the state complete (and Fm clear) before the next C reads it
+        __syncthreads();
+        if (*abort_flag) return;
         if (s >= it.nburn && ++since == it.thin) {
             since = 0;
             pending = true;
         }
-        __syncthreads();
     }
     if (pending && recorder) {
         record();
@@ -898,7 +904,7 @@ size_t bs_lds_bytes(uint32_t n, uint32_t msel_total, uint32_t G)
 size_t split_lds_bytes(uint32_t n, uint32_t n_own, uint32_t m_own, uint32_t G)
 {
     return (size_t)8 * ((size_t)n + 2 * (size_t)n_own + m_own + 2 * G) + (size_t)4 * 3 * kQCap * G +
-           (size_t)4 * 64 * kMaxProps + 8 + 8 * kSplitMaxParts + ((n + 15) / 16 + 15) / 16 * 16;
+           (size_t)4 * 64 * kMaxProps + 8 + 8 * kSplitMaxParts * G + ((n + 15) / 16 + 15) / 16 * 16;
 }
 
 int launch_step_split(const StepItem *d_items, uint32_t nitems, uint32_t G, size_t lds, void *stream,
