@@ -354,8 +354,9 @@ int pbn_sim_set_split(pbn_sim *sim, int parts);
  * (bit-sliced kernel when every predictor has at most 6 parents and the
  * bit-sliced state fits in LDS, else lane-per-chain), 1 = lane-per-chain only,
  * 2 = bit-sliced where possible; waves = waves sharing one 64-chain block in
- * the bit-sliced kernel (0 = chosen from n, else 1, 2, 4, 8 or 16).  Results do not
- * depend on the choice. */
+ * the bit-sliced kernel (0 = chosen from n and from whether the launch has the
+ * CUs to itself, else 1..16; multiples of 4 keep a CU's four SIMDs even).
+ * Results do not depend on the choice.  Returns PBN_EINVAL for waves > 16. */
 int pbn_set_kernel(int mode, uint32_t waves);
 /* Node-split form of the bit-sliced trajectory step (a latency-bound 64-chain
  * group spread over several CUs: each block owns a contiguous range of nodes,

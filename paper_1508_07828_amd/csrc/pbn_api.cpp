@@ -188,7 +188,8 @@ int run_chains(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin)
     if (!fits(sim->t_done, burn_in, 1, kMaxTransition) || !fits(sim->t_done + burn_in, steps, thin, kMaxTransition))
         return fail(PBN_ELIMIT, "transition index limit (2^32)");
     std::vector<pbn::StepItem> items;
-    pbn::sim_extend_items(sim, burn_in, steps, thin, items, pbn::latency_waves(sim) <= pbn::kLatencyWaves);
+    pbn::sim_extend_items(sim, burn_in, steps, thin, items,
+                          pbn::latency_waves(sim) <= pbn::kLatencyWaves ? pbn::kShapeLatency : pbn::kShapeAlone);
     std::string err;
     int rc = pbn::launch_items(items, sim->ws, sim->stream, err, true, true);
     if (!rc && sim->ws.split_used) {
@@ -332,8 +333,11 @@ int pbn_batch_run(pbn_sim *const *sims, uint32_t count, const uint64_t *steps, v
     for (uint32_t i = 0; i < count; ++i)
         if (steps[i]) waves += pbn::latency_waves(sims[i]);
     const bool latency = waves <= pbn::kLatencyWaves;
+    uint32_t extended = 0;
+    for (uint32_t i = 0; i < count; ++i) extended += steps[i] != 0;
+    const int shape = latency ? pbn::kShapeLatency : extended > 1 ? pbn::kShapeShared : pbn::kShapeAlone;
     for (uint32_t i = 0; i < count; ++i)
-        if (steps[i]) pbn::sim_extend_items(sims[i], 0, steps[i], 1, items, latency);
+        if (steps[i]) pbn::sim_extend_items(sims[i], 0, steps[i], 1, items, shape);
     static thread_local pbn::Workspace ws;
     std::string err;
     int rc = pbn::launch_items(items, ws, (hipStream_t)hip_stream, err, true, true);
@@ -851,7 +855,7 @@ int pbn_server_step(pbn_server *srv, uint32_t *active, uint32_t *waiting, uint32
             // server's stream (the moved requests' earlier rounds)
             std::vector<pbn::SimRun *> lr;
             for (ServeReq *rq : srv->long_active) lr.push_back(&rq->run);
-            const pbn::LaunchCfg lcfg{false, true, srv->long_cus, nullptr};
+            const pbn::LaunchCfg lcfg{false, true, false, srv->long_cus, nullptr};
             int rc = PBN_OK;
             if (hipEventRecord(srv->admit_ev, srv->stream) != hipSuccess ||
                 hipStreamWaitEvent(srv->long_stream, srv->admit_ev, 0) != hipSuccess) {
@@ -916,8 +920,8 @@ int pbn_server_poll(pbn_server *srv, uint64_t id, int *ready, pbn_result *out)
 
 int pbn_set_kernel(int mode, uint32_t waves)
 {
-    if (mode < 0 || mode > 2 || (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 16))
-        return fail(PBN_EINVAL, "mode must be 0..2 and waves 0, 1, 2, 4, 8 or 16");
+    if (mode < 0 || mode > 2 || waves > 16)
+        return fail(PBN_EINVAL, "mode must be 0..2 and waves 0..16");
     pbn::set_kernel_mode(mode, waves);
     return PBN_OK;
 }
@@ -931,8 +935,8 @@ int pbn_set_split(uint32_t parts)
 int pbn_sim_set_kernel(pbn_sim *sim, int mode, uint32_t waves)
 {
     if (!sim || mode < -1 || mode > 2 ||
-        (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 16))
-        return fail(PBN_EINVAL, "mode must be -1..2 and waves 0, 1, 2, 4, 8 or 16");
+        waves > 16)
+        return fail(PBN_EINVAL, "mode must be -1..2 and waves 0..16");
     sim->kmode = mode;
     sim->kwaves = mode < 0 ? 0 : waves;
     return PBN_OK;

@@ -750,7 +750,7 @@ int sims_reset_batch(pbn_sim *const *sims, uint32_t count, const pbn_pattern *pr
 
 
 void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin,
-                      std::vector<StepItem> &items, bool latency)
+                      std::vector<StepItem> &items, int shape)
 {
     for (uint32_t c0 = 0; c0 < sim->omega; c0 += 64) {
         StepItem it{};
@@ -766,7 +766,7 @@ void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t t
         it.ops_per_step = (float)sim->net.ops_per_step;
         it.philox_per_step = (float)sim->net.philox_per_step;
         it.owner = sim;
-        choose_kernel(sim, it, latency);
+        choose_kernel(sim, it, shape);
         items.push_back(it);
     }
     sim->t_done += burn_in + steps * thin;
@@ -775,11 +775,23 @@ void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t t
 
 // Kernel choice per item: the bit-sliced kernel when every predictor has
 // k <= 6 and its LDS fits, else the lane-per-chain kernel.  The waves per
-// 64-chain block follow measured per-transition cost on the device: for
-// throughput (many blocks per CU) 2 waves below 40 nodes, 4 up to 600, 8
-// beyond; for latency (the chip holds every block of the work at once) 2, 8
-// or 16 waves, which shortens each transition's critical path.  kernel_mode
-// forces one kernel or wave count (testing and tuning).
+// 64-chain block follow measured kernel times on the device (65536 chains, one
+// network alone, and the batched solve):
+//   latency (the chip holds every block of the work at once): 2 waves below 40
+//     nodes, 8 below 150, else 16, which shortens each transition's critical
+//     path;
+//   alone (throughput, one network's launch with the CUs to itself): 2 below
+//     40 nodes, 4 below 400, 8 below 1000, else 12.  Waves are spread over a
+//     CU's four SIMDs in turn, so multiples of four keep the SIMDs even; more
+//     waves per block give a CU more waves in all within its LDS (8 waves at
+//     n = 803: 32 waves per CU against 16, 13% faster; 12 at n = 1500-2000:
+//     24 against 16, 12-17%);
+//   shared (throughput, many networks of mixed sizes: the batched lanes and
+//     server rounds): 2 below 40 nodes, 4 below 900, else 8.  There the alone
+//     shapes are slower (61 -> 64-74 ms per 512-network solve): more block
+//     shapes mean more launches per round, and wider blocks leave less room
+//     for the others'.
+// kernel_mode forces one kernel or wave count (testing and tuning).
 // Process-wide settings, read by launches on any thread.
 namespace {
 std::atomic<int> g_kernel_mode{0};     // 0 auto, 1 lane-per-chain, 2 bit-sliced
@@ -803,15 +815,16 @@ void set_split_spins(uint32_t polls) { g_split_spins = polls ? polls : kSplitSpi
 uint64_t latency_waves(const pbn_sim *sim)
 {
     StepItem probe{};
-    choose_kernel(sim, probe, true);
+    choose_kernel(sim, probe, kShapeLatency);
     return (uint64_t)((sim->omega + 63) / 64) * (probe.kernel ? probe.kernel : 1);
 }
 
-uint32_t waves_for(uint32_t n, bool latency)
+uint32_t waves_for(uint32_t n, int shape)
 {
     uint32_t G = 0;
-    if (tuned_waves(n, latency, &G)) return G;
-    if (latency) return n < 40 ? 2 : n < 150 ? 8 : 16;
+    if (tuned_waves(n, shape == kShapeLatency, &G)) return G;
+    if (shape == kShapeLatency) return n < 40 ? 2 : n < 150 ? 8 : 16;
+    if (shape == kShapeAlone) return n < 40 ? 2 : n < 400 ? 4 : n < 1000 ? 8 : 12;
     return n < 40 ? 2 : n < 900 ? 4 : 8;
 }
 
@@ -819,7 +832,7 @@ int kernel_mode_of(const pbn_sim *sim) { return sim && sim->kmode >= 0 ? sim->km
 uint32_t waves_override_of(const pbn_sim *sim) { return sim && sim->kmode >= 0 ? sim->kwaves : g_waves_override.load(); }
 uint32_t split_mode_of(const pbn_sim *sim) { return sim && sim->split >= 0 ? (uint32_t)sim->split : g_split_mode.load(); }
 
-void choose_kernel(const pbn_sim *sim, StepItem &it, bool latency)
+void choose_kernel(const pbn_sim *sim, StepItem &it, int shape)
 {
     const Net &net = sim->net;
     it.kernel = 0;
@@ -827,11 +840,11 @@ void choose_kernel(const pbn_sim *sim, StepItem &it, bool latency)
     it.small = 0;
     if (kernel_mode_of(sim) == 1 || !net.bitsliced) return;
     const uint32_t forced = waves_override_of(sim);
-    uint32_t G = forced ? forced : waves_for(net.n, latency);
+    uint32_t G = forced ? forced : waves_for(net.n, shape);
     size_t lds = bs_lds_bytes(net.n, net.msel_total, G);
-    // a shape whose LDS does not fit falls back to fewer waves
+    // a shape whose LDS does not fit falls back to fewer waves (12 to 8, then halves)
     while (lds > 160 * 1024 && G > 1 && !forced) {
-        G /= 2;
+        G = G > 8 ? 8 : G / 2;
         lds = bs_lds_bytes(net.n, net.msel_total, G);
     }
     if (lds > 160 * 1024) return;
@@ -1358,10 +1371,10 @@ MachineParams make_params(const pbn_sim *sim, const pbn_opts *opts, double r, do
 // single-block timings: about 2.5 us plus 0.17 us per node and wave (0.25 us
 // with 16 waves, whose barriers cost more); about 1 us per node for the
 // lane-per-chain kernel.
-double step_latency_us(const pbn_sim *sim, bool latency)
+double step_latency_us(const pbn_sim *sim, int shape)
 {
     StepItem probe{};
-    choose_kernel(sim, probe, latency);
+    choose_kernel(sim, probe, shape);
     const double n = sim->net.n;
     const double per = probe.kernel == 16 ? 0.25 : 0.17;
     return probe.kernel ? 2.5 + per * n / probe.kernel : 1.0 + 1.0 * n;
@@ -1402,7 +1415,7 @@ static void plan_parts(const std::vector<std::pair<pbn_sim *, uint64_t>> &ext, s
 
 double extension_us(const pbn_sim *sim, uint64_t positions, uint32_t parts)
 {
-    double us = step_latency_us(sim, true);
+    double us = step_latency_us(sim, kShapeLatency);
     if (parts >= 2 && sim->net.bitsliced && split_mode_of(sim) != 1) us = std::min(us, 6.0 + us / parts);
     return us * (double)sim->thin * (double)positions;
 }
@@ -1410,9 +1423,10 @@ double extension_us(const pbn_sim *sim, uint64_t positions, uint32_t parts)
 // parts: the network's 64-chain groups are spread over that many CUs in the
 // node-split form (forced part counts included); a transition then costs
 // about 6 us of exchange plus the one-block time over the parts.
-uint64_t slice_len(const pbn_sim *sim, double tick_us, bool latency, uint32_t parts)
+uint64_t slice_len(const pbn_sim *sim, double tick_us, int shape, uint32_t parts)
 {
-    double us = step_latency_us(sim, latency);
+    const bool latency = shape == kShapeLatency;
+    double us = step_latency_us(sim, shape);
     const uint32_t mode = split_mode_of(sim);
     if (mode >= 2) parts = std::min(std::min(mode, kSplitMaxParts), sim->net.nblk);
     if (latency && parts >= 2 && mode != 1 && sim->net.bitsliced) us = std::min(us, 6.0 + us / parts);
@@ -1459,12 +1473,14 @@ int round_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, 
     // decided before slicing so that each slice is about tick_us long
     std::vector<uint32_t> parts(ext.size(), 1);
     if (tick_us > 0.0 && cfg.split && latency) plan_parts(ext, parts, cfg.cus);
+    // one network alone on the device takes its own best shape; several share
+    const int shape = latency ? kShapeLatency : cfg.shared || ext.size() > 1 ? kShapeShared : kShapeAlone;
     for (size_t k = 0; k < ext.size(); ++k) {
         pbn_sim *sim = ext[k].first;
         uint64_t e = ext[k].second;
-        if (tick_us > 0.0) e = std::min(e, slice_len(sim, tick_us, latency != 0, cfg.split ? parts[k] : 1));
+        if (tick_us > 0.0) e = std::min(e, slice_len(sim, tick_us, shape, cfg.split ? parts[k] : 1));
         const size_t first = items.size();
-        sim_extend_items(sim, 0, e, sim->thin, items, latency != 0);
+        sim_extend_items(sim, 0, e, sim->thin, items, shape);
         for (size_t i = first; i < items.size(); ++i) items[i].parts_hint = parts[k];
     }
     int rc = launch_items(items, ws, stream, err, cfg.fork, cfg.split, cfg.cus, cfg.pool);
@@ -1555,9 +1571,9 @@ int ahead_begin(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, 
     std::vector<StepItem> items;
     for (size_t k = 0; k < ext.size(); ++k) {
         pbn_sim *sim = ext[k].first;
-        const uint64_t e = std::min(ext[k].second, slice_len(sim, tick_us, true, cfg.split ? parts[k] : 1));
+        const uint64_t e = std::min(ext[k].second, slice_len(sim, tick_us, kShapeLatency, cfg.split ? parts[k] : 1));
         const size_t first = items.size();
-        sim_extend_items(sim, 0, e, sim->thin, items, true);
+        sim_extend_items(sim, 0, e, sim->thin, items, kShapeLatency);
         for (size_t i = first; i < items.size(); ++i) items[i].parts_hint = parts[k];
     }
     const int rc = launch_items(items, ws, stream, err, cfg.fork, cfg.split, cfg.cus, cfg.pool);
@@ -1686,7 +1702,7 @@ int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
         }
         for (SimRun *r : order) {
             const uint64_t first = r->machines.empty() ? 0 : r->machines[0].request().need_len;
-            const double serial = (double)first * step_latency_us(r->sim, false);
+            const double serial = (double)first * step_latency_us(r->sim, kShapeShared);
             if (serial > 0.25 * bulk_us) crit.push_back({serial, r});
         }
         std::stable_sort(crit.begin(), crit.end(),
@@ -1705,8 +1721,8 @@ int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
     }
     for (SimRun *r : order) {
         StepItem probe{};
-        choose_kernel(r->sim, probe, false);
-        const int k = probe.kernel == 8 ? 0 : probe.kernel == 4 ? 1 : 2;
+        choose_kernel(r->sim, probe, kShapeShared);
+        const int k = probe.kernel >= 8 ? 0 : probe.kernel >= 4 ? 1 : 2;
         P.lane[k]->runs.push_back(r);
     }
     auto work = [](const Lane &L) {
@@ -1749,7 +1765,7 @@ int run_lanes(std::vector<SimRun *> &runs, Workspace &ws, hipStream_t stream, st
             all_done = false;
             // the express lane takes whole extensions
             const double tick = k < nl ? kTickUs : 0.0;
-            const LaunchCfg lane_cfg{false, false, 256, nullptr};
+            const LaunchCfg lane_cfg{false, false, true, 256, nullptr};
             if ((rc = round_begin(L.runs, L.ws, L.stream, L.ctx, err, lane_cfg, tick, k < nl ? latency : xlatency)))
                 break;
             if (L.ctx.pending) any_pending = true;

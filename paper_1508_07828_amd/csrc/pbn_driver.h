@@ -165,11 +165,20 @@ int sim_reset(pbn_sim *sim, const pbn_pattern *props, uint32_t nprops, hipStream
 // Reset many simulations with one descriptor upload and one setup launch on stream.
 int sims_reset_batch(pbn_sim *const *sims, uint32_t count, const pbn_pattern *props, const uint32_t *nprops,
                      const uint32_t *prop_off, Workspace &ws, hipStream_t stream, std::string &err);
-// Append the step items that extend sim by `steps` recorded positions.
-// latency: pick the kernel shape for the shortest transition (the chip is not
-// full) rather than for throughput.
+// Kernel shape (waves per 64-chain block) of a launch:
+//   kShapeShared  throughput for launches of many networks of mixed sizes, or
+//                 that share the CUs with other concurrent launches (batched
+//                 class lanes, server rounds): few block shapes, each leaving
+//                 room for the others;
+//   kShapeLatency the shortest transition (the chip holds every block at once);
+//   kShapeAlone   throughput for one network's launch with the CUs to itself
+//                 (plain runs): more waves per block for larger networks.
+// A bool converts to the first two (false: shared, true: latency).
+enum Shape : int { kShapeShared = 0, kShapeLatency = 1, kShapeAlone = 2 };
+// Append the step items that extend sim by `steps` recorded positions, in
+// the given kernel shape.
 void sim_extend_items(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint32_t thin,
-                      std::vector<StepItem> &items, bool latency);
+                      std::vector<StepItem> &items, int shape);
 // Latency shapes are picked while every 64-chain block of the unfinished work,
 // in its latency shape, fits on the chip at once (waves of 256 CUs at six
 // waves per SIMD).
@@ -223,6 +232,9 @@ struct StreamPool {
 // on them).
 struct LaunchCfg {
     bool fork = true, split = true;
+    // the launch shares the CUs with other lanes' launches: throughput
+    // shapes are kShapeShared even for one network
+    bool shared = false;
     uint32_t cus = 256;
     StreamPool *pool = nullptr;
 };
@@ -275,12 +287,12 @@ void profile_clear();
 
 // Kernel selection for a step item of sim (see pbn_driver.cpp): the
 // simulation's own setting, else the process-wide one.
-void choose_kernel(const pbn_sim *sim, StepItem &it, bool latency);
+void choose_kernel(const pbn_sim *sim, StepItem &it, int shape);
 // Autotuner (pbn_tune.cpp): measured shapes per size bucket, if measured.
 bool tuned_waves(uint32_t n, bool latency, uint32_t *G);
 int autotune(hipStream_t stream, pbn_tune_row *rows, uint32_t cap, uint32_t *count, std::string &err);
 void autotune_reset();
-uint32_t waves_for(uint32_t n, bool latency);
+uint32_t waves_for(uint32_t n, int shape);
 void set_kernel_mode(int mode, uint32_t waves);
 // Node-split form: 0 = automatic, 1 = never, P >= 2 = P parts wherever the
 // network has P node blocks (launches that allow it).

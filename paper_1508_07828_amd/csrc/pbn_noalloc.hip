@@ -97,7 +97,7 @@ int run_chains_noalloc_impl(pbn_sim *sim, uint64_t burn_in, uint64_t steps, uint
     proto.nodes = sim->net.n;
     proto.ops_per_step = (float)sim->net.ops_per_step;
     proto.philox_per_step = (float)sim->net.philox_per_step;
-    choose_kernel(sim, proto, latency_waves(sim) <= kLatencyWaves);
+    choose_kernel(sim, proto, latency_waves(sim) <= kLatencyWaves ? kShapeLatency : kShapeAlone);
     if (proto.kernel == 0 && step_rows_words(groups, sim->net.W) > 0) {
         err = "state rows beyond LDS need device scratch: not available without allocation";
         return PBN_ELIMIT;

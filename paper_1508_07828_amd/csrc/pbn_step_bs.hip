@@ -911,8 +911,8 @@ int launch_step_split(const StepItem *d_items, uint32_t nitems, uint32_t G, size
                       std::string &err)
 {
     if (nitems == 0) return PBN_OK;
-    if (G != 1 && G != 2 && G != 4 && G != 8 && G != 16) {
-        err = "node-split kernel: waves per block must be 1, 2, 4, 8 or 16";
+    if (G < 1 || G > 16) {
+        err = "node-split kernel: waves per block must be 1..16";
         return PBN_EINVAL;
     }
     if (lds > 160 * 1024) {
@@ -932,8 +932,8 @@ int launch_step_bs(const StepItem *d_items, uint32_t nitems, uint32_t G, bool sm
                    std::string &err)
 {
     if (nitems == 0) return PBN_OK;
-    if (G != 1 && G != 2 && G != 4 && G != 8 && G != 16) {
-        err = "bit-sliced kernel: waves per block must be 1, 2, 4, 8 or 16";
+    if (G < 1 || G > 16) {
+        err = "bit-sliced kernel: waves per block must be 1..16";
         return PBN_EINVAL;
     }
     if (lds > 160 * 1024) {

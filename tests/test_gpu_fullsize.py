@@ -113,6 +113,32 @@ def test_large_long_trajectories(large_oracle, shape):
         assert prof["split_launches"] == 0, prof
 
 
+@pytest.mark.parametrize("target_n,chains", [(803, 65536), (2000, 32768)])
+def test_owned_throughput_shapes(target_n, chains):
+    """A plain run with more chains than the chip holds in latency shapes
+    takes the throughput shapes of a launch that owns the CUs (8 waves per
+    block at n = 803, 12 at n = 2000): states and indicators of three sampled
+    64-chain groups equal the oracle's after 200 transitions."""
+    jobs = ps.batched(512)
+    job = min(jobs, key=lambda j: abs(j.net.n - target_n)) if target_n != 2000 else ps.large()
+    text = ps.to_text(job.net)
+    pats = job.patterns[:1]
+    steps = 200
+    say("owned throughput shape: n={} chains={} x {} transitions".format(job.net.n, chains, steps))
+    sim = pkg.Simulation(pkg.Network(text), chains, job.seed, max_props=1, max_len=steps + 64)
+    sim.reset(pats)
+    sim.run(steps // 2)
+    sim.run(steps - steps // 2)
+    st = sim.read_state()
+    bits = sim.read_bits(0, 0, steps)
+    onet = oracle.Net(text)
+    for c0 in (0, chains // 2 + 64, chains - 64):
+        ch = oracle.Chains(onet, 64, job.seed, pats, chain0=c0)
+        ch.extend(steps)
+        assert np.array_equal(st[c0:c0 + 64], ch.states), c0
+        assert np.array_equal(bits[c0:c0 + 64], ch.bits[0]), c0
+
+
 def test_large_config_end_to_end():
     """The large configuration as the benchmark solves it (automatic shapes,
     node-split parts), against the oracle's Alg. 3 then Alg. 5 for each state

@@ -69,11 +69,11 @@ CASES = {
 }
 
 # (mode, waves): the lane-per-chain kernel and the bit-sliced kernel with 1 to 16 waves per block
-KERNELS = [("lane", 0), ("bitsliced", 1), ("bitsliced", 2), ("bitsliced", 4), ("bitsliced", 8),
-           ("bitsliced", 16)]
+KERNELS = [("lane", 0), ("bitsliced", 1), ("bitsliced", 2), ("bitsliced", 4), ("bitsliced", 5), ("bitsliced", 8),
+           ("bitsliced", 12), ("bitsliced", 16)]
 
 
-@pytest.fixture(params=KERNELS, ids=["lane", "bs1", "bs2", "bs4", "bs8", "bs16"])
+@pytest.fixture(params=KERNELS, ids=["lane", "bs1", "bs2", "bs4", "bs5", "bs8", "bs12", "bs16"])
 def kernel(request):
     pkg.set_kernel(*request.param)
     yield request.param
@@ -743,7 +743,7 @@ def test_kernel_choice_per_simulation():
     a.set_kernel("global")
     b.set_split(-1)
     with pytest.raises(pkg.PbnError):
-        a.set_kernel("bitsliced", 3)
+        a.set_kernel("bitsliced", 17)
 
 
 def test_split_workspace_grows():
