@@ -601,12 +601,16 @@ def main() -> int:
 
 def kernel_sha() -> str:
     """Hash of the sources the step kernel is compiled from (kernel file and the
-    headers it includes), so recorded counter traffic is used only while it
-    still describes the same kernel."""
+    headers it includes), comments and whitespace left out, so recorded counter
+    traffic is used only while it still describes the same kernel."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("pbn_step_bs.hip", "pbn_device.h", "pbn_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_1508_07828_amd", "csrc", f), "rb").read())
+        text = open(os.path.join(ROOT, "paper_1508_07828_amd", "csrc", f)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)     # block comments
+        text = re.sub(r"//[^\n]*", " ", text)                   # line comments
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -543,18 +543,21 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
 // slot groups [tab[P + 1 + r], tab[P + 2 + r]) of those nodes.  Each keeps the
 // whole state S in LDS (every slot may read any parent) but only its own
 // nodes' next-state words, function values and selection masks.  Per
-// transition:
-//   A  own blocks, as in the one-block form: flips into Gm, masks into M
-//   -- barrier
+// transition s (A of the first transition runs before the loop):
 //   C  own slots: the K-input multiplexers, restricted to the chains that
 //      selected the predictor, OR-ed into Fm[node] (the function values)
 //   -- barrier
-//   X  with Pr the chains this block perturbed, publish for every own node
+//   X1 with Pr the chains this block perturbed, publish for every own node
 //      h_i = Pr & (S_i ^ flips_i) | ~Pr & f_i and the word Pr to the group's
 //      exchange area, each 64-bit word a 32-bit half tagged with the
-//      transition, then read every other part's words, polling each until it
-//      carries this transition's tag: node i of part q becomes h_i, except in
-//      the chains perturbed by another part only, which keep S_i.
+//      transition (h_i kept in Fm, the flips cleared)
+//   -- barrier
+//   A  transition s + 1's draws on the own blocks, as in the one-block form:
+//      flips into Gm, masks into M (they read no state)
+//   X2 read every other part's words, polling each until it carries this
+//      transition's tag: node i of part q becomes h_i, except in the chains
+//      perturbed by another part only, which keep S_i
+//   -- barrier
 // The wait is bounded: a block that polls about a second gives up.  The
 // group's status word then decides, once, between the two ends of the
 // launch: a block that gives up moves it from 0 to 1 (aborted), block 0 moves
