@@ -72,12 +72,14 @@ def run_serving(pkg, torch, seconds, rate, arena_bytes, serial_budget_s=20.0, sc
     pkg.profile_enable(True)
     pkg.profile_reset()
     rounds = 0
+    pending = set()                   # submitted, not yet answered
     while len(finish) < len(jobs):
         now = time.perf_counter() - t0
         while nxt < len(jobs) and jobs[nxt].arrival <= now:
             j = jobs[nxt]
             ids[nxt] = srv.submit(nets[nxt], j.chains, j.seed, j.patterns, j.r, j.confidence,
                                   max_len=MAX_LEN, psrf_max=1.1)
+            pending.add(nxt)
             nxt += 1
         active, waiting, done = srv.step()
         rounds += 1
@@ -86,11 +88,9 @@ def run_serving(pkg, torch, seconds, rate, arena_bytes, serial_budget_s=20.0, sc
                 rounds, time.perf_counter() - t0, nxt, active, waiting, done))
         if done > len(finish):
             t_now = time.perf_counter() - t0
-            for i in list(ids):
-                if i in finish:
-                    continue
-                if srv.poll(ids[i]) is not None:
-                    finish[i] = t_now
+            for i in [i for i in pending if srv.poll(ids[i]) is not None]:
+                finish[i] = t_now
+                pending.discard(i)
         if active == 0 and waiting == 0 and nxt < len(jobs):
             time.sleep(max(0.0, jobs[nxt].arrival - (time.perf_counter() - t0)))
     wall = time.perf_counter() - t0
