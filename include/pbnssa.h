@@ -399,12 +399,14 @@ typedef struct {
     double transition_us;        /* at waves_latency, 64 chains               */
 } pbn_tune_row;
 
-/* Measures the bit-sliced kernel's shapes (1, 2, 4, 8, 16 waves per block) on
- * synthetic networks of 24..3072 nodes drawn like the paper's random networks
- * (Sec. 5.1: 1-3 predictors per node, 1-5 parents, p = 1e-3), with short
- * event-timed launches on hip_stream (under a second of GPU time), and uses
- * the result for every later launch in this process instead of the built-in
- * rule.  Results of the method do not depend on the shapes.  Fills
+/* Measures the bit-sliced kernel's shapes (1, 2, 4, 5, 8, 12, 16 waves per
+ * block) on synthetic networks of 24..3072 nodes drawn like the paper's random
+ * networks (Sec. 5.1: 1-3 predictors per node, 1-5 parents, p = 1e-3), with
+ * short event-timed launches on hip_stream (about a second of GPU time), one
+ * network alone on the chip, and uses the result for every later latency and
+ * one-network launch in this process instead of the built-in rule (the batched
+ * lanes, whose launches share the CUs, keep their built-in shapes).  Results
+ * of the method do not depend on the shapes.  Fills
  * rows[0 .. min(cap, *count)) and sets *count to the number of rows (8).
  * The library allocates and frees its own device memory for the runs.
  * Errors: PBN_ENOMEM, PBN_EDEVICE (message in pbn_last_error). */

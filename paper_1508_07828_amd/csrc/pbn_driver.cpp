@@ -822,7 +822,7 @@ uint64_t latency_waves(const pbn_sim *sim)
 uint32_t waves_for(uint32_t n, int shape)
 {
     uint32_t G = 0;
-    if (tuned_waves(n, shape == kShapeLatency, &G)) return G;
+    if (tuned_waves(n, shape, &G)) return G;
     if (shape == kShapeLatency) return n < 40 ? 2 : n < 150 ? 8 : 16;
     if (shape == kShapeAlone) return n < 40 ? 2 : n < 400 ? 4 : n < 1000 ? 8 : 12;
     return n < 40 ? 2 : n < 900 ? 4 : 8;

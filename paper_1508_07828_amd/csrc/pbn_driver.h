@@ -289,7 +289,7 @@ void profile_clear();
 // simulation's own setting, else the process-wide one.
 void choose_kernel(const pbn_sim *sim, StepItem &it, int shape);
 // Autotuner (pbn_tune.cpp): measured shapes per size bucket, if measured.
-bool tuned_waves(uint32_t n, bool latency, uint32_t *G);
+bool tuned_waves(uint32_t n, int shape, uint32_t *G);
 int autotune(hipStream_t stream, pbn_tune_row *rows, uint32_t cap, uint32_t *count, std::string &err);
 void autotune_reset();
 uint32_t waves_for(uint32_t n, int shape);

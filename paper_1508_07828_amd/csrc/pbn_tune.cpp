@@ -1,9 +1,10 @@
 // Autotuner of the bit-sliced kernel's shape: waves per 64-chain block, per
-// network-size bucket, for throughput (the chip full of blocks) and for
-// latency (one block alone), from short event-timed launches on synthetic
+// network-size bucket, for throughput (one network's blocks filling the chip)
+// and for latency (one block alone), from short event-timed launches on synthetic
 // networks drawn like the workloads' (1-3 predictors per node, 1-5 parents,
 // random truth tables, p = 1e-3; the paper's random-network recipe of Sec. 5.1).
-// The measured table replaces the built-in rule for the rest of the process.
+// The measured table replaces the built-in latency and one-network rules for
+// the rest of the process; the batched lanes keep their built-in shapes.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -118,7 +119,7 @@ int measure(uint32_t n, hipStream_t stream, TuneRow &row, std::string &err)
         rc = sim_setup(&sim, net, omega, 7828, 1, max_len, buf, bytes, stream, err);
         if (rc) break;
         const uint64_t steps = omega == big ? thr_steps : lat_steps;
-        for (uint32_t G : {1u, 2u, 4u, 8u, 16u}) {
+        for (uint32_t G : {1u, 2u, 4u, 5u, 8u, 12u, 16u}) {
             if (bs_lds_bytes(net.n, net.msel_total, G) > 160 * 1024) continue;
             double ms = 0.0, warm = 0.0;
             if ((rc = sim_reset(&sim, &pat, 1, stream, err))) break;
@@ -145,8 +146,11 @@ int measure(uint32_t n, hipStream_t stream, TuneRow &row, std::string &err)
 
 }  // namespace
 
-bool tuned_waves(uint32_t n, bool latency, uint32_t *G)
+bool tuned_waves(uint32_t n, int shape, uint32_t *G)
 {
+    // the table times one network alone on the chip: it stands for the latency
+    // and one-network shapes, not for the batched lanes' shared one
+    if (shape == kShapeShared) return false;
     std::lock_guard<std::mutex> lock(g_tune_mu);
     if (g_tune.empty()) return false;
     const TuneRow *best = &g_tune[0];
@@ -155,7 +159,7 @@ bool tuned_waves(uint32_t n, bool latency, uint32_t *G)
         const double d = std::fabs(std::log2((double)n) - std::log2((double)r.n));
         if (d < dbest) dbest = d, best = &r;
     }
-    *G = latency ? best->g_lat : best->g_thr;
+    *G = shape == kShapeLatency ? best->g_lat : best->g_thr;
     return true;
 }
 

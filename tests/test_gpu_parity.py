@@ -599,7 +599,7 @@ def test_autotune_keeps_results():
     try:
         assert len(rows) == 8
         for r in rows:
-            assert r["waves_throughput"] in (1, 2, 4, 8, 16) and r["waves_latency"] in (1, 2, 4, 8, 16)
+            assert r["waves_throughput"] in (1, 2, 4, 5, 8, 12, 16) and r["waves_latency"] in (1, 2, 4, 5, 8, 12, 16)
             assert r["node_updates_per_s"] > 0 and r["transition_us"] > 0
         after = solve()
     finally:
