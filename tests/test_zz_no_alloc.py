@@ -83,6 +83,24 @@ def test_noalloc_equals_run_chains(case):
     _same(a, b, len(pats))
 
 
+@pytest.mark.parametrize("target_n", [803, 1100])
+def test_noalloc_one_network_shapes(target_n):
+    """More chains than the chip holds in latency shapes: both calls take the
+    throughput shapes of one network alone on the chip (8 waves per block at
+    n = 803, 12 beyond 1000 nodes) and leave identical chains, the second call
+    smaller than the first."""
+    jobs = ps.batched(512)
+    job = min(jobs, key=lambda j: abs(j.net.n - target_n))
+    text = ps.to_text(job.net)
+    pats = job.patterns[:1]
+    for omega, steps in ((32768, 24), (28672, 9)):
+        say("noalloc one-network shape: n={} chains={} steps={}".format(job.net.n, omega, steps))
+        a, b = _twins(text, omega, job.seed, pats, max_len=64)
+        a.run(steps)
+        b.run_noalloc(steps)
+        _same(a, b, 1)
+
+
 def test_noalloc_limits():
     net = pkg.Network(ps.to_text(ps.tiny().net))
     sim = pkg.Simulation(net, (1 << 18) + 1, 1, max_props=1, max_len=64)
