@@ -168,6 +168,14 @@ def _skart_cases():
     b[7, 2] = 4
     yield b, 7                                           # one batch off
     yield np.tile([0, 1], (3, 100)), 1                   # alternating 0-1 batches
+    # batch means a few observations apart at a huge batch size: Q2 is tiny
+    # beside S1^2, a cancellation that only exact sums survive
+    b = np.full((1280, 1), (1 << 28) + 3, dtype=np.int64)
+    b[::7] += 1
+    b[::11] -= 2
+    yield b, 1 << 29
+    # at the observation limit itself (batch size x batches = 2^40)
+    yield rng.integers((1 << 31) - 64, 1 << 31, size=(256, 2)), 1 << 31
     for _ in range(40):                                  # small random sets near the t interval's size
         omega = int(rng.integers(1, 50))
         m = int(rng.integers(1, 40))
