@@ -199,3 +199,39 @@ def test_skart_cap_while_batches_grow():
     want = drivers.solve(text, 64, 5, job.patterns, 0.0005, 0.95, 1.1, method="skart", cap=3000)
     assert want[0]["status"] == drivers.NOT_CONVERGED and want[0]["kappa"] > 0
     assert_same_result(got[0], want[0], "cap")
+
+
+BATCH_CAP = 1 << 17
+ORACLE_BUDGET = 3e9                   # node-updates the sampled oracle solves may take in all
+
+
+def test_batched_full_workload_sampled():
+    """The 512-network batched workload in one call, as the benchmark runs it;
+    eight networks' results equal the oracle's solo solves: the two smallest,
+    two near the median size and the four largest whose solves fit the
+    oracle's budget (the choice uses the GPU's chain lengths, the expected
+    values come from the oracle alone)."""
+    jobs = ps.batched(512)
+    say("batched full workload: 512 networks on the GPU")
+    nets = [pkg.Network(ps.to_text(j.net)) for j in jobs]
+    sims = [pkg.Simulation(nt, j.chains, j.seed, max_props=1, max_len=BATCH_CAP) for nt, j in zip(nets, jobs)]
+    got = pkg.batch_estimate(sims, [j.patterns for j in jobs], [j.r for j in jobs],
+                             [j.confidence for j in jobs], psrf_max=1.1)
+    assert all(g[0]["status"] == 0 for g in got)
+    cost = [j.net.n * j.chains * g[0]["chain_len"] for j, g in zip(jobs, got)]
+    by_n = sorted(range(len(jobs)), key=lambda b: jobs[b].net.n)
+    pick = by_n[:2] + by_n[len(by_n) // 2: len(by_n) // 2 + 2]
+    spent = sum(cost[b] for b in pick)
+    for b in reversed(by_n):
+        if len(pick) == 8:
+            break
+        if b not in pick and spent + cost[b] <= ORACLE_BUDGET:
+            pick.append(b)
+            spent += cost[b]
+    assert len(pick) == 8 and max(jobs[b].net.n for b in pick) > 1500
+    for b in pick:
+        j = jobs[b]
+        say("oracle: batched[{}] n={} chains={} chain_len={}".format(b, j.net.n, j.chains, got[b][0]["chain_len"]))
+        want = drivers.solve(ps.to_text(j.net), j.chains, j.seed, j.patterns, j.r, j.confidence, 1.1,
+                             cap=BATCH_CAP)
+        assert_same_result(got[b][0], want[0], j.name)
