@@ -61,8 +61,8 @@ def node_updates_of(sims, jobs):
     return float(sum(s.position()[1] * j.chains * j.net.n for s, j in zip(sims, jobs)))
 
 
-def run_serving(pkg, torch, seconds, rate, arena_bytes, serial_budget_s=20.0, sched=None):
-    jobs = ps.serving(duration_s=seconds, rate=rate, workers=cpu_threads())
+def run_serving(pkg, torch, seconds, rate, arena_bytes, serial_budget_s=20.0, sched=None, workers=None):
+    jobs = ps.serving(duration_s=seconds, rate=rate, workers=cpu_threads() if workers is None else workers)
     log("serving: {} requests over {:.1f} s".format(len(jobs), seconds))
     nets = [pkg.Network(j.text) for j in jobs]
     srv = pkg.Server(arena_bytes)
@@ -435,6 +435,8 @@ def main() -> int:
     ap.add_argument("--count", type=int, default=512)
     ap.add_argument("--plain-sample", type=int, default=0, help="networks of the plain leg (0 = all)")
     ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--serve-workers", type=int, default=-1,
+                    help="processes drawing the serving trace (-1: the host threads; 0: this process, as under a profiler)")
     ap.add_argument("--long-lane-us", type=float, default=0.0,
                     help="server long-request lane threshold in us of kernel time (0 = no long lane)")
     ap.add_argument("--ahead-us", type=float, default=0.0,
@@ -568,7 +570,8 @@ def main() -> int:
     if not args.no_serve:
         log("serving")
         sched = dict(ahead_us=args.ahead_us, long_lane_us=args.long_lane_us, long_quarters=args.long_lane_quarters)
-        serving = run_serving(pkg, torch, args.serve_seconds, 200.0, 16 << 30, args.serial_seconds, sched)
+        serving = run_serving(pkg, torch, args.serve_seconds, 200.0, 16 << 30, args.serial_seconds, sched,
+                              None if args.serve_workers < 0 else args.serve_workers)
         serving["schedule"] = sched
         log("serving: p50 {:.1f} ms p99 {:.1f} ms".format(serving["p50_ms"], serving["p99_ms"]))
         if args.saturate > 0:

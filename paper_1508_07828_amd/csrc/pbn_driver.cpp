@@ -855,10 +855,14 @@ void choose_kernel(const pbn_sim *sim, StepItem &it, int shape)
 
 namespace {
 
+// The process-wide pools live until the process ends and are never destroyed:
+// a static destructor would call the HIP runtime (stream and event
+// destruction) while the process shuts down, when the runtime or a tool
+// attached to it may already be gone; the driver reclaims them at exit.
 StreamPool &stream_pool()
 {
-    static StreamPool p;
-    return p;
+    static StreamPool *p = new StreamPool;
+    return *p;
 }
 }  // namespace
 
@@ -1671,8 +1675,8 @@ struct LanePool {
 };
 LanePool &lane_pool()
 {
-    static LanePool p;
-    return p;
+    static LanePool *p = new LanePool;    // never destroyed, as the stream pool
+    return *p;
 }
 }  // namespace
 
