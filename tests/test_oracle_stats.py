@@ -1,4 +1,4 @@
-"""Pins for the oracle's statistics (Alg. 1 line-8 formulas, Alg. 3, Skart-P pieces).
+"""Pins for the oracle's statistics (the sample-size and burn-in formulas of Sec. 3.1, Alg. 3, Skart-P pieces).
 
 * Gelman-Rubin: a worked-by-hand example (golden file) and the identical-chains
   case R = sqrt(1 - 1/psi) (B = 0).
